@@ -1,0 +1,222 @@
+"""Seeded synthetic inputs for selected-basis diagonalisation.
+
+This module only draws inputs: one- and two-electron integrals, a core energy
+and alpha/beta occupation bitstring sets.  It holds none of the method's
+arithmetic (no matrix elements, no excitation tables, no sigma) and is shared
+by the CPU oracle, the tests and the benchmark so both sides of every parity
+check read the very same arrays.
+
+Conventions
+-----------
+* Orbital p is bit p of a ``uint64`` half-bitstring (bit 0 = lowest orbital).
+* Integrals: ``h[p, q]`` symmetric; ``eri[p, q, r, s]`` is the chemists'
+  integral (pq|rs), built as sum_k L^k_pq L^k_rs with symmetric L^k, so it has
+  the full 8-fold permutational symmetry and is positive semidefinite as a
+  (pq),(rs) matrix.
+* The string sets stand in for the quantum-sampled configurations of the
+  paper's experiment (Sec. IV, Fe4S4 with 6,000 sampled 36-bit
+  configurations), which are not available: strings are drawn without
+  replacement with probability proportional to exp(-0.7 * excitation level
+  relative to the Aufbau string), the Aufbau string always included.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from itertools import combinations
+
+import numpy as np
+
+E_CORE_DEFAULT = 10.0
+LEVEL_DECAY = 0.7
+_ENUMERATE_LIMIT = 2_000_000
+
+
+def make_integrals(norb: int, seed: int):
+    """Return (h, eri, e_core) for ``norb`` spatial orbitals.
+
+    Draw order with ``numpy.random.default_rng(seed)``:
+    1. orbital energies uniform in [-20, 2], sorted ascending, on the diagonal
+       of h;
+    2. off-diagonal h_pq (p < q, row-major) ~ N(0, 0.1) * exp(-|p-q|/4);
+    3. for k = 0 .. 2*norb-1, the upper triangle (with diagonal, row-major) of
+       a symmetric L^k ~ N(0, 0.3/sqrt(k+1)).
+    """
+    if norb < 1:
+        raise ValueError("norb must be >= 1")
+    rng = np.random.default_rng(seed)
+    eps = np.sort(rng.uniform(-20.0, 2.0, norb))
+    h = np.diag(eps).astype(np.float64)
+    iu, ju = np.triu_indices(norb, 1)
+    off = rng.normal(0.0, 0.1, size=iu.size) * np.exp(-np.abs(iu - ju) / 4.0)
+    h[iu, ju] = off
+    h[ju, iu] = off
+    it, jt = np.triu_indices(norb, 0)
+    nl = 2 * norb
+    L = np.zeros((nl, norb, norb))
+    for k in range(nl):
+        v = rng.normal(0.0, 0.3 / math.sqrt(k + 1), size=it.size)
+        L[k, it, jt] = v
+        L[k, jt, it] = v
+    Lm = L.reshape(nl, norb * norb)
+    eri = (Lm.T @ Lm).reshape(norb, norb, norb, norb)
+    # exact symmetrisation guards against last-bit asymmetry of the product
+    eri = 0.5 * (eri + eri.transpose(2, 3, 0, 1))
+    return h, np.ascontiguousarray(eri), E_CORE_DEFAULT
+
+
+def all_strings(norb: int, n: int) -> np.ndarray:
+    """Every occupation string with ``n`` of ``norb`` bits set, ascending."""
+    out = np.fromiter((sum(1 << p for p in c) for c in combinations(range(norb), n)),
+                      dtype=np.uint64, count=math.comb(norb, n))
+    out.sort()
+    return out
+
+
+def _level(strings: np.ndarray, n: int) -> np.ndarray:
+    aufbau = np.uint64((1 << n) - 1)
+    x = strings & ~aufbau
+    # popcount of uint64 via byte table
+    b = x.view(np.uint8).reshape(-1, 8)
+    table = np.array([bin(i).count("1") for i in range(256)], dtype=np.int64)
+    return table[b].sum(axis=1)
+
+
+def sample_strings(norb: int, n: int, count: int, seed: int,
+                   decay: float = LEVEL_DECAY) -> np.ndarray:
+    """Sorted unique occupation strings drawn without replacement.
+
+    P(string) is proportional to exp(-decay * level), level = number of
+    electrons outside the Aufbau orbitals.  When all C(norb, n) strings can be
+    enumerated this uses weighted sampling keys u**(1/w) (Efraimidis and
+    Spirakis); otherwise a level is drawn with probability proportional to
+    C(n,k) C(norb-n,k) exp(-decay k), then k holes and k particles uniformly,
+    rejecting duplicates.  Both realise successive sampling proportional to
+    the weight.  The Aufbau string is always included.
+    """
+    if not (0 <= n <= norb <= 64):
+        raise ValueError("need 0 <= n <= norb <= 64")
+    total = math.comb(norb, n)
+    count = min(int(count), total)
+    if count <= 0:
+        return np.zeros(0, dtype=np.uint64)
+    rng = np.random.default_rng(seed)
+    aufbau = (1 << n) - 1
+    if count == total:
+        return all_strings(norb, n)
+    if total <= _ENUMERATE_LIMIT:
+        pool = all_strings(norb, n)
+        w = np.exp(-decay * _level(pool, n).astype(np.float64))
+        u = rng.uniform(size=pool.size)
+        key = np.log(u) / w          # log of u**(1/w); larger is better
+        key[pool == np.uint64(aufbau)] = np.inf
+        pick = np.argpartition(-key, count - 1)[:count]
+        out = np.sort(pool[pick])
+        return out
+    kmax = min(n, norb - n)
+    ks = np.arange(kmax + 1)
+    wk = np.array([math.comb(n, k) * math.comb(norb - n, k) * math.exp(-decay * k) for k in ks])
+    pk = wk / wk.sum()
+    chosen = {aufbau}
+    while len(chosen) < count:
+        k = int(rng.choice(kmax + 1, p=pk))
+        holes = rng.choice(n, k, replace=False)
+        parts = rng.choice(norb - n, k, replace=False) + n
+        s = aufbau
+        for q in holes:
+            s &= ~(1 << int(q))
+        for q in parts:
+            s |= 1 << int(q)
+        chosen.add(s)
+    return np.array(sorted(chosen), dtype=np.uint64)
+
+
+@dataclass
+class Workload:
+    name: str
+    norb: int
+    n_alpha: int
+    n_beta: int
+    alpha: np.ndarray
+    beta: np.ndarray
+    h: np.ndarray
+    eri: np.ndarray
+    e_core: float
+    nroots: int = 1
+    tol: float = 1e-6
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ndet(self) -> int:
+        return int(self.alpha.size) * int(self.beta.size)
+
+
+# The five synthetic configurations: (name, norb, n, strings per spin,
+# roots, seeds (integrals, alpha, beta), residual tolerance).
+CONFIGS = {
+    "fci8": dict(norb=8, n=4, nstr=None, nroots=1, seeds=(101, 0, 0), tol=1e-8),
+    "sel16": dict(norb=16, n=8, nstr=2000, nroots=1, seeds=(102, 2001, 2002), tol=1e-6),
+    "sel26": dict(norb=26, n=7, nstr=10000, nroots=1, seeds=(103, 3001, 3002), tol=1e-6),
+    "block20": dict(norb=20, n=8, nstr=5000, nroots=4, seeds=(104, 4001, 4002), tol=1e-6),
+}
+
+
+def make_config(name: str, nstr: int | None = None) -> Workload:
+    """Build one of the named synthetic workloads (optionally with fewer strings)."""
+    c = CONFIGS[name]
+    norb, n = c["norb"], c["n"]
+    si, sa, sb = c["seeds"]
+    h, eri, ecore = make_integrals(norb, si)
+    k = nstr if nstr is not None else c["nstr"]
+    if k is None:
+        a = all_strings(norb, n)
+        b = all_strings(norb, n)
+    else:
+        a = sample_strings(norb, n, k, sa)
+        b = sample_strings(norb, n, k, sb)
+    return Workload(name, norb, n, n, a, b, h, eri, ecore, c["nroots"], c["tol"],
+                    meta=dict(seeds=c["seeds"], nstr=k))
+
+
+def serving_stream(nreq: int = 256, seed: int = 5000, rate: float = 20.0,
+                   norb_range=(12, 32), ndet_range=(1e4, 2e7)):
+    """Request descriptors of the serving workload (no arrays, cheap).
+
+    Poisson arrivals at ``rate`` per second; norb uniform in the range,
+    n = floor(norb/2) - 1 electrons per spin, a log-uniform target
+    determinant count, sqrt of it strings per spin (capped at C(norb, n)),
+    1 or 2 roots.  Request r draws its integrals with seed+r and its alpha and
+    beta strings with seed+r+100000 and seed+r+200000.
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for r in range(nreq):
+        t += rng.exponential(1.0 / rate)
+        norb = int(rng.integers(norb_range[0], norb_range[1] + 1))
+        n = norb // 2 - 1
+        ndet = math.exp(rng.uniform(math.log(ndet_range[0]), math.log(ndet_range[1])))
+        nstr = min(int(round(math.sqrt(ndet))), math.comb(norb, n))
+        nroots = int(rng.integers(1, 3))
+        out.append(dict(index=r, arrival=t, norb=norb, n=n, nstr=nstr, nroots=nroots,
+                        seeds=(seed + r, seed + r + 100000, seed + r + 200000)))
+    return out
+
+
+def make_request(desc: dict) -> Workload:
+    """Materialise the arrays of one serving request."""
+    norb, n = desc["norb"], desc["n"]
+    si, sa, sb = desc["seeds"]
+    h, eri, ecore = make_integrals(norb, si)
+    a = sample_strings(norb, n, desc["nstr"], sa)
+    b = sample_strings(norb, n, desc["nstr"], sb)
+    return Workload(f"req{desc['index']}", norb, n, n, a, b, h, eri, ecore,
+                    desc["nroots"], 1e-6, meta=dict(desc))
+
+
+def random_vector(ndet: int, seed: int, nvec: int = 1) -> np.ndarray:
+    """Unit-norm random FP64 vectors, shape (nvec, ndet)."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((nvec, ndet))
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    return x
