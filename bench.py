@@ -1,0 +1,212 @@
+"""Benchmark: selected-basis Davidson solve on one MI355X.
+
+One step = one whole solve of the hot path on a synthetic workload: basis
+build (sort/dedupe), excitation tables, Hamiltonian set-up (diagonal and
+coefficients), and the Davidson iteration to ||r|| <= 1e-6 in the chosen form
+(FP32 sigma with FP64 Gram-Schmidt / Rayleigh-Ritz / residuals and FP64
+refinement).  ``value`` is whole-job sigma throughput: determinants times
+sigma vector applications divided by the step's wall time.  Also reported:
+the plain-FP64 solve of the same workload, time to 1e-6 Ha for both, and the
+dominant kernel's roofline and the CPU oracle's sigma rate.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sel26]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU = 157.3e12  # MI355X fp32 vector FLOP/s
+PEAK_FP64_VALU = 78.6e12
+PEAK_HBM = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("k_sigma.hip", "internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2601_16637_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    if the summary is missing or was taken on a different kernel source."""
+    p = os.path.join(ROOT, "profiles", "sigma_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except ValueError:
+        return None
+    ent = d.get(f"{kernel}/{workload}")
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def time_to(hist_theta, hist_time, e_ref, tol=1e-6):
+    for th, t in zip(hist_theta, hist_time):
+        if abs(th - e_ref) <= tol:
+            return t
+    return None
+
+
+def cpu_baseline(W, target_s=15.0):
+    """Oracle sigma rate (determinants/s) on a bounded random sample of rows."""
+    import oracle
+    S = oracle.OracleSystem.from_workload(W)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(S.N)
+    idx = rng.integers(0, S.N, 4000)
+    t0 = time.perf_counter()
+    S.sigma_at(x, idx)
+    dt = time.perf_counter() - t0
+    m = int(min(max(4000 * target_s / max(dt, 1e-3), 4000), 5_000_000))
+    idx = rng.integers(0, S.N, m)
+    t0 = time.perf_counter()
+    S.sigma_at(x, idx)
+    dt = time.perf_counter() - t0
+    return dict(value=m / dt, unit="det/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"FP64 sigma of {m} random determinants of the same basis "
+                       f"({dt:.1f} s, C oracle, OpenMP over rows)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sel26")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the multi-GPU path is not built "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2601_16637_amd as sbd
+    import workload as wl
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    W = wl.make_config(args.workload)
+    N = W.ndet
+    tol = 1e-6
+    log(f"[bench] workload {W.name}: norb={W.norb} n={W.n_alpha} strings={W.alpha.size}x"
+        f"{W.beta.size} N={N} roots={W.nroots}")
+
+    def solve(prec, tol_r):
+        B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
+        X = sbd.Excitations(B, stream=stream)
+        H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
+        e, rep, st = sbd.davidson(H, W.nroots, stream=stream, tol_residual=tol_r,
+                                  sigma_prec=prec, max_space=20)
+        return e, rep, st, (B, X, H)
+
+    for i in range(args.warmup):
+        e, rep, st, _ = solve(sbd.FP32, tol)
+        log(f"[bench] warmup {i}: E={e[0]:.10f} it={rep['iterations']} "
+            f"t={rep['t_total_ms']:.1f} ms")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for i in range(args.steps):
+        e, rep, st, _ = solve(sbd.FP32, tol)
+        reps.append((e, rep))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt / args.steps
+    applications = sum(r["sigma_calls"] for _, r in reps)
+    value = N * applications / dt
+    e_mixed = reps[-1][0]
+    rep_m = reps[-1][1]
+    log(f"[bench] timed: {args.steps} steps {ms_per_step:.1f} ms/step, sigma apps "
+        f"{applications}, E={e_mixed[0]:.10f}")
+
+    extra = {}
+    if not args.no_plain:
+        tp = time.perf_counter()
+        e64, rep64, st64, keep = solve(sbd.FP64, tol)
+        torch.cuda.synchronize()
+        t_plain = 1e3 * (time.perf_counter() - tp)
+        # tight FP64 reference energy for time-to-1e-6 Ha
+        eref, repref, _ = sbd.davidson(keep[2], W.nroots, stream=stream, tol_residual=1e-8,
+                                       sigma_prec=sbd.FP64, max_space=20)
+        ttp = time_to(rep64["theta_history"], rep64["time_history_ms"], eref[0])
+        ttm = time_to(rep_m["theta_history"], rep_m["time_history_ms"], eref[0])
+        extra = dict(
+            plain_fp64=dict(ms_solve=t_plain, iterations=rep64["iterations"],
+                            sigma_calls=rep64["sigma_calls"], energy=float(e64[0]),
+                            time_to_1e6_ms=ttp, sigma_ms=rep64["t_sigma_ms"],
+                            update_ms=rep64["t_update_ms"]),
+            chosen_fp32_sigma=dict(ms_solve=ms_per_step, iterations=rep_m["iterations"],
+                                   sigma_calls=rep_m["sigma_calls"],
+                                   sigma_calls_fp64=rep_m["sigma_calls_fp64"],
+                                   energy=float(e_mixed[0]), time_to_1e6_ms=ttm,
+                                   sigma_ms=rep_m["t_sigma_ms"], update_ms=rep_m["t_update_ms"]),
+            reference_energy=float(eref[0]),
+            energy_error_chosen_vs_fp64=float(abs(e_mixed[0] - eref[0])),
+            energy_error_plain_vs_fp64=float(abs(e64[0] - eref[0])),
+        )
+        log(f"[bench] plain FP64: {t_plain:.1f} ms, E={e64[0]:.10f}; ref {eref[0]:.10f}")
+
+    # dominant kernel: FP32 sigma, timed with HIP events on the launch stream
+    B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
+    X = sbd.Excitations(B, stream=stream)
+    H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
+    x32 = torch.randn(N, device="cuda", dtype=torch.float32)
+    y32 = torch.empty_like(x32)
+    for _ in range(2):
+        sbd.sigma(H, x32, y32, prec=sbd.FP32, shift=-200.0, stream=stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nl = 10
+    ev0.record(stream)
+    for _ in range(nl):
+        sbd.sigma(H, x32, y32, prec=sbd.FP32, shift=-200.0, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_launch = ev0.elapsed_time(ev1) / nl * 1e-3
+    p1a, p2a = X.count(0, 1), X.count(0, 2)
+    p1b, p2b = X.count(1, 1), X.count(1, 2)
+    nnz = N + B.nb * (p1a + p2a) + B.na * (p1b + p2b) + p1a * p1b
+    flops = 2.0 * nnz
+    achieved = flops / t_launch
+    traffic = traffic_for("k_sigma_rows<float,1>", W.name)
+    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
+                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU, traffic=traffic,
+                    kernel="k_sigma_rows<float,1>", launch_ms=t_launch * 1e3,
+                    algorithmic_flops=flops, nnz_pairs=nnz,
+                    sigma_det_per_s=N / t_launch,
+                    hbm_frac_algorithmic=(N * 8.0 / t_launch) / PEAK_HBM)
+    log(f"[bench] sigma fp32 launch {t_launch*1e3:.3f} ms, NNZ {nnz:.3e}, "
+        f"{achieved/1e12:.2f} TFLOP/s")
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(W)
+    out = dict(metric="sigma determinants/s over a whole Davidson solve to 1e-6 (chosen form: "
+                      "FP32 sigma + FP64 refinement); time-to-1e-6 Ha plain FP64 vs chosen",
+               value=value, unit="det/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=ms_per_step, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload=W.name, norb=W.norb, n_alpha=W.n_alpha, n_beta=W.n_beta,
+                           strings_per_spin=int(W.alpha.size), determinants=N,
+                           nroots=W.nroots, tol_residual=tol, max_space=20),
+               roofline=roofline, cpu_baseline=cpu, **extra)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * sbd.h - C ABI of the MI355X (gfx950) selected-basis diagonalisation library.
+ *
+ * The library computes, on one AMD GPU, the lowest eigenpairs of the
+ * electronic Hamiltonian restricted to a selected determinant basis (paper
+ * Sec. II, Eqs. 1-2).  The basis is the Cartesian product of a set of alpha
+ * and a set of beta occupation bitstrings ("half-bitstrings", Sec. II-B);
+ * determinant (ia, ib) has index ia * n_beta_str + ib where ia/ib index the
+ * SORTED string lists (Sec. III-B, task loop).  The Hamiltonian is given by
+ * one-electron integrals h_pq, two-electron integrals (pq|rs) and a core
+ * energy (Eq. 3).
+ *
+ * Conventions used by every entry point
+ *   - Bit p of a uint64 string is spatial orbital p (bit 0 = orbital 0), so
+ *     1 <= norb <= 64.  A string for spin s must have exactly n_s bits set,
+ *     all below norb.
+ *   - (pq|rs) is the chemists' two-electron integral stored at
+ *     ((p*norb + q)*norb + r)*norb + s; it must have the 8-fold symmetry
+ *     (pq|rs) = (qp|rs) = (pq|sr) = (rs|pq).  The two-body operator is
+ *     1/2 sum (pq|rs) a+_p a+_r a_s a_q with spin conserved within (pq) and
+ *     within (rs).  h is norb x norb row-major and symmetric.
+ *   - A determinant is (alpha creators, ascending)(beta creators, ascending)
+ *     acting on the vacuum; this fixes the signs of the vector components.
+ *   - All functions return an int status: 0 (SBD_OK), a positive warning or a
+ *     negative error.  On error nothing is written to outputs and a message
+ *     is available from sbd_last_error() on the calling thread.  Argument
+ *     validation happens on the host before any device work.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is enqueued on it; calls that return host data synchronise
+ *     it before returning.
+ *   - Handles are created by the library, are immutable after creation, may
+ *     be used from several streams at once, and are released with the
+ *     matching sbd_free_* call.  Host input arrays are borrowed only for the
+ *     duration of the call (the library copies them).  Device vectors passed
+ *     to sbd_sigma / sbd_davidson are owned by the caller, contiguous, and
+ *     8-byte aligned (16-byte recommended).
+ */
+#ifndef SBD_H
+#define SBD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SBD_OK = 0,
+    SBD_NOT_CONVERGED = 1,   /* warning: outputs valid, residual above tolerance after max_iter */
+    SBD_ERR_ARG = -1,        /* null pointer, negative size, nroots > N, bad option value        */
+    SBD_ERR_NORB = -2,       /* norb < 1 or norb > 64                                            */
+    SBD_ERR_STRING = -3,     /* popcount != n_spin, or a bit at or above norb is set             */
+    SBD_ERR_INTEGRALS = -4,  /* h not symmetric or (pq|rs) not 8-fold symmetric (1e-10 relative) */
+    SBD_ERR_NOMEM = -5,      /* device allocation failed or exceeds the allowed budget           */
+    SBD_ERR_HIP = -6,        /* HIP runtime error; the message carries hipGetErrorString          */
+    SBD_ERR_NUMERIC = -7,    /* NaN or Inf met during the computation                            */
+    SBD_ERR_STATE = -8       /* handles that do not belong together                              */
+} sbd_status;
+
+typedef enum { SBD_FP64 = 0, SBD_FP32 = 1 } sbd_precision;
+
+/* Message of the last failing call on this thread (never NULL). */
+const char* sbd_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int sbd_version(void);
+
+typedef struct sbd_basis sbd_basis;
+typedef struct sbd_exc sbd_exc;
+typedef struct sbd_ham sbd_ham;
+
+/*
+ * Selected basis (Sec. II-B half-bitstrings; Sec. III-B bra/ket index layout).
+ *   alpha_strings / beta_strings: host arrays of n_*_in strings in any order,
+ *   duplicates allowed.  The library validates them (popcount, bits below
+ *   norb), sorts each list ascending as unsigned integers and removes
+ *   duplicates on the device.  n_*_in >= 1.
+ * Errors: SBD_ERR_NORB, SBD_ERR_STRING, SBD_ERR_ARG, SBD_ERR_NOMEM, SBD_ERR_HIP.
+ */
+int sbd_build_basis(int norb, int n_alpha, int n_beta,
+                    const uint64_t* alpha_strings, int64_t n_alpha_in,
+                    const uint64_t* beta_strings, int64_t n_beta_in,
+                    void* stream, sbd_basis** out);
+/* Numbers of unique sorted strings per spin (synchronises the build stream). */
+int sbd_basis_sizes(const sbd_basis* b, int64_t* n_alpha_str, int64_t* n_beta_str);
+/* Host copies of the sorted unique strings (arrays sized by sbd_basis_sizes). */
+int sbd_basis_strings(const sbd_basis* b, uint64_t* alpha_out, uint64_t* beta_out);
+void sbd_free_basis(sbd_basis* b);
+
+/*
+ * Same-spin excitation tables (Slater-Condon neighbourhoods, Eq. 4; the
+ * singles/doubles lists of the task loop in Sec. III-B).  For spin s and
+ * bra string I, the single table lists every ket J of the same spin with
+ * popcount(I ^ J) == 2, the double table every J with popcount(I ^ J) == 4,
+ * as CSR rows sorted by ascending ket index J.  A single records (i, a):
+ * i in J\I is annihilated and a in I\J created; a double records (i, j, a, b)
+ * with i < j in J\I and a < b in I\J.  sign is the phase of a+_a a_i |J>
+ * (single) or a+_a a+_b a_j a_i |J> (double), operators applied right to
+ * left.  Built on the device by a wavefront ballot/popcount scan, an
+ * exclusive scan of the row counts and a compaction.
+ */
+int sbd_build_excitations(const sbd_basis* b, void* stream, sbd_exc** out);
+/* Number of entries of a table.  spin: 0 alpha, 1 beta; kind: 1 single, 2 double. */
+int sbd_exc_count(const sbd_exc* e, int spin, int kind, int64_t* nnz);
+/*
+ * Host copy of a table: row_ptr[n_str+1] (int64), J[nnz] (int32),
+ * orbs[nnz*2*kind] (uint8: (i,a) or (i,j,a,b)), sign[nnz] (int8, +1/-1).
+ * Any output pointer may be NULL to skip it.
+ */
+int sbd_exc_export(const sbd_exc* e, int spin, int kind,
+                   int64_t* row_ptr, int32_t* J, uint8_t* orbs, int8_t* sign);
+void sbd_free_exc(sbd_exc* e);
+
+/*
+ * Hamiltonian on a basis (Eq. 3).  Uploads h and (pq|rs), builds the
+ * diagonal H_ii (cached, Sec. II-D) and per-table-entry matrix-element
+ * coefficients in FP64 and FP32.  h1: norb*norb host array; eri: norb^4
+ * host array; e_core is added to every diagonal element.
+ * Errors: SBD_ERR_INTEGRALS (asymmetric input), SBD_ERR_STATE (exc not built
+ * from b), SBD_ERR_ARG, SBD_ERR_NOMEM, SBD_ERR_HIP.
+ */
+int sbd_set_hamiltonian(const sbd_basis* b, const sbd_exc* e,
+                        const double* h1, const double* eri, double e_core,
+                        void* stream, sbd_ham** out);
+/* Copy the FP64 diagonal H_ii (N values) into a caller-owned device buffer. */
+int sbd_ham_diag(const sbd_ham* h, double* diag_dev, void* stream);
+void sbd_free_ham(sbd_ham* h);
+
+/*
+ * Matrix-free sigma = (H - shift I) c (Eq. 4, apply_H of Sec. II-B; the
+ * three task types of Sec. III-B: alpha-beta, beta-beta, alpha-alpha).
+ *   nvec vectors of N = n_alpha_str * n_beta_str determinants.
+ *   prec SBD_FP64: c, sigma are double; SBD_FP32: float, with FP32 gathers
+ *   and FP32 accumulation (the diagonal term is formed as (float)(H_ii - shift)).
+ *   layout 0: vector v at offset v*N ([v][ia][ib]); layout 1: interleaved,
+ *   element (det, v) at det*nvec + v ([ia][ib][v]).
+ *   c and sigma are caller-owned device pointers that must not overlap.
+ * Each sigma element is produced by one thread in a fixed order: results are
+ * bitwise reproducible run to run.
+ * Errors: SBD_ERR_ARG (nvec < 1, nvec > 8 with layout 1, null pointers,
+ * bad precision), SBD_ERR_STATE, SBD_ERR_HIP.
+ */
+int sbd_sigma(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h,
+              int nvec, int prec, double shift,
+              const void* c, void* sigma, int layout, void* stream);
+
+/* Options of sbd_davidson; sbd_davidson_default_opts fills the defaults. */
+typedef struct {
+    double tol_residual;   /* ||H u - theta u||_2 per root (unit u); default 1e-6                 */
+    int max_iter;          /* iterations (subspace expansions); default 200                        */
+    int max_space;         /* subspace size before restart; default 20 (>= 2*nroots+1)             */
+    double precond_delta;  /* delta of the damped denominators (Eq. 7); default 1e-8 Ha            */
+    int sigma_prec;        /* SBD_FP64 (plain) or SBD_FP32 (FP32 sigma + FP64 refinement)          */
+    int use_graph;         /* reserved (0)                                                          */
+    int use_autotune;      /* reserved (0)                                                          */
+    const double* guess;   /* optional device pointer, n_guess x N initial vectors (NULL = none)   */
+    int n_guess;
+    int verbose;           /* 1: print one line per iteration to stderr                            */
+} sbd_davidson_opts;
+
+typedef struct {
+    int iterations;        /* expansions performed                                                  */
+    int sigma_calls;       /* sigma applications (vectors)                                          */
+    int sigma_calls_fp64;  /* of which in FP64                                                      */
+    int converged;         /* 1 if every root met tol_residual                                      */
+    int restarts;
+    double residual[64];   /* final ||r||_2 per root                                                */
+    double ortho_loss;     /* ||V^T V - I||_F at exit                                               */
+    double t_sigma_ms, t_update_ms, t_total_ms;
+    int n_history;         /* entries filled in theta_history                                       */
+    double theta_history[512]; /* lowest Ritz value per iteration (first 512 iterations)            */
+    double time_history_ms[512]; /* wall time since the call started, per iteration                 */
+} sbd_davidson_report;
+
+void sbd_davidson_default_opts(sbd_davidson_opts* o);
+
+/*
+ * Lowest nroots eigenpairs by the Davidson method (Sec. II-C): sigma of new
+ * basis vectors, projected matrix T = V^T W, smallest Ritz pairs, residual
+ * r = W y - theta V y, damped diagonal preconditioner (Eqs. 6-7),
+ * orthogonalisation against the subspace with a second pass, restart onto
+ * the lowest Ritz vectors at max_space, block variant for several roots.
+ * Initial vectors: opts->guess, else unit vectors on the nroots lowest
+ * diagonal elements (lowest index on ties).
+ *   energies: host array of nroots (including e_core), ascending.
+ *   vectors : optional caller-owned device array nroots x N (FP64, unit norm).
+ *   report  : optional host struct.
+ * Returns SBD_OK, SBD_NOT_CONVERGED (outputs valid), or an error
+ * (SBD_ERR_ARG, SBD_ERR_STATE, SBD_ERR_NOMEM, SBD_ERR_NUMERIC, SBD_ERR_HIP).
+ * Workspace (2*max_space + 2*nroots vectors of N doubles, plus FP32 copies
+ * in SBD_FP32 mode) is allocated for the call and freed before returning.
+ */
+int sbd_davidson(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h, int nroots,
+                 const sbd_davidson_opts* opts, double* energies, double* vectors,
+                 sbd_davidson_report* report, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SBD_H */

@@ -1,0 +1,12 @@
+"""MI355X-native selected-basis diagonalisation (SBD) hot path.
+
+The computation lives in the HIP library ``libsbd.so`` (C ABI in
+``include/sbd.h``); this package only marshals arguments to it.
+"""
+from ._native import (FP32, FP64, SBD_NOT_CONVERGED, SBD_OK, Basis, DavidsonOpts,
+                      DavidsonReport, Excitations, Hamiltonian, SBDError, davidson,
+                      default_opts, last_error, load, sigma, EXPORTED, LIB_PATH)
+
+__all__ = ["FP32", "FP64", "SBD_OK", "SBD_NOT_CONVERGED", "Basis", "Excitations",
+           "Hamiltonian", "SBDError", "sigma", "davidson", "default_opts", "DavidsonOpts",
+           "DavidsonReport", "last_error", "load", "EXPORTED", "LIB_PATH"]

@@ -1,0 +1,262 @@
+"""ctypes binding of libsbd.so: argument marshalling only.
+
+Every computation runs in the HIP library.  There is no CPU fallback: if the
+library is missing, loading raises ``RuntimeError``.  Device buffers are
+passed as torch tensors (their ``data_ptr()``) or raw integer addresses;
+streams as ``torch.cuda.Stream``, a raw ``hipStream_t`` integer, or None for
+torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsbd.so")
+
+SBD_OK = 0
+SBD_NOT_CONVERGED = 1
+FP64, FP32 = 0, 1
+STATUS_NAMES = {0: "SBD_OK", 1: "SBD_NOT_CONVERGED", -1: "SBD_ERR_ARG", -2: "SBD_ERR_NORB",
+                -3: "SBD_ERR_STRING", -4: "SBD_ERR_INTEGRALS", -5: "SBD_ERR_NOMEM",
+                -6: "SBD_ERR_HIP", -7: "SBD_ERR_NUMERIC", -8: "SBD_ERR_STATE"}
+
+# Every symbol include/sbd.h declares.
+EXPORTED = ["sbd_last_error", "sbd_version", "sbd_build_basis", "sbd_basis_sizes",
+            "sbd_basis_strings", "sbd_free_basis", "sbd_build_excitations", "sbd_exc_count",
+            "sbd_exc_export", "sbd_free_exc", "sbd_set_hamiltonian", "sbd_ham_diag",
+            "sbd_free_ham", "sbd_sigma", "sbd_davidson_default_opts", "sbd_davidson"]
+
+
+class SBDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class DavidsonOpts(ctypes.Structure):
+    _fields_ = [("tol_residual", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("max_space", ctypes.c_int), ("precond_delta", ctypes.c_double),
+                ("sigma_prec", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("use_autotune", ctypes.c_int), ("guess", ctypes.c_void_p),
+                ("n_guess", ctypes.c_int), ("verbose", ctypes.c_int)]
+
+
+class DavidsonReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("sigma_calls", ctypes.c_int),
+                ("sigma_calls_fp64", ctypes.c_int), ("converged", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("residual", ctypes.c_double * 64),
+                ("ortho_loss", ctypes.c_double), ("t_sigma_ms", ctypes.c_double),
+                ("t_update_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
+                ("n_history", ctypes.c_int), ("theta_history", ctypes.c_double * 512),
+                ("time_history_ms", ctypes.c_double * 512)]
+
+    def as_dict(self, nroots: int) -> dict:
+        n = self.n_history
+        return dict(iterations=self.iterations, sigma_calls=self.sigma_calls,
+                    sigma_calls_fp64=self.sigma_calls_fp64, converged=bool(self.converged),
+                    restarts=self.restarts, residual=list(self.residual[:nroots]),
+                    ortho_loss=self.ortho_loss, t_sigma_ms=self.t_sigma_ms,
+                    t_update_ms=self.t_update_ms, t_total_ms=self.t_total_ms,
+                    theta_history=list(self.theta_history[:n]),
+                    time_history_ms=list(self.time_history_ms[:n]))
+
+
+_lib = None
+
+
+def load():
+    """Load libsbd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run __graft_entry__.build() or python -m paper_2601_16637_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    L.sbd_last_error.restype = ctypes.c_char_p
+    L.sbd_last_error.argtypes = []
+    L.sbd_version.restype = i32
+    L.sbd_build_basis.argtypes = [i32, i32, i32, P, i64, P, i64, P, PP]
+    L.sbd_basis_sizes.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.sbd_basis_strings.argtypes = [P, P, P]
+    L.sbd_free_basis.argtypes = [P]
+    L.sbd_free_basis.restype = None
+    L.sbd_build_excitations.argtypes = [P, P, PP]
+    L.sbd_exc_count.argtypes = [P, i32, i32, ctypes.POINTER(i64)]
+    L.sbd_exc_export.argtypes = [P, i32, i32, P, P, P, P]
+    L.sbd_free_exc.argtypes = [P]
+    L.sbd_free_exc.restype = None
+    L.sbd_set_hamiltonian.argtypes = [P, P, P, P, d, P, PP]
+    L.sbd_ham_diag.argtypes = [P, P, P]
+    L.sbd_free_ham.argtypes = [P]
+    L.sbd_free_ham.restype = None
+    L.sbd_sigma.argtypes = [P, P, P, i32, i32, d, P, P, i32, P]
+    L.sbd_davidson_default_opts.argtypes = [ctypes.POINTER(DavidsonOpts)]
+    L.sbd_davidson_default_opts.restype = None
+    L.sbd_davidson.argtypes = [P, P, P, i32, ctypes.POINTER(DavidsonOpts), P, P,
+                               ctypes.POINTER(DavidsonReport), P]
+    for name in EXPORTED:
+        if name not in ("sbd_last_error", "sbd_version", "sbd_free_basis", "sbd_free_exc",
+                        "sbd_free_ham", "sbd_davidson_default_opts"):
+            getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return load().sbd_last_error().decode()
+
+
+def check(status: int) -> int:
+    if status < 0:
+        raise SBDError(status, last_error())
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return ctypes.c_void_p(0)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return ctypes.c_void_p(x)
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def _host(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Basis:
+    """Selected alpha x beta basis (sbd_build_basis)."""
+
+    def __init__(self, norb, n_alpha, n_beta, alpha, beta, stream=None):
+        L = load()
+        a = np.ascontiguousarray(alpha, dtype=np.uint64)
+        b = np.ascontiguousarray(beta, dtype=np.uint64)
+        h = ctypes.c_void_p()
+        check(L.sbd_build_basis(int(norb), int(n_alpha), int(n_beta), _host(a), a.size,
+                                _host(b), b.size, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.norb, self.n_alpha, self.n_beta = int(norb), int(n_alpha), int(n_beta)
+        na, nb = ctypes.c_int64(), ctypes.c_int64()
+        check(L.sbd_basis_sizes(h, ctypes.byref(na), ctypes.byref(nb)))
+        self.na, self.nb = na.value, nb.value
+        self.N = self.na * self.nb
+
+    def strings(self):
+        a = np.zeros(self.na, dtype=np.uint64)
+        b = np.zeros(self.nb, dtype=np.uint64)
+        check(load().sbd_basis_strings(self._h, _host(a), _host(b)))
+        return a, b
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.sbd_free_basis(self._h)
+            self._h = None
+
+
+class Excitations:
+    """Same-spin single/double excitation tables (sbd_build_excitations)."""
+
+    def __init__(self, basis: Basis, stream=None):
+        self.basis = basis
+        h = ctypes.c_void_p()
+        check(load().sbd_build_excitations(basis._h, _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def count(self, spin: int, kind: int) -> int:
+        n = ctypes.c_int64()
+        check(load().sbd_exc_count(self._h, spin, kind, ctypes.byref(n)))
+        return n.value
+
+    def export(self, spin: int, kind: int):
+        nstr = self.basis.na if spin == 0 else self.basis.nb
+        nnz = self.count(spin, kind)
+        rp = np.zeros(nstr + 1, dtype=np.int64)
+        J = np.zeros(max(nnz, 1), dtype=np.int32)
+        orbs = np.zeros((max(nnz, 1), 2 * kind), dtype=np.uint8)
+        sign = np.zeros(max(nnz, 1), dtype=np.int8)
+        check(load().sbd_exc_export(self._h, spin, kind, _host(rp), _host(J), _host(orbs),
+                                    _host(sign)))
+        return rp, J[:nnz], orbs[:nnz], sign[:nnz]
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.sbd_free_exc(self._h)
+            self._h = None
+
+
+class Hamiltonian:
+    """Integrals, cached diagonal and per-entry coefficients (sbd_set_hamiltonian)."""
+
+    def __init__(self, basis: Basis, exc: Excitations, h1, eri, e_core, stream=None):
+        self.basis, self.exc = basis, exc
+        h1 = np.ascontiguousarray(h1, dtype=np.float64)
+        eri = np.ascontiguousarray(eri, dtype=np.float64)
+        n = basis.norb
+        if h1.size != n * n or eri.size != n ** 4:
+            raise ValueError("integral arrays have the wrong size for norb")
+        h = ctypes.c_void_p()
+        check(load().sbd_set_hamiltonian(basis._h, exc._h, _host(h1), _host(eri),
+                                         float(e_core), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def diag_into(self, out, stream=None):
+        check(load().sbd_ham_diag(self._h, _dptr(out), _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.sbd_free_ham(self._h)
+            self._h = None
+
+
+def sigma(ham: Hamiltonian, c, out, nvec: int = 1, prec: int = FP64, shift: float = 0.0,
+          layout: int = 0, stream=None):
+    """out = (H - shift) c on device buffers (sbd_sigma)."""
+    check(load().sbd_sigma(ham.basis._h, ham.exc._h, ham._h, int(nvec), int(prec), float(shift),
+                           _dptr(c), _dptr(out), int(layout), _stream(stream)))
+    return out
+
+
+def default_opts() -> DavidsonOpts:
+    o = DavidsonOpts()
+    load().sbd_davidson_default_opts(ctypes.byref(o))
+    return o
+
+
+def davidson(ham: Hamiltonian, nroots: int = 1, vectors=None, stream=None, **kw):
+    """Lowest eigenpairs (sbd_davidson).  Keyword options are DavidsonOpts fields;
+    ``guess`` may be a device tensor of shape (n_guess, N).  Returns
+    (energies ndarray, report dict, status)."""
+    o = default_opts()
+    for k, v in kw.items():
+        if k == "guess":
+            o.guess = _dptr(v).value if v is not None else None
+            continue
+        if not hasattr(o, k):
+            raise TypeError(f"unknown Davidson option {k}")
+        setattr(o, k, v)
+    e = np.zeros(nroots, dtype=np.float64)
+    rep = DavidsonReport()
+    st = check(load().sbd_davidson(ham.basis._h, ham.exc._h, ham._h, int(nroots),
+                                   ctypes.byref(o), _host(e), _dptr(vectors), ctypes.byref(rep),
+                                   _stream(stream)))
+    return e, rep.as_dict(nroots), st

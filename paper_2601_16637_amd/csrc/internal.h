@@ -1,0 +1,196 @@
+// Internal declarations shared by the host core (abi.cpp, davidson.cpp) and
+// the HIP kernels (*.hip).  Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sbd.h"
+
+namespace sbd {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+int fail(int status, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define SBD_HIP(call)                                           \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
+        if (e_ != hipSuccess) return ::sbd::hip_fail(e_, #call); \
+    } while (0)
+
+// Device buffer owned by a handle.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    hipError_t alloc(size_t n) {
+        release();
+        bytes = n;
+        if (n == 0) return hipSuccess;
+        return hipMalloc(&p, n);
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------- handles
+struct SpinStrings {
+    int64_t n = 0;              // unique sorted strings
+    DevBuf d;                   // uint64[n]
+    std::vector<uint64_t> host; // sorted copy
+};
+
+}  // namespace sbd
+
+struct sbd_basis {
+    int norb = 0, n_el[2] = {0, 0};
+    sbd::SpinStrings s[2];  // 0 alpha, 1 beta
+    uint64_t id = 0;        // unique per basis, ties tables/hamiltonians to it
+};
+
+namespace sbd {
+// One CSR table: row_ptr[n+1], ket index J, packed orbitals, sign.
+struct Table {
+    int kind = 1;
+    int64_t nnz = 0;
+    DevBuf row_ptr;  // int64[n+1]
+    DevBuf J;        // int32[nnz]
+    DevBuf orb;      // uint32[nnz]: i | j<<8 | a<<16 | b<<24 (double); i | a<<8 (single)
+    DevBuf sign;     // int8[nnz]
+};
+}  // namespace sbd
+
+struct sbd_exc {
+    uint64_t basis_id = 0;
+    int64_t n[2] = {0, 0};
+    sbd::Table t[2][2];  // [spin][kind-1]
+    uint64_t id = 0;
+};
+
+namespace sbd {
+// Hamiltonian data per spin: coefficients per table entry and the spectator
+// table G[pair(a,i)][string] = sum_{k in string} (ai|kk).
+struct SpinCoef {
+    DevBuf c1_64, c1_32;  // single base coefficient s*(h_ai + sum_{k in J} ((ai|kk)-(ak|ki)))
+    DevBuf ps1;           // int32 per single: pair(a,i) << 1 | (sign < 0)
+    DevBuf c2_64, c2_32;  // double coefficient s*((ai|bj) - (aj|bi))
+    DevBuf G64, G32;      // spectator table of THIS spin's strings: [npair][n]
+    DevBuf dspin;         // double[n]: same-spin diagonal part of each string
+};
+}  // namespace sbd
+
+struct sbd_ham {
+    uint64_t basis_id = 0, exc_id = 0;
+    int norb = 0;
+    int64_t na = 0, nb = 0;
+    double e_core = 0.0;
+    double diag_min = 0.0;
+    sbd::DevBuf h64, eri64, eri32;  // integrals on device
+    sbd::SpinCoef sc[2];
+    sbd::DevBuf diag;               // double[N]
+};
+
+namespace sbd {
+
+inline int pair_index(int a, int i) {  // symmetric pair (a,i) -> triangular index
+    int hi = a > i ? a : i, lo = a > i ? i : a;
+    return hi * (hi + 1) / 2 + lo;
+}
+inline int npairs(int norb) { return norb * (norb + 1) / 2; }
+
+// ---------------------------------------------------------------- kernels
+// All launchers enqueue on `st` and return hipGetLastError() of the launch.
+
+// Basis: sort ascending and dedupe `n` strings in d_in (device, capacity >= pow2(n)).
+// Writes unique strings to d_out, count to d_count (device int64).
+hipError_t launch_sort_unique(uint64_t* d_work, int64_t n, uint64_t* d_out, int64_t* d_count,
+                              int64_t* d_tmp_i64, hipStream_t st);
+
+// Excitation tables.
+hipError_t launch_exc_count(const uint64_t* d_s, int64_t n, int64_t* d_cnt1, int64_t* d_cnt2,
+                            hipStream_t st);
+hipError_t launch_exclusive_scan(const int64_t* d_in, int64_t n, int64_t* d_out /*n+1*/,
+                                 hipStream_t st);
+hipError_t launch_exc_fill(const uint64_t* d_s, int64_t n, const int64_t* rp1, const int64_t* rp2,
+                           int32_t* J1, uint32_t* orb1, int8_t* sg1, int32_t* J2, uint32_t* orb2,
+                           int8_t* sg2, hipStream_t st);
+
+// Hamiltonian pieces.
+hipError_t launch_string_diag(const uint64_t* d_s, int64_t n, int norb, const double* h,
+                              const double* eri, double* out, hipStream_t st);
+hipError_t launch_spectator(const uint64_t* d_s, int64_t n, int norb, const double* eri,
+                            double* G64, float* G32, hipStream_t st);
+hipError_t launch_single_coef(const uint64_t* d_s, int64_t nnz, const int32_t* J,
+                              const uint32_t* orb, const int8_t* sg, int norb, const double* h,
+                              const double* eri, double* c64, float* c32, int32_t* ps,
+                              hipStream_t st);
+hipError_t launch_double_coef(int64_t nnz, const uint32_t* orb, const int8_t* sg, int norb,
+                              const double* eri, double* c64, float* c32, hipStream_t st);
+hipError_t launch_full_diag(const uint64_t* d_a, int64_t na, const double* da,
+                            const double* db, const double* Gb /*[npair][nb]*/, int64_t nb,
+                            int norb, double e_core, double* diag, hipStream_t st);
+hipError_t launch_d2f(const double* in, float* out, int64_t n, hipStream_t st);
+
+// Sigma.  Tables and coefficients of both spins, one precision.
+template <class T>
+struct SigmaArgs {
+    int64_t na, nb;
+    int norb;
+    // alpha tables
+    const int64_t* a1p; const int32_t* a1J; const uint32_t* a1o; const int8_t* a1s;
+    const T* a1c; const int32_t* a1ps;
+    const int64_t* a2p; const int32_t* a2J; const T* a2c;
+    // beta tables
+    const int64_t* b1p; const int32_t* b1J; const uint32_t* b1o; const int8_t* b1s;
+    const T* b1c; const int32_t* b1ps;
+    const int64_t* b2p; const int32_t* b2J; const T* b2c;
+    const T* Ga;   // [npair][na]  sum_{k in alpha(ia)} (pair|kk)
+    const T* Gb;   // [npair][nb]
+    const T* eri;  // norb^4
+    const double* diag;
+    double shift;
+};
+template <class T>
+hipError_t launch_sigma(const SigmaArgs<T>& A, int nvec, const T* c, T* y, int layout,
+                        hipStream_t st);
+
+// Dense vector kernels for Davidson (FP64 unless noted).  Vectors are rows
+// of length N stored contiguously: A + j*N.
+// out[j] (device) = sum_i A[j][i] x[i], j < m.  Deterministic two-stage reduction.
+hipError_t launch_multidot(const double* A, int m, const double* x, int64_t N, double* d_out,
+                           double* d_part, hipStream_t st);
+// x[i] -= sum_j A[j][i] h[j]  (h on device)
+hipError_t launch_sub_combination(const double* A, int m, const double* d_h, double* x, int64_t N,
+                                  hipStream_t st);
+// out[r][i] = sum_j A[j][i] Y[j*ldy + r], r < k (Y on device, m x k column block)
+hipError_t launch_combination(const double* A, int m, const double* d_Y, int ldy, int k,
+                              double* out, int64_t N, hipStream_t st);
+// t[i] = (W y - theta V y)_i / damp(diag_i - theta); part sums of r^2 into d_part (block partials)
+hipError_t launch_residual_precond(const double* V, const double* W, int m, const double* d_y,
+                                   double theta, const double* diag, double delta, double* t,
+                                   int64_t N, double* d_out /*[2]: r2, t2*/, double* d_part,
+                                   hipStream_t st);
+hipError_t launch_scale(double* x, int64_t N, double s, hipStream_t st);
+hipError_t launch_copy(const double* x, double* y, int64_t N, hipStream_t st);
+// lexicographic successor minimum: smallest (v,i) > (vprev, iprev); writes value/index
+hipError_t launch_argmin_after(const double* v, int64_t N, double vprev, int64_t iprev,
+                               double* d_val, int64_t* d_idx, double* d_part_v,
+                               int64_t* d_part_i, hipStream_t st);
+hipError_t launch_set_unit(double* x, int64_t N, int64_t idx, hipStream_t st);
+
+// Reduction scratch sizing.
+constexpr int kRedBlocks = 1024;
+
+}  // namespace sbd

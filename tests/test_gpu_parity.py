@@ -1,0 +1,362 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Bars: strings and excitation tables bit-exact; FP64 sigma within 1e-12
+relative (normwise); FP32 sigma within its rounding bound; energies within
+1e-8 Ha (FP64) and 1e-6 Ha (mixed precision) of the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workload as wl
+
+torch = pytest.importorskip("torch")
+sbd = pytest.importorskip("paper_2601_16637_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def gpu_system(norb, na_el, nb_el, A, B, h, eri, ec):
+    bas = sbd.Basis(norb, na_el, nb_el, A, B)
+    exc = sbd.Excitations(bas)
+    ham = sbd.Hamiltonian(bas, exc, h, eri, ec)
+    return bas, exc, ham
+
+
+def from_workload(W):
+    return gpu_system(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, W.h, W.eri, W.e_core)
+
+
+def dev(x, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(x), device=DEV, dtype=dtype)
+
+
+def gpu_sigma(ham, x, prec=0, shift=0.0, nvec=1, layout=0):
+    dt = torch.float64 if prec == 0 else torch.float32
+    xd = dev(x, dt)
+    yd = torch.empty_like(xd)
+    sbd.sigma(ham, xd, yd, nvec=nvec, prec=prec, shift=shift, layout=layout)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ------------------------------------------------------------------ a1 basis
+@pytest.mark.parametrize("count,seed", [(1, 1), (7, 2), (1023, 3), (1024, 4), (1025, 5),
+                                        (5000, 6), (20000, 7)])
+def test_basis_sort_unique_bitexact(count, seed):
+    norb, n = 30, 9
+    rng = np.random.default_rng(seed)
+    pool = wl.sample_strings(norb, n, max(count // 2, 1), seed)
+    raw = rng.choice(pool, size=count, replace=True)       # duplicates, any order
+    bas = sbd.Basis(norb, n, n, raw, raw[::-1].copy())
+    a, b = bas.strings()
+    ref = oracle.sort_unique(raw)
+    assert np.array_equal(a, ref) and np.array_equal(b, ref)
+    assert bas.na == ref.size
+
+
+def test_basis_edge_strings():
+    # zero electrons (only the empty string), all orbitals filled, norb = 64
+    z = np.zeros(3, dtype=np.uint64)
+    bas = sbd.Basis(5, 0, 0, z, z)
+    assert bas.na == 1 and bas.nb == 1
+    full = np.array([(1 << 64) - 1] * 2, dtype=np.uint64)
+    bas = sbd.Basis(64, 64, 64, full, full)
+    a, _ = bas.strings()
+    assert a.tolist() == [(1 << 64) - 1]
+    top = np.array([(1 << 63) | 1, (1 << 62) | 2, (1 << 63) | 1], dtype=np.uint64)
+    bas = sbd.Basis(64, 2, 2, top, top)
+    assert np.array_equal(bas.strings()[0], np.sort(np.unique(top)))
+
+
+# ------------------------------------------------------------------ a2 tables
+def _check_tables(bas, exc, norb):
+    a, b = bas.strings()
+    for spin, s in ((0, a), (1, b)):
+        for kind in (1, 2):
+            ref = oracle.exc_table(s, norb, kind)
+            rp, J, orbs, sign = exc.export(spin, kind)
+            assert np.array_equal(rp, ref.row_ptr), (spin, kind)
+            assert np.array_equal(J, ref.J), (spin, kind)
+            assert np.array_equal(orbs, ref.orbs), (spin, kind)
+            assert np.array_equal(sign, ref.sign), (spin, kind)
+
+
+@pytest.mark.parametrize("name,nstr", [("fci8", None), ("sel16", 2000), ("block20", 700),
+                                       ("sel26", 10000)])
+def test_tables_bitexact(name, nstr):
+    W = wl.make_config(name, nstr=nstr)
+    bas = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta)
+    exc = sbd.Excitations(bas)
+    _check_tables(bas, exc, W.norb)
+
+
+@pytest.mark.parametrize("norb,n,count", [(64, 3, 300), (64, 61, 200), (6, 0, 1), (6, 6, 1),
+                                          (12, 1, 12), (40, 20, 2100)])
+def test_tables_edge_shapes(norb, n, count):
+    A = wl.sample_strings(norb, n, count, 17)
+    bas = sbd.Basis(norb, n, n, A, A)
+    exc = sbd.Excitations(bas)
+    _check_tables(bas, exc, norb)
+
+
+# ------------------------------------------------------------------ a3 diagonal
+@pytest.mark.parametrize("name,nstr", [("fci8", None), ("sel16", 300), ("sel26", 150)])
+def test_diagonal(name, nstr):
+    W = wl.make_config(name, nstr=nstr)
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    d = torch.empty(S.N, device=DEV, dtype=torch.float64)
+    ham.diag_into(d)
+    torch.cuda.synchronize()
+    assert np.abs(d.cpu().numpy() - S.diag()).max() <= 1e-12 * np.abs(S.diag()).max()
+
+
+def test_trace_closed_form_full_ci():
+    """P6 on the GPU diagonal: full-CI trace against the combinatorial formula."""
+    n, na, nb = 8, 4, 3
+    h, eri, ec = wl.make_integrals(n, 77)
+    _, _, ham = gpu_system(n, na, nb, wl.all_strings(n, na), wl.all_strings(n, nb), h, eri, ec)
+    C = math.comb
+    Na, Nb = C(n, na), C(n, nb)
+    d = torch.empty(Na * Nb, device=DEV, dtype=torch.float64)
+    ham.diag_into(d)
+    torch.cuda.synchronize()
+    trh = np.trace(h)
+    Kp = sum(eri[p, p, q, q] - eri[p, q, q, p] for p in range(n) for q in range(p + 1, n))
+    J = sum(eri[p, p, q, q] for p in range(n) for q in range(n))
+    closed = (Na * Nb * ec + Nb * C(n - 1, na - 1) * trh + Na * C(n - 1, nb - 1) * trh
+              + Nb * C(n - 2, na - 2) * Kp + Na * C(n - 2, nb - 2) * Kp
+              + C(n - 1, na - 1) * C(n - 1, nb - 1) * J)
+    assert abs(d.sum().item() - closed) <= 1e-10 * abs(closed)
+
+
+# ------------------------------------------------------------------ a4/a5 sigma
+CASES = [("fci8", None), ("sel16", 300), ("block20", 260), ("sel26", 180)]
+
+
+@pytest.mark.parametrize("name,nstr", CASES)
+def test_sigma_fp64(name, nstr):
+    W = wl.make_config(name, nstr=nstr)
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    x = wl.random_vector(S.N, 3)[0]
+    y = gpu_sigma(ham, x)
+    assert rel(y, S.sigma(x)) <= 1e-12
+
+
+def test_sigma_fp64_ragged_and_asymmetric():
+    """nalpha != nbeta, string counts not multiples of the block size."""
+    norb = 14
+    A = wl.sample_strings(norb, 6, 333, 41)
+    B = wl.sample_strings(norb, 4, 257, 42)
+    h, eri, ec = wl.make_integrals(norb, 43)
+    _, _, ham = gpu_system(norb, 6, 4, A, B, h, eri, ec)
+    S = oracle.OracleSystem(norb, A, B, h, eri, ec)
+    x = wl.random_vector(S.N, 44)[0]
+    assert rel(gpu_sigma(ham, x), S.sigma(x)) <= 1e-12
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_sigma_multivector(layout):
+    W = wl.make_config("sel16", nstr=200)
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    X = wl.random_vector(S.N, 9, nvec=4)
+    Yo = S.sigma(X)
+    if layout == 0:
+        Y = gpu_sigma(ham, X.reshape(-1), nvec=4, layout=0).reshape(4, S.N)
+    else:
+        Y = gpu_sigma(ham, X.T.reshape(-1), nvec=4, layout=1).reshape(S.N, 4).T
+    for v in range(4):
+        assert rel(Y[v], Yo[v]) <= 1e-12
+
+
+def test_sigma_fp32_within_rounding_bound():
+    """|s32 - s64|_I <= 2 (z_I + 2) u32 (|H - shift| |x|)_I with u32 = 2^-24 (dense |H|)."""
+    W = wl.make_config("fci8")
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    Hd = S.dense_h()
+    shift = S.diag().min()
+    Hs = Hd - shift * np.eye(S.N)
+    x = wl.random_vector(S.N, 12)[0].astype(np.float32).astype(np.float64)
+    y32 = gpu_sigma(ham, x, prec=1, shift=shift)
+    exact = Hs @ x
+    z = (np.abs(Hs) > 0).sum(axis=1)
+    bound = 2 * (z + 2) * 2.0 ** -24 * (np.abs(Hs) @ np.abs(x))
+    assert np.all(np.abs(y32 - exact) <= bound)
+
+
+def test_sigma_fp32_normwise_sampled_basis():
+    W = wl.make_config("sel26", nstr=200)
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    shift = S.diag().min()
+    x = wl.random_vector(S.N, 13)[0].astype(np.float32).astype(np.float64)
+    y32 = gpu_sigma(ham, x, prec=1, shift=shift)
+    exact = S.sigma(x) - shift * x
+    assert rel(y32, exact) <= 2e-5
+
+
+def test_hermiticity_gpu():
+    W = wl.make_config("block20", nstr=400)
+    _, _, ham = from_workload(W)
+    x, y = wl.random_vector(400 * 400, 21, nvec=2)
+    sx, sy = gpu_sigma(ham, x), gpu_sigma(ham, y)
+    assert abs(x @ sy - sx @ y) <= 1e-13 * np.linalg.norm(sx)
+
+
+def test_alpha_beta_swap_gpu():
+    W = wl.make_config("sel16", nstr=150)
+    B = wl.sample_strings(16, 8, 190, 5)
+    _, _, h1 = gpu_system(16, 8, 8, W.alpha, B, W.h, W.eri, W.e_core)
+    _, _, h2 = gpu_system(16, 8, 8, B, W.alpha, W.h, W.eri, W.e_core)
+    na, nb = W.alpha.size, B.size
+    Cm = wl.random_vector(na * nb, 6)[0].reshape(na, nb)
+    y1 = gpu_sigma(h1, Cm.reshape(-1)).reshape(na, nb)
+    y2 = gpu_sigma(h2, Cm.T.reshape(-1)).reshape(nb, na)
+    assert np.abs(y1.T - y2).max() <= 1e-12 * np.abs(y1).max()
+
+
+def test_sigma_deterministic_bitwise():
+    W = wl.make_config("sel16", nstr=400)
+    _, _, ham = from_workload(W)
+    x = wl.random_vector(W.ndet, 8)[0]
+    y1 = gpu_sigma(ham, x)
+    y2 = gpu_sigma(ham, x)
+    assert np.array_equal(y1, y2)
+
+
+@pytest.mark.parametrize("name", ["sel16", "sel26"])
+def test_sigma_full_size_sampled(name):
+    """Full-size basis in the launch configuration the benchmark uses: sampled
+    outputs against the oracle computed one determinant at a time."""
+    W = wl.make_config(name)
+    _, _, ham = from_workload(W)
+    N = W.ndet
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal(N)
+    x /= np.linalg.norm(x)
+    y = gpu_sigma(ham, x)
+    S = oracle.OracleSystem.from_workload(W)
+    idx = np.unique(np.concatenate([rng.integers(0, N, 3000), [0, N - 1, W.beta.size - 1,
+                                                               W.beta.size, N // 2]]))
+    yo = S.sigma_at(x, idx)
+    assert rel(y[idx], yo) <= 1e-12
+    assert np.abs(y[idx] - yo).max() <= 1e-11 * np.abs(yo).max()
+
+
+# ------------------------------------------------------------------ a6 Davidson
+def test_davidson_fci8_vs_dense():
+    W = wl.make_config("fci8")
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    ev = np.linalg.eigvalsh(S.dense_h())
+    e, rep, st = sbd.davidson(ham, 1, tol_residual=1e-8)
+    assert st == 0 and rep["converged"]
+    assert abs(e[0] - ev[0]) <= 1e-8
+    e4, rep4, st4 = sbd.davidson(ham, 4, tol_residual=1e-8, max_space=24)
+    assert st4 == 0
+    assert np.abs(e4 - ev[:4]).max() <= 1e-8
+
+
+def test_davidson_vectors_are_eigenvectors():
+    W = wl.make_config("fci8")
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    vec = torch.empty(2 * S.N, device=DEV, dtype=torch.float64)
+    e, _, st = sbd.davidson(ham, 2, vectors=vec, tol_residual=1e-9)
+    assert st == 0
+    U = vec.cpu().numpy().reshape(2, S.N)
+    _, Vd = np.linalg.eigh(S.dense_h())
+    for r in range(2):
+        assert abs(np.linalg.norm(U[r]) - 1) < 1e-12
+        assert abs(abs(U[r] @ Vd[:, r]) - 1) < 1e-10
+        res = S.sigma(U[r]) - e[r] * U[r]
+        assert np.linalg.norm(res) <= 1e-8
+
+
+@pytest.mark.parametrize("name,nstr,nroots", [("sel16", 300, 1), ("block20", 200, 4),
+                                              ("sel26", 250, 1)])
+def test_davidson_vs_oracle(name, nstr, nroots):
+    W = wl.make_config(name, nstr=nstr)
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    ro = oracle.davidson(S.sigma, S.diag(), nroots, tol=1e-8, max_space=24)
+    e, rep, st = sbd.davidson(ham, nroots, tol_residual=1e-8, max_space=24)
+    assert st == 0 and ro.converged
+    assert np.abs(e - ro.energies).max() <= 1e-8
+
+
+@pytest.mark.parametrize("nroots", [1, 2])
+def test_davidson_mixed_precision(nroots):
+    W = wl.make_config("sel16", nstr=400)
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    ro = oracle.davidson(S.sigma, S.diag(), nroots, tol=1e-8, max_space=24)
+    e, rep, st = sbd.davidson(ham, nroots, tol_residual=1e-6, sigma_prec=sbd.FP32)
+    assert st == 0 and rep["converged"]
+    assert rep["sigma_calls_fp64"] < rep["sigma_calls"]
+    assert np.abs(e - ro.energies).max() <= 1e-6
+
+
+def test_davidson_full_sel16_residual_by_oracle():
+    """Full-size solve; the oracle checks the returned eigenpair on sampled rows."""
+    W = wl.make_config("sel16")
+    _, _, ham = from_workload(W)
+    vec = torch.empty(W.ndet, device=DEV, dtype=torch.float64)
+    e, rep, st = sbd.davidson(ham, 1, vectors=vec, tol_residual=1e-6)
+    assert st == 0
+    u = vec.cpu().numpy()
+    S = oracle.OracleSystem.from_workload(W)
+    idx = np.argsort(-np.abs(u))[:400]
+    r = S.sigma_at(u, idx) - e[0] * u[idx]
+    assert np.linalg.norm(r) <= 1e-6
+    assert e[0] <= S.diag().min()
+
+
+def test_davidson_single_determinant():
+    norb = 6
+    A = np.array([0b000111], dtype=np.uint64)
+    h, eri, ec = wl.make_integrals(norb, 3)
+    _, _, ham = gpu_system(norb, 3, 3, A, A, h, eri, ec)
+    S = oracle.OracleSystem(norb, A, A, h, eri, ec)
+    e, rep, st = sbd.davidson(ham, 1)
+    assert st == 0 and abs(e[0] - S.diag()[0]) < 1e-12
+
+
+# ------------------------------------------------------------------ errors
+def test_error_paths_on_gpu():
+    W = wl.make_config("fci8")
+    bas, exc, ham = from_workload(W)
+    bad = W.h.copy()
+    bad[0, 1] += 1e-3
+    with pytest.raises(sbd.SBDError) as ei:
+        sbd.Hamiltonian(bas, exc, bad, W.eri, W.e_core)
+    assert ei.value.status == -4
+    eri = W.eri.copy()
+    eri[0, 1, 2, 3] += 1e-3
+    with pytest.raises(sbd.SBDError) as ei:
+        sbd.Hamiltonian(bas, exc, W.h, eri, W.e_core)
+    assert ei.value.status == -4
+    other = sbd.Basis(W.norb, 4, 4, W.alpha[:10], W.beta[:10])
+    other_exc = sbd.Excitations(other)
+    with pytest.raises(sbd.SBDError) as ei:
+        sbd.Hamiltonian(bas, other_exc, W.h, W.eri, W.e_core)
+    assert ei.value.status == -8
+    with pytest.raises(sbd.SBDError) as ei:
+        sbd.davidson(ham, 0)
+    assert ei.value.status == -1
+    x = torch.zeros(W.ndet, device=DEV, dtype=torch.float64)
+    with pytest.raises(sbd.SBDError):
+        sbd.sigma(ham, x, x)
+    with pytest.raises(sbd.SBDError):
+        sbd.sigma(ham, x, torch.empty_like(x), nvec=9, layout=1)
