@@ -138,12 +138,35 @@ void sbd_free_ham(sbd_ham* h);
  *   c and sigma are caller-owned device pointers that must not overlap.
  * Each sigma element is produced by one thread in a fixed order: results are
  * bitwise reproducible run to run.
- * Errors: SBD_ERR_ARG (nvec < 1, nvec > 8 with layout 1, null pointers,
- * bad precision), SBD_ERR_STATE, SBD_ERR_HIP.
+ * A workspace of 2 * N * (layout ? nvec : 1) elements per stream is kept by
+ * the Hamiltonian handle (allocated on first use, freed with the handle).
+ * Errors: SBD_ERR_ARG (nvec < 1, layout 1 with nvec not in {1, 2, 4, 8},
+ * null pointers, c == sigma, bad precision), SBD_ERR_STATE, SBD_ERR_NOMEM,
+ * SBD_ERR_HIP.
  */
 int sbd_sigma(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h,
               int nvec, int prec, double shift,
               const void* c, void* sigma, int layout, void* stream);
+
+/*
+ * Autotuner of the sigma launch configuration (the schedule of the sigma
+ * kernels: rows per wavefront of the same-spin stream kernel, LDS budget of
+ * the alpha-beta kernel).  Times a fixed candidate set on scratch vectors of
+ * this shape (prec, nvec, layout as in sbd_sigma) and stores the fastest in
+ * the Hamiltonian handle for that precision; results are cached per shape for the process, so a
+ * second call on the same shape costs nothing.  best_ms (nullable) receives
+ * the winner's time per sigma, or -1 when taken from the cache.  Must not run
+ * concurrently with other calls on the same handle.  Sigma results do not
+ * depend on the choice beyond floating-point summation order.
+ * Errors: SBD_ERR_ARG, SBD_ERR_STATE, SBD_ERR_NOMEM, SBD_ERR_HIP.
+ */
+int sbd_autotune(const sbd_basis* b, const sbd_exc* e, sbd_ham* h, int prec, int nvec,
+                 int layout, void* stream, double* best_ms);
+/* Read or set the sigma launch configuration of a handle for one precision
+ * (stream_rw in {1, 2}: output rows per wavefront of the stream kernel;
+ * ab_lds_bytes in [4096, 1 MiB], capped at the device's LDS per workgroup). */
+int sbd_get_tune(const sbd_ham* h, int prec, int* stream_rw, int* ab_lds_bytes);
+int sbd_set_tune(sbd_ham* h, int prec, int stream_rw, int ab_lds_bytes);
 
 /* Options of sbd_davidson; sbd_davidson_default_opts fills the defaults. */
 typedef struct {
@@ -153,7 +176,7 @@ typedef struct {
     double precond_delta;  /* delta of the damped denominators (Eq. 7); default 1e-8 Ha            */
     int sigma_prec;        /* SBD_FP64 (plain) or SBD_FP32 (FP32 sigma + FP64 refinement)          */
     int use_graph;         /* reserved (0)                                                          */
-    int use_autotune;      /* reserved (0)                                                          */
+    int use_autotune;      /* 1: run sbd_autotune for the sigma shapes this solve uses             */
     const double* guess;   /* optional device pointer, n_guess x N initial vectors (NULL = none)   */
     int n_guess;
     int verbose;           /* 1: print one line per iteration to stderr                            */

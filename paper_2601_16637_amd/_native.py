@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "SBD_OK", 1: "SBD_NOT_CONVERGED", -1: "SBD_ERR_ARG", -2: "SBD
 EXPORTED = ["sbd_last_error", "sbd_version", "sbd_build_basis", "sbd_basis_sizes",
             "sbd_basis_strings", "sbd_free_basis", "sbd_build_excitations", "sbd_exc_count",
             "sbd_exc_export", "sbd_free_exc", "sbd_set_hamiltonian", "sbd_ham_diag",
-            "sbd_free_ham", "sbd_sigma", "sbd_davidson_default_opts", "sbd_davidson"]
+            "sbd_free_ham", "sbd_sigma", "sbd_autotune", "sbd_get_tune", "sbd_set_tune",
+            "sbd_davidson_default_opts", "sbd_davidson"]
 
 
 class SBDError(RuntimeError):
@@ -96,6 +97,9 @@ def load():
     L.sbd_free_ham.argtypes = [P]
     L.sbd_free_ham.restype = None
     L.sbd_sigma.argtypes = [P, P, P, i32, i32, d, P, P, i32, P]
+    L.sbd_autotune.argtypes = [P, P, P, i32, i32, i32, P, ctypes.POINTER(d)]
+    L.sbd_get_tune.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.sbd_set_tune.argtypes = [P, i32, i32, i32]
     L.sbd_davidson_default_opts.argtypes = [ctypes.POINTER(DavidsonOpts)]
     L.sbd_davidson_default_opts.restype = None
     L.sbd_davidson.argtypes = [P, P, P, i32, ctypes.POINTER(DavidsonOpts), P, P,
@@ -218,6 +222,21 @@ class Hamiltonian:
         check(load().sbd_set_hamiltonian(basis._h, exc._h, _host(h1), _host(eri),
                                          float(e_core), _stream(stream), ctypes.byref(h)))
         self._h = h
+
+    def autotune(self, prec: int = FP64, nvec: int = 1, layout: int = 0, stream=None) -> float:
+        """Pick the fastest sigma launch configuration for this shape (sbd_autotune)."""
+        ms = ctypes.c_double()
+        check(load().sbd_autotune(self.basis._h, self.exc._h, self._h, int(prec), int(nvec),
+                                  int(layout), _stream(stream), ctypes.byref(ms)))
+        return ms.value
+
+    def get_tune(self, prec: int = FP64):
+        rw, lds = ctypes.c_int(), ctypes.c_int()
+        check(load().sbd_get_tune(self._h, int(prec), ctypes.byref(rw), ctypes.byref(lds)))
+        return dict(stream_rw=rw.value, ab_lds_bytes=lds.value)
+
+    def set_tune(self, prec: int = FP64, stream_rw: int = 1, ab_lds_bytes: int = 98304):
+        check(load().sbd_set_tune(self._h, int(prec), int(stream_rw), int(ab_lds_bytes)))
 
     def diag_into(self, out, stream=None):
         check(load().sbd_ham_diag(self._h, _dptr(out), _stream(stream)))

@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <string>
 
 #include "internal.h"
@@ -169,6 +171,10 @@ int sbd_build_excitations(const sbd_basis* b, void* stream, sbd_exc** out) {
                                 t2.row_ptr.as<int64_t>(), t1.J.as<int32_t>(), t1.orb.as<uint32_t>(),
                                 t1.sign.as<int8_t>(), t2.J.as<int32_t>(), t2.orb.as<uint32_t>(),
                                 t2.sign.as<int8_t>(), st);
+        if (e == hipSuccess) e = t1.pack.alloc(sizeof(uint64_t) * (size_t)std::max<int64_t>(t1.nnz, 1));
+        if (e == hipSuccess)
+            e = launch_pack_singles(t1.nnz, t1.J.as<int32_t>(), t1.orb.as<uint32_t>(),
+                                    t1.sign.as<int8_t>(), t1.pack.as<uint64_t>(), st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
             delete x;
@@ -323,11 +329,11 @@ SigmaArgs<double> make_args<double>(const sbd_exc* x, const sbd_ham* H, double s
     SigmaArgs<double> A{};
     A.na = H->na; A.nb = H->nb; A.norb = H->norb;
     const Table *a1 = &x->t[0][0], *a2 = &x->t[0][1], *b1 = &x->t[1][0], *b2 = &x->t[1][1];
-    A.a1p = a1->row_ptr.as<int64_t>(); A.a1J = a1->J.as<int32_t>(); A.a1o = a1->orb.as<uint32_t>();
-    A.a1s = a1->sign.as<int8_t>(); A.a1c = H->sc[0].c1_64.as<double>(); A.a1ps = H->sc[0].ps1.as<int32_t>();
+    A.a1p = a1->row_ptr.as<int64_t>(); A.a1J = a1->J.as<int32_t>(); A.a1pack = a1->pack.as<uint64_t>();
+    A.a1c = H->sc[0].c1_64.as<double>(); A.a1ps = H->sc[0].ps1.as<int32_t>();
     A.a2p = a2->row_ptr.as<int64_t>(); A.a2J = a2->J.as<int32_t>(); A.a2c = H->sc[0].c2_64.as<double>();
-    A.b1p = b1->row_ptr.as<int64_t>(); A.b1J = b1->J.as<int32_t>(); A.b1o = b1->orb.as<uint32_t>();
-    A.b1s = b1->sign.as<int8_t>(); A.b1c = H->sc[1].c1_64.as<double>(); A.b1ps = H->sc[1].ps1.as<int32_t>();
+    A.b1p = b1->row_ptr.as<int64_t>(); A.b1J = b1->J.as<int32_t>(); A.b1pack = b1->pack.as<uint64_t>();
+    A.b1c = H->sc[1].c1_64.as<double>(); A.b1ps = H->sc[1].ps1.as<int32_t>();
     A.b2p = b2->row_ptr.as<int64_t>(); A.b2J = b2->J.as<int32_t>(); A.b2c = H->sc[1].c2_64.as<double>();
     A.Ga = H->sc[0].G64.as<double>(); A.Gb = H->sc[1].G64.as<double>();
     A.eri = H->eri64.as<double>(); A.diag = H->diag.as<double>(); A.shift = shift;
@@ -339,11 +345,11 @@ SigmaArgs<float> make_args<float>(const sbd_exc* x, const sbd_ham* H, double shi
     SigmaArgs<float> A{};
     A.na = H->na; A.nb = H->nb; A.norb = H->norb;
     const Table *a1 = &x->t[0][0], *a2 = &x->t[0][1], *b1 = &x->t[1][0], *b2 = &x->t[1][1];
-    A.a1p = a1->row_ptr.as<int64_t>(); A.a1J = a1->J.as<int32_t>(); A.a1o = a1->orb.as<uint32_t>();
-    A.a1s = a1->sign.as<int8_t>(); A.a1c = H->sc[0].c1_32.as<float>(); A.a1ps = H->sc[0].ps1.as<int32_t>();
+    A.a1p = a1->row_ptr.as<int64_t>(); A.a1J = a1->J.as<int32_t>(); A.a1pack = a1->pack.as<uint64_t>();
+    A.a1c = H->sc[0].c1_32.as<float>(); A.a1ps = H->sc[0].ps1.as<int32_t>();
     A.a2p = a2->row_ptr.as<int64_t>(); A.a2J = a2->J.as<int32_t>(); A.a2c = H->sc[0].c2_32.as<float>();
-    A.b1p = b1->row_ptr.as<int64_t>(); A.b1J = b1->J.as<int32_t>(); A.b1o = b1->orb.as<uint32_t>();
-    A.b1s = b1->sign.as<int8_t>(); A.b1c = H->sc[1].c1_32.as<float>(); A.b1ps = H->sc[1].ps1.as<int32_t>();
+    A.b1p = b1->row_ptr.as<int64_t>(); A.b1J = b1->J.as<int32_t>(); A.b1pack = b1->pack.as<uint64_t>();
+    A.b1c = H->sc[1].c1_32.as<float>(); A.b1ps = H->sc[1].ps1.as<int32_t>();
     A.b2p = b2->row_ptr.as<int64_t>(); A.b2J = b2->J.as<int32_t>(); A.b2c = H->sc[1].c2_32.as<float>();
     A.Ga = H->sc[0].G32.as<float>(); A.Gb = H->sc[1].G32.as<float>();
     A.eri = H->eri32.as<float>(); A.diag = H->diag.as<double>(); A.shift = shift;
@@ -351,14 +357,34 @@ SigmaArgs<float> make_args<float>(const sbd_exc* x, const sbd_ham* H, double shi
 }
 
 int sigma_internal(const sbd_exc* x, const sbd_ham* H, int nvec, int prec, double shift,
-                   const void* c, void* y, int layout, hipStream_t st) {
+                   const void* c, void* y, int layout, void* ws, hipStream_t st) {
     hipError_t e;
+    const SigmaTune tune = H->tune[prec == SBD_FP64 ? 0 : 1];
     if (prec == SBD_FP64)
-        e = launch_sigma<double>(make_args<double>(x, H, shift), nvec, (const double*)c, (double*)y, layout, st);
+        e = launch_sigma<double>(make_args<double>(x, H, shift), nvec, (const double*)c, (double*)y,
+                                 layout, ws, tune, st);
     else
-        e = launch_sigma<float>(make_args<float>(x, H, shift), nvec, (const float*)c, (float*)y, layout, st);
+        e = launch_sigma<float>(make_args<float>(x, H, shift), nvec, (const float*)c, (float*)y,
+                                layout, ws, tune, st);
     if (e != hipSuccess) return hip_fail(e, "sbd_sigma launch");
     return SBD_OK;
+}
+
+// Per-stream sigma workspace owned by the Hamiltonian handle (grown on demand).
+void* ham_workspace(const sbd_ham* Hc, hipStream_t st, size_t bytes, int* rc) {
+    sbd_ham* H = const_cast<sbd_ham*>(Hc);
+    std::lock_guard<std::mutex> g(H->ws_mu);
+    auto& buf = H->ws[st];
+    if (!buf) buf.reset(new DevBuf());
+    if (buf->bytes < bytes) {
+        hipError_t e = buf->alloc(bytes);
+        if (e != hipSuccess) {
+            *rc = hip_fail(e, "sigma workspace");
+            return nullptr;
+        }
+    }
+    *rc = SBD_OK;
+    return buf->p;
 }
 }  // namespace sbd
 
@@ -373,5 +399,12 @@ extern "C" int sbd_sigma(const sbd_basis* b, const sbd_exc* x, const sbd_ham* H,
     if (prec != SBD_FP64 && prec != SBD_FP32) return fail(SBD_ERR_ARG, "bad precision");
     if (!std::isfinite(shift)) return fail(SBD_ERR_ARG, "shift is not finite");
     if (c == sigma) return fail(SBD_ERR_ARG, "c and sigma must not alias");
-    return sigma_internal(x, H, nvec, prec, shift, c, sigma, layout, (hipStream_t)stream);
+    if (layout == 1 && nvec != 1 && nvec != 2 && nvec != 4 && nvec != 8)
+        return fail(SBD_ERR_ARG, "interleaved layout supports nvec in {1, 2, 4, 8}");
+    const int64_t N = H->na * H->nb;
+    int rc = 0;
+    void* ws = ham_workspace(H, (hipStream_t)stream,
+                             sigma_workspace_bytes(N, nvec, layout, prec == SBD_FP64 ? 8 : 4), &rc);
+    if (!ws && N > 0) return rc;
+    return sigma_internal(x, H, nvec, prec, shift, c, sigma, layout, ws, (hipStream_t)stream);
 }

@@ -27,7 +27,7 @@
 namespace sbd {
 
 int sigma_internal(const sbd_exc* x, const sbd_ham* H, int nvec, int prec, double shift,
-                   const void* c, void* y, int layout, hipStream_t st);
+                   const void* c, void* y, int layout, void* ws, hipStream_t st);
 
 // Cyclic Jacobi eigensolver for a symmetric m x m matrix (row-major).  On exit
 // w holds eigenvalues ascending and Z (row-major, column k = eigenvector k).
@@ -92,7 +92,7 @@ static void jacobi_eigh(int m, std::vector<double> A, std::vector<double>& w,
 namespace {
 
 struct Work {
-    DevBuf V, W, tmp, scr, part, small, d_idx, d32a, d32b;
+    DevBuf V, W, tmp, scr, part, small, d_idx, d32a, d32b, sws;
 };
 
 using clk = std::chrono::steady_clock;
@@ -148,12 +148,19 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     const int keep = std::max(k, std::min(2 * k, ms - k));
     const bool mixed = (o.sigma_prec == SBD_FP32);
     hipStream_t st = (hipStream_t)stream;
+    if (o.use_autotune) {
+        // launch configuration only: sigma values do not depend on it beyond rounding order
+        int rc = sbd_autotune(b, x, const_cast<sbd_ham*>(H), SBD_FP64, 1, 0, stream, nullptr);
+        if (!rc && mixed) rc = sbd_autotune(b, x, const_cast<sbd_ham*>(H), SBD_FP32, 1, 0, stream, nullptr);
+        if (rc) return rc;
+    }
 
     Work w;
     hipError_t e = w.V.alloc(sizeof(double) * (size_t)ms * N);
     if (e == hipSuccess) e = w.W.alloc(sizeof(double) * (size_t)ms * N);
     if (e == hipSuccess) e = w.tmp.alloc(sizeof(double) * (size_t)std::max(k, keep) * N);
     if (e == hipSuccess) e = w.scr.alloc(sizeof(double) * (size_t)keep * N);
+    if (e == hipSuccess) e = w.sws.alloc(sigma_workspace_bytes(N, 1, 0, sizeof(double)));
     if (e == hipSuccess) e = w.part.alloc(sizeof(double) * 16 * kRedBlocks);
     if (e == hipSuccess) e = w.small.alloc(sizeof(double) * 64 * 16);
     if (e == hipSuccess) e = w.d_idx.alloc(sizeof(int64_t) * (kRedBlocks + 1));
@@ -199,14 +206,15 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         auto t0 = clk::now();
         int rc;
         if (!mixed || fp64) {
-            rc = sigma_internal(x, H, cnt, SBD_FP64, 0.0, V + (size_t)j0 * N, W + (size_t)j0 * N, 0, st);
+            rc = sigma_internal(x, H, cnt, SBD_FP64, 0.0, V + (size_t)j0 * N, W + (size_t)j0 * N, 0,
+                                w.sws.p, st);
             sigma64 += cnt;
         } else {
             float* x32 = w.d32a.as<float>();
             float* y32 = w.d32b.as<float>();
             hipError_t ee = launch_f64_to_f32(V + (size_t)j0 * N, x32, (int64_t)cnt * N, st);
             if (ee != hipSuccess) return hip_fail(ee, "to f32");
-            rc = sigma_internal(x, H, cnt, SBD_FP32, shift, x32, y32, 0, st);
+            rc = sigma_internal(x, H, cnt, SBD_FP32, shift, x32, y32, 0, w.sws.p, st);
             if (rc) return rc;
             ee = launch_f32_to_f64_axpy(y32, V + (size_t)j0 * N, shift, W + (size_t)j0 * N,
                                         (int64_t)cnt * N, st);

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -69,6 +72,7 @@ struct Table {
     DevBuf J;        // int32[nnz]
     DevBuf orb;      // uint32[nnz]: i | j<<8 | a<<16 | b<<24 (double); i | a<<8 (single)
     DevBuf sign;     // int8[nnz]
+    DevBuf pack;     // singles only: uint64 J | i << 32 | a << 40 | (sign < 0) << 48
 };
 }  // namespace sbd
 
@@ -82,6 +86,14 @@ struct sbd_exc {
 namespace sbd {
 // Hamiltonian data per spin: coefficients per table entry and the spectator
 // table G[pair(a,i)][string] = sum_{k in string} (ai|kk).
+// Launch parameters of the sigma kernels (picked per shape by the autotuner).
+struct SigmaTune {
+    int ab_threads = 1024;       // threads per alpha-beta workgroup
+    int ab_lds_bytes = 98304;    // LDS budget for the staged row of the alpha-beta kernel
+    int stream_rows = 4;         // wavefronts per stream workgroup
+    int stream_rw = 1;           // output rows per stream wavefront (1 or 2)
+};
+
 struct SpinCoef {
     DevBuf c1_64, c1_32;  // single base coefficient s*(h_ai + sum_{k in J} ((ai|kk)-(ak|ki)))
     DevBuf ps1;           // int32 per single: pair(a,i) << 1 | (sign < 0)
@@ -93,6 +105,7 @@ struct SpinCoef {
 
 struct sbd_ham {
     uint64_t basis_id = 0, exc_id = 0;
+    sbd::SigmaTune tune[2];         // sigma launch configuration per precision
     int norb = 0;
     int64_t na = 0, nb = 0;
     double e_core = 0.0;
@@ -100,6 +113,8 @@ struct sbd_ham {
     sbd::DevBuf h64, eri64, eri32;  // integrals on device
     sbd::SpinCoef sc[2];
     sbd::DevBuf diag;               // double[N]
+    std::mutex ws_mu;               // per-stream sigma workspaces of sbd_sigma
+    std::map<hipStream_t, std::unique_ptr<sbd::DevBuf>> ws;
 };
 
 namespace sbd {
@@ -126,6 +141,8 @@ hipError_t launch_exclusive_scan(const int64_t* d_in, int64_t n, int64_t* d_out 
 hipError_t launch_exc_fill(const uint64_t* d_s, int64_t n, const int64_t* rp1, const int64_t* rp2,
                            int32_t* J1, uint32_t* orb1, int8_t* sg1, int32_t* J2, uint32_t* orb2,
                            int8_t* sg2, hipStream_t st);
+hipError_t launch_pack_singles(int64_t nnz, const int32_t* J, const uint32_t* orb, const int8_t* sg,
+                               uint64_t* pack, hipStream_t st);
 
 // Hamiltonian pieces.
 hipError_t launch_string_diag(const uint64_t* d_s, int64_t n, int norb, const double* h,
@@ -149,12 +166,12 @@ struct SigmaArgs {
     int64_t na, nb;
     int norb;
     // alpha tables
-    const int64_t* a1p; const int32_t* a1J; const uint32_t* a1o; const int8_t* a1s;
-    const T* a1c; const int32_t* a1ps;
+    const int64_t* a1p; const int32_t* a1J; const T* a1c; const int32_t* a1ps;
+    const uint64_t* a1pack;
     const int64_t* a2p; const int32_t* a2J; const T* a2c;
     // beta tables
-    const int64_t* b1p; const int32_t* b1J; const uint32_t* b1o; const int8_t* b1s;
-    const T* b1c; const int32_t* b1ps;
+    const int64_t* b1p; const int32_t* b1J; const T* b1c; const int32_t* b1ps;
+    const uint64_t* b1pack;
     const int64_t* b2p; const int32_t* b2J; const T* b2c;
     const T* Ga;   // [npair][na]  sum_{k in alpha(ia)} (pair|kk)
     const T* Gb;   // [npair][nb]
@@ -162,9 +179,13 @@ struct SigmaArgs {
     const double* diag;
     double shift;
 };
+
+// Workspace bytes needed by launch_sigma for nvec vectors of type T.
+size_t sigma_workspace_bytes(int64_t N, int nvec, int layout, size_t elem);
+
 template <class T>
-hipError_t launch_sigma(const SigmaArgs<T>& A, int nvec, const T* c, T* y, int layout,
-                        hipStream_t st);
+hipError_t launch_sigma(const SigmaArgs<T>& A, int nvec, const T* c, T* y, int layout, void* ws,
+                        const SigmaTune& tune, hipStream_t st);
 
 // Dense vector kernels for Davidson (FP64 unless noted).  Vectors are rows
 // of length N stored contiguously: A + j*N.

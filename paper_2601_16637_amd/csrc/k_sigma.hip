@@ -1,137 +1,547 @@
 // Matrix-free sigma = (H - shift) c over the alpha x beta determinant basis
 // (Eq. 4; the three task types of Sec. III-B).
 //
-// Owner computes: the thread that owns output element (ia, ib) accumulates
-// every contribution to it in registers, in a fixed order, and stores it
-// once.  No atomics, so results are bitwise reproducible (the paper resolves
-// write races with atomicAdd instead).
+// Vectors are stored alpha-major, c[ia][ib] (index ia*nb + ib), optionally
+// with nv vectors interleaved per determinant ([ia][ib][v]).  One sigma is
+// five launches on one stream:
 //
-//   diag     : (H_ii - shift) c[ia, ib]
-//   task 2   : alpha singles/doubles  sum_{Ja} coef * c[Ja, ib]   (row stream,
-//              consecutive ib are consecutive addresses -> coalesced)
-//   task 1   : beta singles/doubles   sum_{Jb} coef * c[ia, Jb]   (gather in row ia)
-//   task 0   : alpha single x beta single  sa sb (ai|bj) c[Ja, Jb]
+//   1. transpose   cT[ib][ia] = c[ia][ib]                         (LDS tiles)
+//   2. stream      y[ia][:]  = (H_diag - shift) c[ia][:]
+//                            + sum_{Ja in S1/S2 alpha(ia)} coef * c[Ja][:]   (task 2)
+//   3. stream      yT[ib][:] = sum_{Jb in S1/S2 beta(ib)} coef * cT[Jb][:]   (task 1)
+//   4. alpha-beta  y[ia][ib] += sum_{Ja in S1a(ia)} sum_{Jb in S1b(ib)}
+//                              sa sb (a_a i_a | b_b j_b) c[Ja][Jb]         (task 0)
+//   5. transpose   y[ia][ib] += yT[ib][ia]                          (LDS tiles)
 //
-// Single coefficients add the spectator term of the other spin read from
-// G[pair][string]; the rest of each coefficient is per table entry.
+// The same-spin work (tasks 1 and 2, about 65-95 % of all connected pairs)
+// thus becomes a row stream: one wavefront owns one output row and one
+// 64-column tile, walks the row's excitation list with wave-uniform (scalar)
+// loads of the ket index and coefficient, and reads the ket row segment with
+// one coalesced load per entry.  Tiles are assigned so that the workgroups
+// resident on one XCD share a column tile, keeping in[:, tile] in that XCD's
+// L2.  The alpha-beta term stages the ket row c[Ja][:] and the integral slice
+// (a_a i_a | . .) in LDS and gathers from there.
+//
+// Every output element is written by one owner in a fixed order: no atomics,
+// results are bitwise reproducible.
 #include "internal.h"
 
 namespace sbd {
 namespace {
 
-constexpr int kSigBlock = 256;
-
-template <class T, int NV>
-__global__ void __launch_bounds__(kSigBlock) k_sigma_rows(SigmaArgs<T> A, const T* __restrict__ c,
-                                                          T* __restrict__ y) {
-    const int64_t nb = A.nb, na = A.na;
-    const int n = A.norb;
-    int64_t ib = (int64_t)blockIdx.x * kSigBlock + threadIdx.x;
-    if (ib >= nb) return;
-    for (int64_t ia = blockIdx.y; ia < na; ia += gridDim.y) {
-        const int64_t det = ia * nb + ib;
-        T acc[NV];
-        const T dg = (T)(A.diag[det] - A.shift);
+// ------------------------------------------------------------------ transpose
+template <class T, int NV, bool ADD>
+__global__ void __launch_bounds__(256) k_transpose(const T* __restrict__ in, T* __restrict__ out,
+                                                   int64_t nrow, int64_t ncol, int64_t nby) {
+    constexpr int TD = 32;
+    __shared__ T tile[TD][TD * NV + 1];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    const int64_t c0 = (int64_t)blockIdx.x * TD;
+    for (int64_t by = blockIdx.y; by < nby; by += gridDim.y) {
+        const int64_t r0 = by * TD;
+        __syncthreads();
+        for (int j = ty; j < TD; j += 8) {
+            const int64_t r = r0 + j, c = c0 + tx;
+            if (r < nrow && c < ncol) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = dg * c[det * NV + v];
-
-        // task 2: alpha singles (coefficient depends on beta string ib)
-        for (int64_t e = A.a1p[ia]; e < A.a1p[ia + 1]; ++e) {
-            const int64_t ja = A.a1J[e];
-            const int ps = A.a1ps[e];
-            const T g = A.Gb[(int64_t)(ps >> 1) * nb + ib];
-            const T coef = A.a1c[e] + ((ps & 1) ? -g : g);
-            const T* src = c + (ja * nb + ib) * NV;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] += coef * src[v];
-        }
-        // task 2: alpha doubles
-        for (int64_t e = A.a2p[ia]; e < A.a2p[ia + 1]; ++e) {
-            const int64_t ja = A.a2J[e];
-            const T coef = A.a2c[e];
-            const T* src = c + (ja * nb + ib) * NV;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] += coef * src[v];
-        }
-        // task 1: beta singles (coefficient depends on alpha string ia)
-        for (int64_t e = A.b1p[ib]; e < A.b1p[ib + 1]; ++e) {
-            const int64_t jb = A.b1J[e];
-            const int ps = A.b1ps[e];
-            const T g = A.Ga[(int64_t)(ps >> 1) * na + ia];
-            const T coef = A.b1c[e] + ((ps & 1) ? -g : g);
-            const T* src = c + (ia * nb + jb) * NV;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] += coef * src[v];
-        }
-        // task 1: beta doubles
-        for (int64_t e = A.b2p[ib]; e < A.b2p[ib + 1]; ++e) {
-            const int64_t jb = A.b2J[e];
-            const T coef = A.b2c[e];
-            const T* src = c + (ia * nb + jb) * NV;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] += coef * src[v];
-        }
-        // task 0: alpha single x beta single
-        for (int64_t ea = A.a1p[ia]; ea < A.a1p[ia + 1]; ++ea) {
-            const int64_t ja = A.a1J[ea];
-            const uint32_t oa = A.a1o[ea];
-            const int ai = oa & 255, aa = (oa >> 8) & 255;
-            const T* slice = A.eri + ((size_t)aa * n + ai) * n * n;  // (a_a i_a | . .)
-            const int sa = A.a1s[ea];
-            for (int64_t eb = A.b1p[ib]; eb < A.b1p[ib + 1]; ++eb) {
-                const int64_t jb = A.b1J[eb];
-                const uint32_t ob = A.b1o[eb];
-                const int bi = ob & 255, ba = (ob >> 8) & 255;
-                const T g = slice[ba * n + bi];
-                const T coef = (sa * A.b1s[eb] < 0) ? -g : g;
-                const T* src = c + (ja * nb + jb) * NV;
-#pragma unroll
-                for (int v = 0; v < NV; ++v) acc[v] += coef * src[v];
+                for (int v = 0; v < NV; ++v) tile[j][tx * NV + v] = in[(r * ncol + c) * NV + v];
             }
         }
+        __syncthreads();
+        for (int j = ty; j < TD; j += 8) {
+            const int64_t c = c0 + j, r = r0 + tx;
+            if (c < ncol && r < nrow) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) y[det * NV + v] = acc[v];
+                for (int v = 0; v < NV; ++v) {
+                    const T val = tile[tx][j * NV + v];
+                    T* dst = out + (c * nrow + r) * NV + v;
+                    if (ADD)
+                        *dst += val;
+                    else
+                        *dst = val;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ row stream
+template <class T>
+struct StreamArgs {
+    int64_t nrow, ncol;
+    int64_t ntiles, row_blocks;
+    int rows_per_wg;
+    const int64_t* p1; const int32_t* J1; const T* c1; const int32_t* ps1;
+    const int64_t* p2; const int32_t* J2; const T* c2;
+    const T* G;           // [npair][ncol]: spectator of the column spin
+    const double* diag;   // [nrow][ncol] or null
+    double shift;
+};
+
+// Broadcast lane k's value of v to the whole wavefront (k wave-uniform).
+__device__ __forceinline__ int bcast(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+__device__ __forceinline__ float bcast(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ double bcast(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Load W = VEC*NV consecutive values (vectorised when aligned by construction).
+template <class T, int W>
+struct Vec {
+    T x[W];
+};
+template <class T, int W>
+__device__ __forceinline__ Vec<T, W> vload(const T* p) {
+    Vec<T, W> v;
+    if constexpr (W * sizeof(T) == 16) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        __builtin_memcpy(&v, &q, 16);
+    } else if constexpr (W * sizeof(T) == 8) {
+        const float2 q = *reinterpret_cast<const float2*>(p);
+        __builtin_memcpy(&v, &q, 8);
+    } else {
+#pragma unroll
+        for (int i = 0; i < W; ++i) v.x[i] = p[i];
+    }
+    return v;
+}
+
+// One wavefront = RW output rows (RW = 1 or 2) and VEC*64/RW consecutive
+// columns: with RW = 2 each half-wave owns one row, which halves the column
+// tile (and so the per-XCD working set in[:, tile]) at the same bytes per load
+// instruction.  Each row's entry list is fetched with one vector load per 64/RW
+// entries and broadcast lane by lane (v_readlane), so ket-row loads never wait
+// on scalar memory; four ket rows are in flight per step.
+template <class T, int NV, int VEC, int RW>
+__global__ void __launch_bounds__(256) k_stream(StreamArgs<T> A, const T* __restrict__ in,
+                                                T* __restrict__ out) {
+    constexpr int W = NV * VEC;
+    constexpr int HL = 64 / RW;  // lanes per row
+    const int lane = threadIdx.x & 63;
+    const int half = RW == 2 ? (lane >> 5) : 0;
+    const int hl = lane & (HL - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // workgroups are dispatched round-robin over the 8 XCDs: give each XCD its
+    // own sequence of column tiles so its resident waves share one tile
+    const int64_t g = blockIdx.x;
+    const int xcd = (int)(g & 7);
+    const int64_t l = g >> 3;
+    const int64_t tl = l / A.row_blocks;
+    const int64_t rb = l - tl * A.row_blocks;
+    const int64_t tile = tl * 8 + xcd;
+    const int64_t rwave = (rb * A.rows_per_wg + wv) * RW;  // first row of this wave
+    if (tile >= A.ntiles || rwave >= A.nrow || wv >= A.rows_per_wg) return;
+    const int64_t r = rwave + half;
+    const bool rok = r < A.nrow;
+    const int64_t rr = rok ? r : rwave;
+    const int64_t ncol = A.ncol;
+    const int64_t col = (tile * HL + hl) * VEC;   // first of VEC columns (ncol % VEC == 0)
+    const bool act = rok && col < ncol;
+    const int64_t cc = col < ncol ? col : 0;
+
+    T acc[W];
+    if (A.diag) {
+        const Vec<T, W> x = vload<T, W>(in + (rr * ncol + cc) * NV);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+            const T dg = (T)(A.diag[rr * ncol + cc + q] - A.shift);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[q * NV + v] = dg * x.x[q * NV + v];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < W; ++i) acc[i] = T(0);
+    }
+    // entry ranges of the wave's rows (uniform per half)
+    const int64_t r0 = rwave, r1 = (RW == 2 && rwave + 1 < A.nrow) ? rwave + 1 : rwave;
+    // singles: coefficient = base + sign * G[pair][col]
+    {
+        const int64_t a0 = A.p1[r0], a1 = A.p1[r0 + 1];
+        const int64_t b0 = A.p1[r1], b1 = (RW == 2 && r1 != r0) ? A.p1[r1 + 1] : b0;
+        const int64_t my0 = half ? b0 : a0, my1 = half ? b1 : a1;
+        const int64_t n0 = a1 - a0, n1 = b1 - b0;
+        const int64_t nmax = n0 > n1 ? n0 : n1;
+        for (int64_t base = 0; base < nmax; base += HL) {
+            const int64_t mine = my1 - my0 - base;
+            const int cnt = (int)(mine < HL ? (mine < 0 ? 0 : mine) : HL);
+            const int mj = hl < cnt ? A.J1[my0 + base + hl] : 0;
+            const int mp = hl < cnt ? A.ps1[my0 + base + hl] : 0;
+            const T mc = hl < cnt ? A.c1[my0 + base + hl] : T(0);
+            const int64_t lim = (nmax - base) < HL ? (nmax - base) : HL;
+            for (int k = 0; k < lim; ++k) {
+                int j = bcast(mj, k), ps = bcast(mp, k);
+                T cb = bcast(mc, k);
+                if (RW == 2) {
+                    const int j2 = bcast(mj, k + 32), p2 = bcast(mp, k + 32);
+                    const T c2 = bcast(mc, k + 32);
+                    j = half ? j2 : j;
+                    ps = half ? p2 : ps;
+                    cb = half ? c2 : cb;
+                }
+                if (k < cnt) {
+                    const Vec<T, VEC> gv = vload<T, VEC>(A.G + (int64_t)(ps >> 1) * ncol + cc);
+                    const Vec<T, W> x = vload<T, W>(in + ((int64_t)j * ncol + cc) * NV);
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) {
+                        const T coef = cb + ((ps & 1) ? -gv.x[q] : gv.x[q]);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) acc[q * NV + v] += coef * x.x[q * NV + v];
+                    }
+                }
+            }
+        }
+    }
+    // doubles: coefficient per entry; four ket rows in flight
+    {
+        const int64_t a0 = A.p2[r0], a1 = A.p2[r0 + 1];
+        const int64_t b0 = A.p2[r1], b1 = (RW == 2 && r1 != r0) ? A.p2[r1 + 1] : b0;
+        const int64_t my0 = half ? b0 : a0, my1 = half ? b1 : a1;
+        const int64_t n0 = a1 - a0, n1 = b1 - b0;
+        const int64_t nmax = n0 > n1 ? n0 : n1;
+        for (int64_t base = 0; base < nmax; base += HL) {
+            const int64_t mine = my1 - my0 - base;
+            const int cnt = (int)(mine < HL ? (mine < 0 ? 0 : mine) : HL);
+            const int mj = hl < cnt ? A.J2[my0 + base + hl] : 0;
+            const T mc = hl < cnt ? A.c2[my0 + base + hl] : T(0);
+            const int lim = (int)((nmax - base) < HL ? (nmax - base) : HL);
+            for (int k = 0; k < lim; k += 4) {
+                int j[4];
+                T f[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int kk = (k + u) < HL ? (k + u) : (HL - 1);
+                    int jv = bcast(mj, kk);
+                    T fv = bcast(mc, kk);
+                    if (RW == 2) {
+                        const int j2 = bcast(mj, kk + 32);
+                        const T f2 = bcast(mc, kk + 32);
+                        jv = half ? j2 : jv;
+                        fv = half ? f2 : fv;
+                    }
+                    const bool ok = (k + u) < cnt;
+                    j[u] = ok ? jv : (int)rr;   // padded entries read a valid row with weight 0
+                    f[u] = ok ? fv : T(0);
+                }
+                Vec<T, W> x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x[u] = vload<T, W>(in + ((int64_t)j[u] * ncol + cc) * NV);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int i = 0; i < W; ++i) acc[i] += f[u] * x[u].x[i];
+            }
+        }
+    }
+    if (act) {
+        T* dst = out + (r * ncol + col) * NV;
+#pragma unroll
+        for (int i = 0; i < W; ++i) dst[i] = acc[i];
+    }
+}
+
+// ------------------------------------------------------------------ alpha-beta
+template <class T>
+struct AbArgs {
+    int64_t na, nb;
+    int norb;
+    int64_t win;        // ket-row window staged in LDS (determinants)
+    int krows;          // alpha singles (ket rows) staged together
+    const int64_t* a1p; const uint64_t* a1pack;
+    const int64_t* b1p; const uint64_t* b1pack;
+    const T* eri;
+};
+
+// Copy n elements global -> LDS with 16-byte loads for the aligned body
+// (scalar head and tail, so nothing outside [src, src+n) is read).
+template <class T>
+__device__ __forceinline__ void stage_row(T* __restrict__ dst, const T* __restrict__ src, int64_t n) {
+    constexpr int E = 16 / sizeof(T);
+    const int bd = blockDim.x, tid = threadIdx.x;
+    int64_t head = (int64_t)(((16 - ((uintptr_t)src & 15)) & 15) / sizeof(T));
+    if (head > n) head = n;
+    for (int64_t k = tid; k < head; k += bd) dst[k] = src[k];
+    const int64_t nv = (n - head) / E;
+    const float4* s4 = reinterpret_cast<const float4*>(src + head);
+    T* d = dst + head;
+#pragma unroll 4
+    for (int64_t k = tid; k < nv; k += bd) {
+        const float4 q = s4[k];
+        T tmp[E];
+        __builtin_memcpy(tmp, &q, 16);
+#pragma unroll
+        for (int i = 0; i < E; ++i) d[k * E + i] = tmp[i];
+    }
+    for (int64_t k = head + nv * E + tid; k < n; k += bd) dst[k] = src[k];
+}
+
+// One workgroup = one bra row ia and a block of Q*blockDim columns.  The
+// alpha singles (Ja, i_a -> a_a) of ia are taken K at a time: their ket rows
+// c[Ja][:] (or a window of them) and integral slices (a_a i_a | . .) are staged
+// in LDS, then each thread walks the beta singles of its Q columns.  Each
+// beta-single entry is loaded once per group of K rows, and the entries of the
+// Q columns are fetched step by step so their loads are independent.
+template <class T, int NV, int Q>
+__global__ void __launch_bounds__(1024) k_ab(AbArgs<T> A, const T* __restrict__ c,
+                                             T* __restrict__ y) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = A.norb;
+    const int sl_stride = (n * n + 3) & ~3;
+    const int K = A.krows;
+    T* slices = reinterpret_cast<T*>(smem);
+    T* rows = slices + (size_t)K * sl_stride;
+    const int64_t row_stride = A.win * NV;
+    const int64_t ia = blockIdx.x;
+    const int64_t nb = A.nb;
+    const int64_t col0 = (int64_t)blockIdx.y * blockDim.x * Q + threadIdx.x;
+    const int64_t t0 = A.a1p[ia], t1 = A.a1p[ia + 1];
+    if (t0 == t1) return;  // no alpha single: nothing to add (uniform exit)
+
+    T acc[Q][NV];
+    int u0[Q], len[Q];
+    int maxlen = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t ib = col0 + (int64_t)q * blockDim.x;
+        u0[q] = (ib < nb) ? (int)A.b1p[ib] : 0;
+        len[q] = (ib < nb) ? (int)(A.b1p[ib + 1] - A.b1p[ib]) : 0;
+        maxlen = len[q] > maxlen ? len[q] : maxlen;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[q][v] = T(0);
+    }
+    for (int64_t tg = t0; tg < t1; tg += K) {
+        const int kk = (int)((t1 - tg) < K ? (t1 - tg) : K);
+        int sa_bits = 0;
+        for (int tt = 0; tt < kk; ++tt) sa_bits |= (int)((A.a1pack[tg + tt] >> 48) & 1) << tt;
+        for (int64_t w0 = 0; w0 < nb; w0 += A.win) {
+            const int64_t wl = (nb - w0) < A.win ? (nb - w0) : A.win;
+            __syncthreads();
+            for (int tt = 0; tt < kk; ++tt) {
+                const uint64_t pa = A.a1pack[tg + tt];
+                const int64_t ja = (int64_t)(pa & 0xffffffffull);
+                if (w0 == 0) {
+                    const int ai = (int)((pa >> 32) & 255), aa = (int)((pa >> 40) & 255);
+                    const T* sl = A.eri + ((size_t)aa * n + ai) * n * n;  // (a_a i_a | . .)
+                    for (int k = threadIdx.x; k < n * n; k += blockDim.x)
+                        slices[tt * sl_stride + k] = sl[k];
+                }
+                stage_row<T>(rows + tt * row_stride, c + (ja * nb + w0) * NV, wl * NV);
+            }
+            __syncthreads();
+            for (int s = 0; s < maxlen; ++s) {
+                uint64_t pb[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) pb[q] = (s < len[q]) ? A.b1pack[u0[q] + s] : ~0ull;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    if (pb[q] == ~0ull) continue;
+                    const int64_t jb = (int64_t)(pb[q] & 0xffffffffull) - w0;
+                    if (jb < 0 || jb >= wl) continue;
+                    const int gidx = (int)((pb[q] >> 40) & 255) * n + (int)((pb[q] >> 32) & 255);
+                    const int sb = (int)((pb[q] >> 48) & 1);
+                    for (int tt = 0; tt < kk; ++tt) {
+                        const T gv = slices[tt * sl_stride + gidx];
+                        const T coef = (((sa_bits >> tt) & 1) ^ sb) ? -gv : gv;
+                        const T* x = rows + tt * row_stride + jb * NV;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) acc[q][v] += coef * x[v];
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t ib = col0 + (int64_t)q * blockDim.x;
+        if (ib < nb) {
+            T* dst = y + (ia * nb + ib) * NV;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) dst[v] += acc[q][v];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+template <class T, int NV, bool ADD>
+hipError_t transpose(const T* in, T* out, int64_t nrow, int64_t ncol, hipStream_t st) {
+    const int64_t nbx = (ncol + 31) / 32, nby = (nrow + 31) / 32;
+    const unsigned gy = (unsigned)(nby < 65535 ? nby : 65535);
+    hipLaunchKernelGGL((k_transpose<T, NV, ADD>), dim3((unsigned)nbx, gy), dim3(256), 0, st, in,
+                       out, nrow, ncol, nby);
+    return hipGetLastError();
+}
+
+template <class T, int NV, int VEC, int RW>
+hipError_t stream_vec(StreamArgs<T> S, const T* in, T* out, int rows_per_wg, hipStream_t st) {
+    S.rows_per_wg = rows_per_wg;
+    S.ntiles = (S.ncol + (64 / RW) * VEC - 1) / ((64 / RW) * VEC);
+    const int64_t rows_per_block = (int64_t)rows_per_wg * RW;
+    S.row_blocks = (S.nrow + rows_per_block - 1) / rows_per_block;
+    const int64_t tiles8 = (S.ntiles + 7) / 8 * 8;
+    const int64_t nblk = tiles8 * S.row_blocks;
+    if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_stream<T, NV, VEC, RW>), dim3((unsigned)nblk), dim3(64 * rows_per_wg), 0,
+                       st, S, in, out);
+    return hipGetLastError();
+}
+
+// Columns per lane: wide enough for 8-byte lane loads of FP32 single vectors
+// when every row starts on a multiple of VEC columns; RW rows per wavefront.
+template <class T, int NV>
+hipError_t stream(StreamArgs<T> S, const T* in, T* out, const SigmaTune& tune, hipStream_t st) {
+    constexpr int want = (NV * sizeof(T) >= 8) ? 1 : 2;
+    const bool vec2 = want == 2 && S.ncol % 2 == 0;
+    const int rows = tune.stream_rows;
+    if (tune.stream_rw == 2) {
+        if (vec2) return stream_vec<T, NV, (want == 2 ? 2 : 1), 2>(S, in, out, rows, st);
+        return stream_vec<T, NV, 1, 2>(S, in, out, rows, st);
+    }
+    if (vec2) return stream_vec<T, NV, (want == 2 ? 2 : 1), 1>(S, in, out, rows, st);
+    return stream_vec<T, NV, 1, 1>(S, in, out, rows, st);
+}
+
+int max_lds_per_block() {
+    static int v = -1;
+    if (v < 0) {
+        int dev = 0, x = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            x = 65536;
+        v = x;
+    }
+    return v;
+}
+
+template <class T, int NV, int Q>
+hipError_t ab_launch(const AbArgs<T>& A, const T* c, T* y, int threads, size_t lds, int64_t passes,
+                     hipStream_t st) {
+    auto kern = k_ab<T, NV, Q>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)A.na, (unsigned)passes), dim3(threads), lds, st, A, c,
+                       y);
+    return hipGetLastError();
+}
+
+// Largest columns-per-thread of the alpha-beta kernel that keeps the
+// accumulators and entry bounds within 64 VGPRs (1024-thread workgroups allow 128).
+template <class T, int NV>
+constexpr int ab_qmax() {
+    constexpr int per_q = NV * (int)sizeof(T) / 4 + 4;
+    constexpr int q = 48 / per_q;
+    return q >= 8 ? 8 : (q >= 6 ? 6 : (q >= 4 ? 4 : (q >= 2 ? 2 : 1)));
+}
+
+template <class T, int NV>
+hipError_t alpha_beta(AbArgs<T> A, const T* c, T* y, const SigmaTune& tune, hipStream_t st) {
+    if (A.na > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int threads = A.nb > 512 ? 1024 : (A.nb > 256 ? 512 : 256);
+    constexpr int QM = ab_qmax<T, NV>();
+    // column passes (each restages the ket rows), columns spread evenly over them
+    const int64_t passes = (A.nb + (int64_t)threads * QM - 1) / ((int64_t)threads * QM);
+    const int64_t per = (A.nb + passes * threads - 1) / (passes * threads);  // columns per thread
+    constexpr int steps[5] = {1, 2, 4, 6, 8};
+    int Q = 1;
+    for (int s : steps)
+        if (s <= QM) {
+            Q = s;
+            if (s >= per) break;
+        }
+    const size_t slice_bytes = (size_t)((A.norb * A.norb + 3) & ~3) * sizeof(T);
+    size_t budget = (size_t)tune.ab_lds_bytes;
+    const size_t hw = (size_t)max_lds_per_block();
+    if (budget > hw) budget = hw;
+    const size_t row_bytes = (size_t)A.nb * NV * sizeof(T);
+    int64_t K = (int64_t)(budget / (slice_bytes + row_bytes));
+    if (K > 8) K = 8;
+    if (K >= 1) {
+        A.krows = (int)K;  // whole ket rows, K at a time
+        A.win = A.nb;
+    } else {
+        A.krows = 1;       // one ket row, staged in windows
+        if (budget < slice_bytes + 64 * NV * sizeof(T)) budget = slice_bytes + 64 * NV * sizeof(T);
+        int64_t win = (int64_t)((budget - slice_bytes) / (NV * sizeof(T)));
+        A.win = win > A.nb ? A.nb : win;
+    }
+    const size_t lds = (size_t)A.krows * (slice_bytes + (size_t)A.win * NV * sizeof(T));
+    switch (Q) {
+        case 1: return ab_launch<T, NV, 1>(A, c, y, threads, lds, passes, st);
+        case 2: return ab_launch<T, NV, (QM < 2 ? QM : 2)>(A, c, y, threads, lds, passes, st);
+        case 4: return ab_launch<T, NV, (QM < 4 ? QM : 4)>(A, c, y, threads, lds, passes, st);
+        case 6: return ab_launch<T, NV, (QM < 6 ? QM : 6)>(A, c, y, threads, lds, passes, st);
+        default: return ab_launch<T, NV, QM>(A, c, y, threads, lds, passes, st);
     }
 }
 
 template <class T, int NV>
-hipError_t launch_rows(const SigmaArgs<T>& A, const T* c, T* y, hipStream_t st) {
-    unsigned gx = (unsigned)((A.nb + kSigBlock - 1) / kSigBlock);
-    unsigned gy = (unsigned)(A.na < 65535 ? A.na : 65535);
-    hipLaunchKernelGGL((k_sigma_rows<T, NV>), dim3(gx, gy), dim3(kSigBlock), 0, st, A, c, y);
-    return hipGetLastError();
+hipError_t sigma_nv(const SigmaArgs<T>& A, const T* c, T* y, T* cT, T* yT, const SigmaTune& tune,
+                    hipStream_t st) {
+    const int64_t na = A.na, nb = A.nb;
+    hipError_t e = transpose<T, NV, false>(c, cT, na, nb, st);
+    if (e != hipSuccess) return e;
+    StreamArgs<T> Sa{};
+    Sa.nrow = na; Sa.ncol = nb;
+    Sa.p1 = A.a1p; Sa.J1 = A.a1J; Sa.c1 = A.a1c; Sa.ps1 = A.a1ps;
+    Sa.p2 = A.a2p; Sa.J2 = A.a2J; Sa.c2 = A.a2c;
+    Sa.G = A.Gb; Sa.diag = A.diag; Sa.shift = A.shift;
+    e = stream<T, NV>(Sa, c, y, tune, st);
+    if (e != hipSuccess) return e;
+    StreamArgs<T> Sb{};
+    Sb.nrow = nb; Sb.ncol = na;
+    Sb.p1 = A.b1p; Sb.J1 = A.b1J; Sb.c1 = A.b1c; Sb.ps1 = A.b1ps;
+    Sb.p2 = A.b2p; Sb.J2 = A.b2J; Sb.c2 = A.b2c;
+    Sb.G = A.Ga; Sb.diag = nullptr; Sb.shift = 0.0;
+    e = stream<T, NV>(Sb, cT, yT, tune, st);
+    if (e != hipSuccess) return e;
+    AbArgs<T> B{};
+    B.na = na; B.nb = nb; B.norb = A.norb;
+    B.a1p = A.a1p; B.a1pack = A.a1pack; B.b1p = A.b1p; B.b1pack = A.b1pack; B.eri = A.eri;
+    e = alpha_beta<T, NV>(B, c, y, tune, st);
+    if (e != hipSuccess) return e;
+    return transpose<T, NV, true>(yT, y, nb, na, st);
 }
 
 }  // namespace
 
+size_t sigma_workspace_bytes(int64_t N, int nvec, int layout, size_t elem) {
+    const int nv = layout == 0 ? 1 : nvec;
+    return 2 * (size_t)N * nv * elem;
+}
+
 template <class T>
-hipError_t launch_sigma(const SigmaArgs<T>& A, int nvec, const T* c, T* y, int layout,
-                        hipStream_t st) {
+hipError_t launch_sigma(const SigmaArgs<T>& A, int nvec, const T* c, T* y, int layout, void* ws,
+                        const SigmaTune& tune, hipStream_t st) {
     if (A.na == 0 || A.nb == 0) return hipSuccess;
+    const int64_t N = A.na * A.nb;
+    const int nv = layout == 0 ? 1 : nvec;
+    T* cT = static_cast<T*>(ws);
+    T* yT = cT + (size_t)N * nv;
     if (layout == 0) {
-        const int64_t N = A.na * A.nb;
         for (int v = 0; v < nvec; ++v) {
-            hipError_t e = launch_rows<T, 1>(A, c + v * N, y + v * N, st);
+            hipError_t e = sigma_nv<T, 1>(A, c + v * N, y + v * N, cT, yT, tune, st);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     }
     switch (nvec) {
-        case 1: return launch_rows<T, 1>(A, c, y, st);
-        case 2: return launch_rows<T, 2>(A, c, y, st);
-        case 3: return launch_rows<T, 3>(A, c, y, st);
-        case 4: return launch_rows<T, 4>(A, c, y, st);
-        case 5: return launch_rows<T, 5>(A, c, y, st);
-        case 6: return launch_rows<T, 6>(A, c, y, st);
-        case 7: return launch_rows<T, 7>(A, c, y, st);
-        case 8: return launch_rows<T, 8>(A, c, y, st);
+        case 1: return sigma_nv<T, 1>(A, c, y, cT, yT, tune, st);
+        case 2: return sigma_nv<T, 2>(A, c, y, cT, yT, tune, st);
+        case 4: return sigma_nv<T, 4>(A, c, y, cT, yT, tune, st);
+        case 8: return sigma_nv<T, 8>(A, c, y, cT, yT, tune, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template hipError_t launch_sigma<double>(const SigmaArgs<double>&, int, const double*, double*,
-                                         int, hipStream_t);
+                                         int, void*, const SigmaTune&, hipStream_t);
 template hipError_t launch_sigma<float>(const SigmaArgs<float>&, int, const float*, float*, int,
-                                        hipStream_t);
+                                        void*, const SigmaTune&, hipStream_t);
 
 }  // namespace sbd

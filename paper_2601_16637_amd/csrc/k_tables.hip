@@ -213,6 +213,16 @@ __global__ void __launch_bounds__(kExcWaves * 64) k_exc_fill(
     }
 }
 
+__global__ void k_pack_singles(int64_t nnz, const int32_t* __restrict__ J,
+                               const uint32_t* __restrict__ orb, const int8_t* __restrict__ sg,
+                               uint64_t* pack) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    uint32_t o = orb[e];
+    pack[e] = (uint64_t)(uint32_t)J[e] | ((uint64_t)(o & 255) << 32) |
+              ((uint64_t)((o >> 8) & 255) << 40) | ((uint64_t)(sg[e] < 0 ? 1 : 0) << 48);
+}
+
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -255,6 +265,14 @@ hipError_t launch_exc_fill(const uint64_t* d_s, int64_t n, const int64_t* rp1, c
                            int8_t* sg2, hipStream_t st) {
     hipLaunchKernelGGL(k_exc_fill, dim3(blocks_for(n, kExcWaves)), dim3(kExcWaves * 64), 0, st,
                        d_s, n, rp1, rp2, J1, orb1, sg1, J2, orb2, sg2);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_singles(int64_t nnz, const int32_t* J, const uint32_t* orb, const int8_t* sg,
+                               uint64_t* pack, hipStream_t st) {
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_pack_singles, dim3(blocks_for(nnz, 256)), dim3(256), 0, st, nnz, J, orb,
+                           sg, pack);
     return hipGetLastError();
 }
 

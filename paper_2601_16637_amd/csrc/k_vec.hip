@@ -214,7 +214,23 @@ __global__ void k_f32_to_f64_axpy(const float* y32, const double* x, double shif
         y[i] = (double)y32[i] + shift * x[i];
 }
 
+// Deterministic bounded test pattern: x_i = sin(0.37 i) (FP64 or FP32).
+__global__ void k_fill_pattern(void* p, int64_t n, int prec) {
+    for (int64_t i = (int64_t)blockIdx.x * kVB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVB) {
+        const double v = sin(0.37 * (double)(i % 1000003));
+        if (prec == 0)
+            static_cast<double*>(p)[i] = v;
+        else
+            static_cast<float*>(p)[i] = (float)v;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_fill_pattern(void* p, int64_t n, int prec, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_pattern, dim3(red_blocks(n)), dim3(kVB), 0, st, p, n, prec);
+    return hipGetLastError();
+}
 
 hipError_t launch_multidot(const double* A, int m, const double* x, int64_t N, double* d_out,
                            double* d_part, hipStream_t st) {

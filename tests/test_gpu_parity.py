@@ -360,3 +360,39 @@ def test_error_paths_on_gpu():
         sbd.sigma(ham, x, x)
     with pytest.raises(sbd.SBDError):
         sbd.sigma(ham, x, torch.empty_like(x), nvec=9, layout=1)
+
+
+# ------------------------------------------------------------------ launch configurations
+@pytest.mark.parametrize("rw,lds", [(1, 4096), (2, 4096), (1, 49152), (2, 147456)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sigma_every_launch_config(rw, lds, prec):
+    """Every schedule the autotuner can pick gives the oracle's sigma: windowed
+    alpha-beta staging (tiny LDS budget), several ket rows per group, one or
+    two rows per stream wavefront, odd row counts."""
+    norb = 14
+    A = wl.sample_strings(norb, 6, 333, 51)
+    B = wl.sample_strings(norb, 5, 257, 52)
+    h, eri, ec = wl.make_integrals(norb, 53)
+    _, _, ham = gpu_system(norb, 6, 5, A, B, h, eri, ec)
+    ham.set_tune(prec, rw, lds)
+    assert ham.get_tune(prec) == dict(stream_rw=rw, ab_lds_bytes=lds)
+    S = oracle.OracleSystem(norb, A, B, h, eri, ec)
+    x = wl.random_vector(S.N, 54)[0]
+    if prec == 0:
+        assert rel(gpu_sigma(ham, x), S.sigma(x)) <= 1e-12
+    else:
+        shift = S.diag().min()
+        x32 = x.astype(np.float32).astype(np.float64)
+        y = gpu_sigma(ham, x32, prec=1, shift=shift)
+        assert rel(y, S.sigma(x32) - shift * x32) <= 2e-5
+
+
+def test_autotune_then_sigma():
+    W = wl.make_config("block20", nstr=300)
+    _, _, ham = from_workload(W)
+    ms = ham.autotune(0)
+    assert ms > 0
+    assert ham.autotune(0) == -1.0          # second call: cached
+    S = oracle.OracleSystem.from_workload(W)
+    x = wl.random_vector(S.N, 55)[0]
+    assert rel(gpu_sigma(ham, x), S.sigma(x)) <= 1e-12
