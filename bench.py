@@ -33,6 +33,7 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the sigma kernel source: traffic figures are valid only for it."""
     h = hashlib.sha256()
     for f in ("k_sigma.hip", "internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2601_16637_amd", "csrc", f), "rb").read())
@@ -40,19 +41,17 @@ def kernel_source_hash():
 
 
 def traffic_for(kernel, workload):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    if the summary is missing or was taken on a different kernel source."""
-    p = os.path.join(ROOT, "profiles", "sigma_traffic.json")
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (profiles/sigma_traffic.txt, lines 'kernel workload source_hash bytes'),
+    or None if it is missing or was taken on a different kernel source."""
+    p = os.path.join(ROOT, "profiles", "sigma_traffic.txt")
     if not os.path.exists(p):
         return None
-    try:
-        d = json.load(open(p))
-    except ValueError:
-        return None
-    ent = d.get(f"{kernel}/{workload}")
-    if not ent or ent.get("source_hash") != kernel_source_hash():
-        return None
-    return ent.get("bytes_per_launch")
+    for line in open(p):
+        f = line.split()
+        if len(f) == 4 and not line.startswith("#") and f[0] == kernel and f[1] == workload:
+            return float(f[3]) if f[2] == kernel_source_hash() else None
+    return None
 
 
 def time_to(hist_theta, hist_time, e_ref, tol=1e-6):
@@ -60,6 +59,41 @@ def time_to(hist_theta, hist_time, e_ref, tol=1e-6):
         if abs(th - e_ref) <= tol:
             return t
     return None
+
+
+def sigma_stages(sbd, H, N, prec, stream, reps=10):
+    """Mean per-stage milliseconds of sigma over reps launches (HIP events)."""
+    import torch
+    dt = torch.float64 if prec == sbd.FP64 else torch.float32
+    x = torch.randn(N, device="cuda", dtype=dt)
+    y = torch.empty_like(x)
+    for _ in range(2):
+        sbd.sigma(H, x, y, prec=prec, shift=-200.0, stream=stream)
+    acc = None
+    for _ in range(reps):
+        st = sbd.sigma_timed(H, x, y, prec=prec, shift=-200.0, stream=stream)
+        acc = st if acc is None else {k: acc[k] + st[k] for k in st}
+    return {k: v / reps for k, v in acc.items()}
+
+
+def kernel_only(sbd, W, stream):
+    """Short run for hardware-counter passes: five FP32 sigma launches and one
+    device copy of known size (2 * N * 4 bytes) used to calibrate the counters."""
+    import torch
+    B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
+    X = sbd.Excitations(B, stream=stream)
+    H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
+    H.autotune(sbd.FP32, stream=stream)
+    x = torch.randn(W.ndet, device="cuda", dtype=torch.float32)
+    y = torch.empty_like(x)
+    for _ in range(5):
+        sbd.sigma(H, x, y, prec=sbd.FP32, shift=-200.0, stream=stream)
+    z = torch.empty_like(x)
+    z.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(kernel_only=True, workload=W.name, ndet=W.ndet,
+                          copy_bytes_read=4 * W.ndet, copy_bytes_written=4 * W.ndet,
+                          tune=H.get_tune(sbd.FP32))))
 
 
 def cpu_baseline(W, target_s=15.0):
@@ -90,6 +124,8 @@ def main():
     ap.add_argument("--workload", default="sel26")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only a few sigma launches and a calibration copy (counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU path is not built "
@@ -107,13 +143,16 @@ def main():
     tol = 1e-6
     log(f"[bench] workload {W.name}: norb={W.norb} n={W.n_alpha} strings={W.alpha.size}x"
         f"{W.beta.size} N={N} roots={W.nroots}")
+    if args.kernel_only:
+        kernel_only(sbd, W, stream)
+        return
 
     def solve(prec, tol_r):
         B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
         X = sbd.Excitations(B, stream=stream)
         H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
         e, rep, st = sbd.davidson(H, W.nroots, stream=stream, tol_residual=tol_r,
-                                  sigma_prec=prec, max_space=20)
+                                  sigma_prec=prec, max_space=20, use_autotune=1)
         return e, rep, st, (B, X, H)
 
     for i in range(args.warmup):
@@ -145,7 +184,7 @@ def main():
         t_plain = 1e3 * (time.perf_counter() - tp)
         # tight FP64 reference energy for time-to-1e-6 Ha
         eref, repref, _ = sbd.davidson(keep[2], W.nroots, stream=stream, tol_residual=1e-8,
-                                       sigma_prec=sbd.FP64, max_space=20)
+                                       sigma_prec=sbd.FP64, max_space=20, use_autotune=1)
         ttp = time_to(rep64["theta_history"], rep64["time_history_ms"], eref[0])
         ttm = time_to(rep_m["theta_history"], rep_m["time_history_ms"], eref[0])
         extra = dict(
@@ -164,36 +203,37 @@ def main():
         )
         log(f"[bench] plain FP64: {t_plain:.1f} ms, E={e64[0]:.10f}; ref {eref[0]:.10f}")
 
-    # dominant kernel: FP32 sigma, timed with HIP events on the launch stream
+    # dominant kernel: the FP32 same-spin row stream (two launches per sigma),
+    # timed live with HIP events recorded on the launch stream
     B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
     X = sbd.Excitations(B, stream=stream)
     H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
-    x32 = torch.randn(N, device="cuda", dtype=torch.float32)
-    y32 = torch.empty_like(x32)
-    for _ in range(2):
-        sbd.sigma(H, x32, y32, prec=sbd.FP32, shift=-200.0, stream=stream)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    nl = 10
-    ev0.record(stream)
-    for _ in range(nl):
-        sbd.sigma(H, x32, y32, prec=sbd.FP32, shift=-200.0, stream=stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t_launch = ev0.elapsed_time(ev1) / nl * 1e-3
+    H.autotune(sbd.FP32, stream=stream)
+    stages32 = sigma_stages(sbd, H, N, sbd.FP32, stream)
+    H.autotune(sbd.FP64, stream=stream)
+    stages64 = sigma_stages(sbd, H, N, sbd.FP64, stream)
     p1a, p2a = X.count(0, 1), X.count(0, 2)
     p1b, p2b = X.count(1, 1), X.count(1, 2)
     nnz = N + B.nb * (p1a + p2a) + B.na * (p1b + p2b) + p1a * p1b
-    flops = 2.0 * nnz
-    achieved = flops / t_launch
-    traffic = traffic_for("k_sigma_rows<float,1>", W.name)
+    # algorithmic flops of the two stream launches: one multiply-add per
+    # connected same-spin pair (+ the diagonal term and the spectator add of singles)
+    f_alpha = 2.0 * (B.nb * (p1a + p2a) + N) + 1.0 * B.nb * p1a
+    f_beta = 2.0 * B.na * (p1b + p2b) + 1.0 * B.na * p1b
+    t_stream = (stages32["alpha_stream"] + stages32["beta_stream"]) * 1e-3
+    achieved = (f_alpha + f_beta) / t_stream
+    t_sig32 = sum(stages32.values()) * 1e-3
+    t_sig64 = sum(stages64.values()) * 1e-3
+    traffic = traffic_for("k_stream<float,1,2,1>", W.name)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
-                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU, traffic=traffic,
-                    kernel="k_sigma_rows<float,1>", launch_ms=t_launch * 1e3,
-                    algorithmic_flops=flops, nnz_pairs=nnz,
-                    sigma_det_per_s=N / t_launch,
-                    hbm_frac_algorithmic=(N * 8.0 / t_launch) / PEAK_HBM)
-    log(f"[bench] sigma fp32 launch {t_launch*1e3:.3f} ms, NNZ {nnz:.3e}, "
-        f"{achieved/1e12:.2f} TFLOP/s")
+                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU,
+                    traffic=None if traffic is None else traffic,
+                    kernel="k_stream<float,1,2,1> (alpha and beta launches of one FP32 sigma)",
+                    launch_ms=1e3 * t_stream / 2, algorithmic_flops_per_launch=(f_alpha + f_beta) / 2,
+                    sigma_fp32_stage_ms=stages32, sigma_fp64_stage_ms=stages64,
+                    sigma_fp32_det_per_s=N / t_sig32, sigma_fp64_det_per_s=N / t_sig64,
+                    nnz_pairs=nnz, sigma_fp32_pair_flops_per_s=2.0 * nnz / t_sig32)
+    log(f"[bench] sigma fp32 {1e3*t_sig32:.3f} ms ({stages32}), fp64 {1e3*t_sig64:.3f} ms; "
+        f"stream {achieved/1e12:.2f} TFLOP/s")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(W)
     out = dict(metric="sigma determinants/s over a whole Davidson solve to 1e-6 (chosen form: "

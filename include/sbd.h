@@ -168,6 +168,28 @@ int sbd_autotune(const sbd_basis* b, const sbd_exc* e, sbd_ham* h, int prec, int
 int sbd_get_tune(const sbd_ham* h, int prec, int* stream_rw, int* ab_lds_bytes);
 int sbd_set_tune(sbd_ham* h, int prec, int stream_rw, int ab_lds_bytes);
 
+/*
+ * sbd_sigma with HIP events recorded on `stream` around its five launches;
+ * synchronises the stream and writes the elapsed milliseconds of each stage
+ * of the first vector to stage_ms[5]: transpose of c, alpha-side row stream
+ * (with the diagonal), beta-side row stream, alpha-beta term, transpose-add.
+ * Same results and errors as sbd_sigma (plus SBD_ERR_ARG for stage_ms NULL).
+ */
+int sbd_sigma_timed(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h,
+                    int nvec, int prec, double shift, const void* c, void* sigma, int layout,
+                    void* stream, double* stage_ms);
+
+/*
+ * Tall-skinny projection out = A^T X (the Gram-Schmidt / Rayleigh-Ritz
+ * projections of the Davidson update, Sec. II-C), computed on the FP64 matrix
+ * cores.  A: ma device vectors of N doubles at A + j*N (1 <= ma <= 48);
+ * X: k device vectors at X + q*N (1 <= k <= 8).  out: host array of ma*k
+ * doubles, out[j*k + q] = A_j . X_q, summed in a fixed order (deterministic).
+ * Synchronises the stream.  Errors: SBD_ERR_ARG, SBD_ERR_NOMEM, SBD_ERR_HIP.
+ */
+int sbd_gram(const double* A, int ma, const double* X, int k, int64_t N, double* out,
+             void* stream);
+
 /* Options of sbd_davidson; sbd_davidson_default_opts fills the defaults. */
 typedef struct {
     double tol_residual;   /* ||H u - theta u||_2 per root (unit u); default 1e-6                 */

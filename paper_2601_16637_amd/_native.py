@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "SBD_OK", 1: "SBD_NOT_CONVERGED", -1: "SBD_ERR_ARG", -2: "SBD
 EXPORTED = ["sbd_last_error", "sbd_version", "sbd_build_basis", "sbd_basis_sizes",
             "sbd_basis_strings", "sbd_free_basis", "sbd_build_excitations", "sbd_exc_count",
             "sbd_exc_export", "sbd_free_exc", "sbd_set_hamiltonian", "sbd_ham_diag",
-            "sbd_free_ham", "sbd_sigma", "sbd_autotune", "sbd_get_tune", "sbd_set_tune",
+            "sbd_free_ham", "sbd_sigma", "sbd_sigma_timed", "sbd_autotune", "sbd_get_tune", "sbd_set_tune", "sbd_gram",
             "sbd_davidson_default_opts", "sbd_davidson"]
 
 
@@ -97,9 +97,11 @@ def load():
     L.sbd_free_ham.argtypes = [P]
     L.sbd_free_ham.restype = None
     L.sbd_sigma.argtypes = [P, P, P, i32, i32, d, P, P, i32, P]
+    L.sbd_sigma_timed.argtypes = [P, P, P, i32, i32, d, P, P, i32, P, P]
     L.sbd_autotune.argtypes = [P, P, P, i32, i32, i32, P, ctypes.POINTER(d)]
     L.sbd_get_tune.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.sbd_set_tune.argtypes = [P, i32, i32, i32]
+    L.sbd_gram.argtypes = [P, i32, P, i32, i64, P, P]
     L.sbd_davidson_default_opts.argtypes = [ctypes.POINTER(DavidsonOpts)]
     L.sbd_davidson_default_opts.restype = None
     L.sbd_davidson.argtypes = [P, P, P, i32, ctypes.POINTER(DavidsonOpts), P, P,
@@ -252,6 +254,27 @@ def sigma(ham: Hamiltonian, c, out, nvec: int = 1, prec: int = FP64, shift: floa
     """out = (H - shift) c on device buffers (sbd_sigma)."""
     check(load().sbd_sigma(ham.basis._h, ham.exc._h, ham._h, int(nvec), int(prec), float(shift),
                            _dptr(c), _dptr(out), int(layout), _stream(stream)))
+    return out
+
+
+SIGMA_STAGES = ("transpose", "alpha_stream", "beta_stream", "alpha_beta", "transpose_add")
+
+
+def sigma_timed(ham: Hamiltonian, c, out, nvec: int = 1, prec: int = FP64, shift: float = 0.0,
+                layout: int = 0, stream=None) -> dict:
+    """sigma with HIP-event timing of its five launches (sbd_sigma_timed); returns ms per stage."""
+    ms = np.zeros(5, dtype=np.float64)
+    check(load().sbd_sigma_timed(ham.basis._h, ham.exc._h, ham._h, int(nvec), int(prec),
+                                 float(shift), _dptr(c), _dptr(out), int(layout),
+                                 _stream(stream), _host(ms)))
+    return dict(zip(SIGMA_STAGES, ms.tolist()))
+
+
+def gram(A, ma: int, X, k: int, N: int, stream=None) -> np.ndarray:
+    """A^T X for device row blocks (sbd_gram): returns an (ma, k) host array."""
+    out = np.zeros((ma, k), dtype=np.float64)
+    check(load().sbd_gram(_dptr(A), int(ma), _dptr(X), int(k), int(N), _host(out),
+                          _stream(stream)))
     return out
 
 

@@ -175,6 +175,26 @@ int sbd_build_excitations(const sbd_basis* b, void* stream, sbd_exc** out) {
         if (e == hipSuccess)
             e = launch_pack_singles(t1.nnz, t1.J.as<int32_t>(), t1.orb.as<uint32_t>(),
                                     t1.sign.as<int8_t>(), t1.pack.as<uint64_t>(), st);
+        // sliced-ELL copy of the singles (used when this spin is gathered per lane)
+        const int64_t nslice = (n + 63) / 64;
+        DevBuf slots;
+        if (e == hipSuccess) e = slots.alloc(sizeof(int64_t) * (size_t)std::max<int64_t>(nslice, 1));
+        if (e == hipSuccess) e = t1.sell_off.alloc(sizeof(int64_t) * (size_t)(nslice + 1));
+        if (e == hipSuccess) e = launch_sell_len(t1.row_ptr.as<int64_t>(), n, slots.as<int64_t>(), st);
+        if (e == hipSuccess)
+            e = launch_exclusive_scan(slots.as<int64_t>(), nslice, t1.sell_off.as<int64_t>(), st);
+        int64_t sell_total = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&sell_total, t1.sell_off.as<int64_t>() + nslice, sizeof(int64_t),
+                               hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) {
+            t1.sell_entries = sell_total;
+            e = t1.sell.alloc(sizeof(uint64_t) * (size_t)std::max<int64_t>(sell_total, 1));
+        }
+        if (e == hipSuccess)
+            e = launch_sell_fill(t1.row_ptr.as<int64_t>(), t1.pack.as<uint64_t>(), n,
+                                 t1.sell_off.as<int64_t>(), t1.sell.as<uint64_t>(), st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
             delete x;
@@ -333,6 +353,7 @@ SigmaArgs<double> make_args<double>(const sbd_exc* x, const sbd_ham* H, double s
     A.a1c = H->sc[0].c1_64.as<double>(); A.a1ps = H->sc[0].ps1.as<int32_t>();
     A.a2p = a2->row_ptr.as<int64_t>(); A.a2J = a2->J.as<int32_t>(); A.a2c = H->sc[0].c2_64.as<double>();
     A.b1p = b1->row_ptr.as<int64_t>(); A.b1J = b1->J.as<int32_t>(); A.b1pack = b1->pack.as<uint64_t>();
+    A.b1sell = b1->sell.as<uint64_t>(); A.b1sell_off = b1->sell_off.as<int64_t>();
     A.b1c = H->sc[1].c1_64.as<double>(); A.b1ps = H->sc[1].ps1.as<int32_t>();
     A.b2p = b2->row_ptr.as<int64_t>(); A.b2J = b2->J.as<int32_t>(); A.b2c = H->sc[1].c2_64.as<double>();
     A.Ga = H->sc[0].G64.as<double>(); A.Gb = H->sc[1].G64.as<double>();
@@ -349,6 +370,7 @@ SigmaArgs<float> make_args<float>(const sbd_exc* x, const sbd_ham* H, double shi
     A.a1c = H->sc[0].c1_32.as<float>(); A.a1ps = H->sc[0].ps1.as<int32_t>();
     A.a2p = a2->row_ptr.as<int64_t>(); A.a2J = a2->J.as<int32_t>(); A.a2c = H->sc[0].c2_32.as<float>();
     A.b1p = b1->row_ptr.as<int64_t>(); A.b1J = b1->J.as<int32_t>(); A.b1pack = b1->pack.as<uint64_t>();
+    A.b1sell = b1->sell.as<uint64_t>(); A.b1sell_off = b1->sell_off.as<int64_t>();
     A.b1c = H->sc[1].c1_32.as<float>(); A.b1ps = H->sc[1].ps1.as<int32_t>();
     A.b2p = b2->row_ptr.as<int64_t>(); A.b2J = b2->J.as<int32_t>(); A.b2c = H->sc[1].c2_32.as<float>();
     A.Ga = H->sc[0].G32.as<float>(); A.Gb = H->sc[1].G32.as<float>();
@@ -357,15 +379,15 @@ SigmaArgs<float> make_args<float>(const sbd_exc* x, const sbd_ham* H, double shi
 }
 
 int sigma_internal(const sbd_exc* x, const sbd_ham* H, int nvec, int prec, double shift,
-                   const void* c, void* y, int layout, void* ws, hipStream_t st) {
+                   const void* c, void* y, int layout, void* ws, hipStream_t st, hipEvent_t* ev) {
     hipError_t e;
     const SigmaTune tune = H->tune[prec == SBD_FP64 ? 0 : 1];
     if (prec == SBD_FP64)
         e = launch_sigma<double>(make_args<double>(x, H, shift), nvec, (const double*)c, (double*)y,
-                                 layout, ws, tune, st);
+                                 layout, ws, tune, st, ev);
     else
         e = launch_sigma<float>(make_args<float>(x, H, shift), nvec, (const float*)c, (float*)y,
-                                layout, ws, tune, st);
+                                layout, ws, tune, st, ev);
     if (e != hipSuccess) return hip_fail(e, "sbd_sigma launch");
     return SBD_OK;
 }
@@ -388,8 +410,9 @@ void* ham_workspace(const sbd_ham* Hc, hipStream_t st, size_t bytes, int* rc) {
 }
 }  // namespace sbd
 
-extern "C" int sbd_sigma(const sbd_basis* b, const sbd_exc* x, const sbd_ham* H, int nvec, int prec,
-                         double shift, const void* c, void* sigma, int layout, void* stream) {
+static int sigma_entry(const sbd_basis* b, const sbd_exc* x, const sbd_ham* H, int nvec, int prec,
+                       double shift, const void* c, void* sigma, int layout, void* stream,
+                       hipEvent_t* ev) {
     if (!b || !x || !H || !c || !sigma) return fail(SBD_ERR_ARG, "null argument");
     if (x->basis_id != b->id || H->basis_id != b->id || H->exc_id != x->id)
         return fail(SBD_ERR_STATE, "handles do not belong together");
@@ -406,5 +429,43 @@ extern "C" int sbd_sigma(const sbd_basis* b, const sbd_exc* x, const sbd_ham* H,
     void* ws = ham_workspace(H, (hipStream_t)stream,
                              sigma_workspace_bytes(N, nvec, layout, prec == SBD_FP64 ? 8 : 4), &rc);
     if (!ws && N > 0) return rc;
-    return sigma_internal(x, H, nvec, prec, shift, c, sigma, layout, ws, (hipStream_t)stream);
+    return sigma_internal(x, H, nvec, prec, shift, c, sigma, layout, ws, (hipStream_t)stream, ev);
+}
+
+extern "C" int sbd_sigma(const sbd_basis* b, const sbd_exc* x, const sbd_ham* H, int nvec, int prec,
+                         double shift, const void* c, void* sigma, int layout, void* stream) {
+    return sigma_entry(b, x, H, nvec, prec, shift, c, sigma, layout, stream, nullptr);
+}
+
+extern "C" int sbd_sigma_timed(const sbd_basis* b, const sbd_exc* x, const sbd_ham* H, int nvec,
+                               int prec, double shift, const void* c, void* sigma, int layout,
+                               void* stream, double* stage_ms) {
+    if (!stage_ms) return fail(SBD_ERR_ARG, "stage_ms is NULL");
+    hipEvent_t ev[6];
+    for (int i = 0; i < 6; ++i) SBD_HIP(hipEventCreate(&ev[i]));
+    int rc = sigma_entry(b, x, H, nvec, prec, shift, c, sigma, layout, stream, ev);
+    hipError_t e = rc ? hipSuccess : hipEventSynchronize(ev[5]);
+    for (int i = 0; i < 5 && !rc && e == hipSuccess; ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+        stage_ms[i] = ms;
+    }
+    for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "sbd_sigma_timed");
+    return SBD_OK;
+}
+
+extern "C" int sbd_gram(const double* A, int ma, const double* X, int k, int64_t N, double* out,
+                        void* stream) {
+    if (!A || !X || !out || N < 1) return fail(SBD_ERR_ARG, "null argument or N < 1");
+    if (ma < 1 || ma > 48 || k < 1 || k > 8) return fail(SBD_ERR_ARG, "need 1 <= ma <= 48, 1 <= k <= 8");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf part, res;
+    SBD_HIP(part.alloc(sizeof(double) * (size_t)ma * k * kRedBlocks));
+    SBD_HIP(res.alloc(sizeof(double) * (size_t)ma * k));
+    SBD_HIP(pass_project(A, ma, X, k, N, part.as<double>(), res.as<double>(), st));
+    SBD_HIP(hipMemcpyAsync(out, res.p, sizeof(double) * (size_t)ma * k, hipMemcpyDeviceToHost, st));
+    SBD_HIP(hipStreamSynchronize(st));
+    return SBD_OK;
 }

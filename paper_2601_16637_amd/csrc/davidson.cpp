@@ -1,21 +1,29 @@
 // Davidson eigensolver driver (Sec. II-C) with device-resident FP64 vectors.
 //
 // Per iteration, in the paper's order: sigma of the new basis vectors,
-// projected matrix T = V^T W (updated column by column), smallest Ritz pairs
-// of T, residual r = W y - theta V y fused with the damped diagonal
-// preconditioner (Eqs. 6-7), convergence test on ||r||_2, orthogonalisation
-// of each correction against the subspace (two classical Gram-Schmidt
-// passes: "twice is enough"), expansion, and a restart onto the lowest Ritz
-// vectors when the subspace is full.  Several roots are solved together as a
-// block.
+// projected matrix T = V^T W, smallest Ritz pairs of T, residual
+// r = W y - theta V y fused with the damped diagonal preconditioner (Eqs. 6-7),
+// convergence test on ||r||_2, orthogonalisation of each correction against
+// the subspace (two classical Gram-Schmidt passes, "twice is enough"),
+// expansion, and a restart onto the lowest Ritz vectors when the subspace is
+// full.  Several roots are solved together as a block.
+//
+// The vector work is three fused sweeps over the subspace per new vector,
+// each with its projections fused in (k_project.hip):
+//   1. residual + preconditioner together with the first projection V^T t,
+//   2. t <- t - V h1 together with h2 = V^T t,
+//   3. v_new <- t - V h2 together with |v_new| and W^T v_new, which is the new
+//      column of T (T_{j,new} = w_j . v_new = v_j . H v_new).
+// Only the reduced scalars travel to the host.
 //
 // SBD_FP32 mode (mixed precision): sigma of new basis vectors is computed in
 // FP32 on (H - shift I), shift = lowest diagonal element, and restored in
-// FP64; everything else stays FP64.  Residual-correction refinement: when the
-// inner residuals (which carry the FP32 sigma error) fall below the target,
-// one FP64 sigma of the Ritz vectors certifies the true residuals; if they
-// are not yet below tol the subspace restarts from the Ritz vectors with their
-// exact FP64 sigma and the inner iteration continues.
+// FP64; everything else stays FP64.  Residual-correction refinement: the start
+// vectors get an FP64 sigma, so the first residuals are exact.  When the inner
+// residuals (which carry the FP32 sigma error) reach the target, drop well
+// below the last exact value, stop improving, or the subspace is full, the
+// subspace collapses onto the Ritz vectors and their sigma is recomputed in
+// FP64; convergence is only declared on such exact residuals.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -27,7 +35,8 @@
 namespace sbd {
 
 int sigma_internal(const sbd_exc* x, const sbd_ham* H, int nvec, int prec, double shift,
-                   const void* c, void* y, int layout, void* ws, hipStream_t st);
+                   const void* c, void* y, int layout, void* ws, hipStream_t st,
+                   hipEvent_t* ev = nullptr);
 
 // Cyclic Jacobi eigensolver for a symmetric m x m matrix (row-major).  On exit
 // w holds eigenvalues ascending and Z (row-major, column k = eigenvector k).
@@ -91,21 +100,146 @@ static void jacobi_eigh(int m, std::vector<double> A, std::vector<double>& w,
 
 namespace {
 
-struct Work {
-    DevBuf V, W, tmp, scr, part, small, d_idx, d32a, d32b, sws;
-};
-
 using clk = std::chrono::steady_clock;
 inline double ms_since(clk::time_point t0) {
     return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
 }
 
-}  // namespace
+// Offsets (in doubles) inside the small device scratch buffer.
+constexpr int kRed = 0;       // reduced rows of the residual pass (<= 2*8 + 48*8)
+constexpr int kH1 = 512;      // first projection (<= 48)
+constexpr int kH2 = 576;      // |t'|^2, then the second projection (<= 1 + 48)
+constexpr int kP2 = 640;      // |v_new|^2, then W^T v_new (<= 1 + 48)
+constexpr int kY = 704;       // Ritz coefficients, m x k (<= 48 x 8)
+constexpr int kTheta = 1088;  // Ritz values (<= 8)
+constexpr int kYc = 1152;     // collapse coefficients, m x keep (<= 48 x 16)
+constexpr int kProj = 2048;   // projection results (<= 48 x 8)
+constexpr int kMisc = 3072;   // argmin value
+constexpr int kSmall = 4096;
+constexpr int kPartRows = 512;
 
-// FP32 sigma of FP64 vectors: y = H x via (H - shift) in FP32 plus shift*x in FP64.
-hipError_t launch_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
-hipError_t launch_f32_to_f64_axpy(const float* y32, const double* x, double shift, double* y,
-                                  int64_t n, hipStream_t st);
+struct Solver {
+    const sbd_exc* x;
+    const sbd_ham* H;
+    hipStream_t st;
+    int64_t N;
+    int ms, k, keep;
+    bool mixed;
+    double shift = 0.0;
+    DevBuf V, W, tmp, scr, part, small, idx, x32, y32, sws;
+    double* sm = nullptr;
+    double t_sigma = 0.0;
+    int sigma_calls = 0, sigma64 = 0;
+
+    double* Vr(int j) { return V.as<double>() + (size_t)j * N; }
+    double* Wr(int j) { return W.as<double>() + (size_t)j * N; }
+
+    int alloc() {
+        hipError_t e = V.alloc(sizeof(double) * (size_t)ms * N);
+        if (e == hipSuccess) e = W.alloc(sizeof(double) * (size_t)ms * N);
+        if (e == hipSuccess) e = tmp.alloc(sizeof(double) * (size_t)std::max(k, keep) * N);
+        if (e == hipSuccess) e = scr.alloc(sizeof(double) * (size_t)keep * N);
+        if (e == hipSuccess) e = part.alloc(sizeof(double) * kPartRows * kRedBlocks);
+        if (e == hipSuccess) e = small.alloc(sizeof(double) * kSmall);
+        if (e == hipSuccess) e = idx.alloc(sizeof(int64_t) * (kRedBlocks + 1));
+        if (e == hipSuccess) e = sws.alloc(sigma_workspace_bytes(N, 1, 0, sizeof(double)));
+        if (mixed && e == hipSuccess) e = x32.alloc(sizeof(float) * (size_t)ms * N);
+        if (mixed && e == hipSuccess) e = y32.alloc(sizeof(float) * (size_t)ms * N);
+        if (e != hipSuccess) return hip_fail(e, "sbd_davidson workspace");
+        sm = small.as<double>();
+        return SBD_OK;
+    }
+
+    // W[j0 .. j0+cnt) = H V[j0 .. j0+cnt)
+    int apply_sigma(int j0, int cnt, bool fp64) {
+        auto t0 = clk::now();
+        int rc;
+        if (!mixed || fp64) {
+            rc = sigma_internal(x, H, cnt, SBD_FP64, 0.0, Vr(j0), Wr(j0), 0, sws.p, st);
+            sigma64 += cnt;
+        } else {
+            hipError_t e = launch_f64_to_f32(Vr(j0), x32.as<float>(), (int64_t)cnt * N, st);
+            if (e != hipSuccess) return hip_fail(e, "to f32");
+            rc = sigma_internal(x, H, cnt, SBD_FP32, shift, x32.p, y32.p, 0, sws.p, st);
+            if (rc) return rc;
+            e = launch_f32_to_f64_axpy(y32.as<float>(), Vr(j0), shift, Wr(j0), (int64_t)cnt * N, st);
+            if (e != hipSuccess) return hip_fail(e, "from f32");
+        }
+        if (rc) return rc;
+        sigma_calls += cnt;
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "sigma");
+        t_sigma += ms_since(t0);
+        return SBD_OK;
+    }
+
+    // out[j*k + q] = P_j . X_q for j < mp, q < k (host copy); k <= 8, mp <= 48
+    int project(const double* P, int mp, const double* X, int k, std::vector<double>& out) {
+        out.assign((size_t)mp * k, 0.0);
+        if (mp == 0 || k == 0) return SBD_OK;
+        SBD_HIP(pass_project(P, mp, X, k, N, part.as<double>(), sm + kProj, st));
+        SBD_HIP(hipMemcpyAsync(out.data(), sm + kProj, sizeof(double) * mp * k, hipMemcpyDeviceToHost, st));
+        SBD_HIP(hipStreamSynchronize(st));
+        return SBD_OK;
+    }
+
+    // Orthogonalise t against V[0..m) (two classical passes) into V[m]; the first
+    // projection V^T t must be on the device at sm+kH1.  mw rows of W have a
+    // sigma.  On return u holds W[0..mw)^T v_new / |v_new| and accept tells
+    // whether the vector survived (|v_new| > 1e-12 |t|).
+    int orthonormalise(double* t, int m, int mw, double n0, std::vector<double>& u, bool& accept) {
+        double* p = part.as<double>();
+        SBD_HIP(pass_sub1(V.as<double>(), m, sm + kH1, t, N, p, sm + kH2, st));
+        SBD_HIP(pass_sub2(V.as<double>(), m, sm + kH2 + 1, t, Vr(m), W.as<double>(), mw, N, p, sm + kP2, st));
+        std::vector<double> r(mw + 1);
+        SBD_HIP(hipMemcpyAsync(r.data(), sm + kP2, sizeof(double) * (mw + 1), hipMemcpyDeviceToHost, st));
+        SBD_HIP(hipStreamSynchronize(st));
+        const double n1 = std::sqrt(std::max(r[0], 0.0));
+        accept = n1 > 1e-12 * std::max(n0, 1e-300) && std::isfinite(n1);
+        u.assign(mw, 0.0);
+        if (!accept) return SBD_OK;
+        SBD_HIP(launch_scale(Vr(m), N, 1.0 / n1, st));
+        for (int j = 0; j < mw; ++j) u[j] = r[1 + j] / n1;
+        return SBD_OK;
+    }
+
+    // first projection of t against V[0..m) into sm+kH1 (no host copy)
+    int first_projection(const double* t, int m) {
+        if (m == 0) return SBD_OK;
+        SBD_HIP(pass_project(V.as<double>(), m, t, 1, N, part.as<double>(), sm + kH1, st));
+        return SBD_OK;
+    }
+
+    // V[0..kk) <- V Yc, W[0..kk) <- W Yc (Yc: the first kk columns of Z)
+    int collapse(const std::vector<double>& Z, int m, int kk, bool with_w) {
+        std::vector<double> Y((size_t)m * kk);
+        for (int i = 0; i < m; ++i)
+            for (int c = 0; c < kk; ++c) Y[i * kk + c] = Z[i * m + c];
+        SBD_HIP(hipMemcpyAsync(sm + kYc, Y.data(), sizeof(double) * m * kk, hipMemcpyHostToDevice, st));
+        SBD_HIP(launch_combination(V.as<double>(), m, sm + kYc, kk, kk, scr.as<double>(), N, st));
+        SBD_HIP(hipMemcpyAsync(V.p, scr.p, sizeof(double) * kk * N, hipMemcpyDeviceToDevice, st));
+        if (with_w) {
+            SBD_HIP(launch_combination(W.as<double>(), m, sm + kYc, kk, kk, scr.as<double>(), N, st));
+            SBD_HIP(hipMemcpyAsync(W.p, scr.p, sizeof(double) * kk * N, hipMemcpyDeviceToDevice, st));
+        }
+        return SBD_OK;
+    }
+
+    // T[0..m) x [0..m) from scratch (after an FP64 refinement)
+    int rebuild_T(int m, std::vector<double>& T) {
+        for (int j0 = 0; j0 < m; j0 += 8) {
+            const int kc = std::min(8, m - j0);
+            std::vector<double> g;
+            int rc = project(V.as<double>(), m, Wr(j0), kc, g);
+            if (rc) return rc;
+            for (int i = 0; i < m; ++i)
+                for (int q = 0; q < kc; ++q) T[i * ms + j0 + q] = g[i * kc + q];
+        }
+        return SBD_OK;
+    }
+};
+
+}  // namespace
 
 }  // namespace sbd
 
@@ -143,190 +277,131 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     if (o.sigma_prec != SBD_FP64 && o.sigma_prec != SBD_FP32) return fail(SBD_ERR_ARG, "bad sigma_prec");
     if (o.n_guess < 0 || (o.n_guess > 0 && !o.guess)) return fail(SBD_ERR_ARG, "bad guess");
     int ms = std::max(o.max_space, 2 * k + 1);
-    ms = std::min<int64_t>(ms, std::max<int64_t>(N, 1));
-    ms = std::min(ms, 64);
-    const int keep = std::max(k, std::min(2 * k, ms - k));
-    const bool mixed = (o.sigma_prec == SBD_FP32);
+    ms = (int)std::min<int64_t>(ms, std::max<int64_t>(N, 1));
+    ms = std::min(ms, 48);
     hipStream_t st = (hipStream_t)stream;
     if (o.use_autotune) {
         // launch configuration only: sigma values do not depend on it beyond rounding order
         int rc = sbd_autotune(b, x, const_cast<sbd_ham*>(H), SBD_FP64, 1, 0, stream, nullptr);
-        if (!rc && mixed) rc = sbd_autotune(b, x, const_cast<sbd_ham*>(H), SBD_FP32, 1, 0, stream, nullptr);
+        if (!rc && o.sigma_prec == SBD_FP32)
+            rc = sbd_autotune(b, x, const_cast<sbd_ham*>(H), SBD_FP32, 1, 0, stream, nullptr);
         if (rc) return rc;
     }
 
-    Work w;
-    hipError_t e = w.V.alloc(sizeof(double) * (size_t)ms * N);
-    if (e == hipSuccess) e = w.W.alloc(sizeof(double) * (size_t)ms * N);
-    if (e == hipSuccess) e = w.tmp.alloc(sizeof(double) * (size_t)std::max(k, keep) * N);
-    if (e == hipSuccess) e = w.scr.alloc(sizeof(double) * (size_t)keep * N);
-    if (e == hipSuccess) e = w.sws.alloc(sigma_workspace_bytes(N, 1, 0, sizeof(double)));
-    if (e == hipSuccess) e = w.part.alloc(sizeof(double) * 16 * kRedBlocks);
-    if (e == hipSuccess) e = w.small.alloc(sizeof(double) * 64 * 16);
-    if (e == hipSuccess) e = w.d_idx.alloc(sizeof(int64_t) * (kRedBlocks + 1));
-    if (mixed && e == hipSuccess) e = w.d32a.alloc(sizeof(float) * (size_t)ms * N);
-    if (mixed && e == hipSuccess) e = w.d32b.alloc(sizeof(float) * (size_t)ms * N);
-    if (e != hipSuccess) return hip_fail(e, "sbd_davidson workspace");
-
-    double* V = w.V.as<double>();
-    double* W = w.W.as<double>();
-    double* tmp = w.tmp.as<double>();
-    double* part = w.part.as<double>();
-    double* sm = w.small.as<double>();  // [0..64): dot results, [64..): y upload, [128..]: misc
+    Solver S;
+    S.x = x;
+    S.H = H;
+    S.st = st;
+    S.N = N;
+    S.ms = ms;
+    S.k = k;
+    S.keep = std::max(k, std::min(2 * k, ms - k));
+    S.mixed = (o.sigma_prec == SBD_FP32);
+    int rc = S.alloc();
+    if (rc) return rc;
+    double* sm = S.sm;
+    double* part = S.part.as<double>();
+    double* tmp = S.tmp.as<double>();
     const double* diag = H->diag.as<double>();
+    double t_update = 0.0;
+    int restarts = 0;
 
-    double t_sigma = 0.0, t_update = 0.0;
-    int sigma_calls = 0, sigma64 = 0, restarts = 0;
-    double shift = 0.0;
-
-    // ---- lowest diagonal entries (also the FP32 shift)
+    // ---- lowest diagonal entries (start vectors, and the FP32 shift)
     std::vector<int64_t> low_idx;
     {
         double vprev = -INFINITY;
         int64_t iprev = -1;
-        int need = (o.n_guess >= k) ? 1 : k;
+        const int need = (o.n_guess >= k) ? 1 : k;
         for (int r = 0; r < need; ++r) {
-            e = launch_argmin_after(diag, N, vprev, iprev, sm + 128, w.d_idx.as<int64_t>(), part,
-                                    w.d_idx.as<int64_t>() + 1, st);
+            hipError_t e = launch_argmin_after(diag, N, vprev, iprev, sm + kMisc, S.idx.as<int64_t>(),
+                                               part, S.idx.as<int64_t>() + 1, st);
             if (e != hipSuccess) return hip_fail(e, "argmin");
             double hv;
             int64_t hi;
-            SBD_HIP(hipMemcpyAsync(&hv, sm + 128, sizeof(double), hipMemcpyDeviceToHost, st));
-            SBD_HIP(hipMemcpyAsync(&hi, w.d_idx.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            SBD_HIP(hipMemcpyAsync(&hv, sm + kMisc, sizeof(double), hipMemcpyDeviceToHost, st));
+            SBD_HIP(hipMemcpyAsync(&hi, S.idx.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
             SBD_HIP(hipStreamSynchronize(st));
             low_idx.push_back(hi);
             vprev = hv;
             iprev = hi;
-            if (r == 0) shift = hv;
+            if (r == 0) S.shift = hv;
         }
     }
 
-    // sigma of vectors V[j0 .. j0+cnt) into W[j0 ..)
-    auto apply_sigma = [&](int j0, int cnt, bool fp64) -> int {
-        auto t0 = clk::now();
-        int rc;
-        if (!mixed || fp64) {
-            rc = sigma_internal(x, H, cnt, SBD_FP64, 0.0, V + (size_t)j0 * N, W + (size_t)j0 * N, 0,
-                                w.sws.p, st);
-            sigma64 += cnt;
-        } else {
-            float* x32 = w.d32a.as<float>();
-            float* y32 = w.d32b.as<float>();
-            hipError_t ee = launch_f64_to_f32(V + (size_t)j0 * N, x32, (int64_t)cnt * N, st);
-            if (ee != hipSuccess) return hip_fail(ee, "to f32");
-            rc = sigma_internal(x, H, cnt, SBD_FP32, shift, x32, y32, 0, w.sws.p, st);
-            if (rc) return rc;
-            ee = launch_f32_to_f64_axpy(y32, V + (size_t)j0 * N, shift, W + (size_t)j0 * N,
-                                        (int64_t)cnt * N, st);
-            if (ee != hipSuccess) return hip_fail(ee, "from f32");
-        }
-        sigma_calls += cnt;
-        hipError_t ee = hipStreamSynchronize(st);
-        if (ee != hipSuccess) return hip_fail(ee, "sigma");
-        t_sigma += ms_since(t0);
-        return rc;
-    };
-    // h[0..m) = V[0..m)^T vec, host copy
-    auto project = [&](const double* A, int m, const double* vec, std::vector<double>& out) -> int {
-        out.assign(m, 0.0);
-        if (m == 0) return SBD_OK;
-        hipError_t ee = launch_multidot(A, m, vec, N, sm, part, st);
-        if (ee != hipSuccess) return hip_fail(ee, "multidot");
-        SBD_HIP(hipMemcpyAsync(out.data(), sm, sizeof(double) * m, hipMemcpyDeviceToHost, st));
-        SBD_HIP(hipStreamSynchronize(st));
-        return SBD_OK;
-    };
-    // orthogonalise vec against V[0..m) twice; returns norm after / before
-    auto orthogonalise = [&](double* vec, int m, double& nbefore, double& nafter) -> int {
-        std::vector<double> h;
-        int rc = project(vec, 1, vec, h);
-        if (rc) return rc;
-        nbefore = std::sqrt(std::max(h[0], 0.0));
-        for (int pass = 0; pass < 2 && m > 0; ++pass) {
-            rc = project(V, m, vec, h);
-            if (rc) return rc;
-            SBD_HIP(hipMemcpyAsync(sm + 64, h.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
-            hipError_t ee = launch_sub_combination(V, m, sm + 64, vec, N, st);
-            if (ee != hipSuccess) return hip_fail(ee, "sub_combination");
-        }
-        rc = project(vec, 1, vec, h);
-        if (rc) return rc;
-        nafter = std::sqrt(std::max(h[0], 0.0));
-        return SBD_OK;
-    };
-
-    // ---- initial subspace
+    // ---- initial subspace: guesses, then unit vectors, orthonormalised
     int m = 0;
-    if (o.n_guess > 0) {
-        int ng = std::min(o.n_guess, ms - k);
-        for (int g = 0; g < ng; ++g) {
-            SBD_HIP(hipMemcpyAsync(V + (size_t)m * N, o.guess + (size_t)g * N, sizeof(double) * N,
-                                   hipMemcpyDeviceToDevice, st));
-            double nb0, nb1;
-            int rc = orthogonalise(V + (size_t)m * N, m, nb0, nb1);
-            if (rc) return rc;
-            if (nb1 <= 1e-12 * std::max(nb0, 1e-300)) continue;
-            SBD_HIP(launch_scale(V + (size_t)m * N, N, 1.0 / nb1, st));
-            ++m;
+    auto add_start = [&](const double* src, int64_t unit) -> int {
+        double* t = tmp;
+        if (src) {
+            SBD_HIP(hipMemcpyAsync(t, src, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+        } else {
+            SBD_HIP(launch_set_unit(t, N, unit, st));
         }
+        std::vector<double> nn;
+        int rc2 = S.project(t, 1, t, 1, nn);
+        if (rc2) return rc2;
+        rc2 = S.first_projection(t, m);
+        if (rc2) return rc2;
+        std::vector<double> u;
+        bool ok = false;
+        rc2 = S.orthonormalise(t, m, 0, std::sqrt(std::max(nn[0], 0.0)), u, ok);
+        if (rc2) return rc2;
+        if (ok) ++m;
+        return SBD_OK;
+    };
+    for (int g = 0; g < o.n_guess && m < ms - k; ++g) {
+        rc = add_start(o.guess + (size_t)g * N, 0);
+        if (rc) return rc;
     }
     for (size_t r = 0; m < k && r < low_idx.size(); ++r) {
-        SBD_HIP(launch_set_unit(V + (size_t)m * N, N, low_idx[r], st));
-        double nb0, nb1;
-        int rc = orthogonalise(V + (size_t)m * N, m, nb0, nb1);
+        rc = add_start(nullptr, low_idx[r]);
         if (rc) return rc;
-        if (nb1 <= 1e-12 * std::max(nb0, 1e-300)) continue;
-        SBD_HIP(launch_scale(V + (size_t)m * N, N, 1.0 / nb1, st));
-        ++m;
     }
     if (m < k) return fail(SBD_ERR_ARG, "could not form nroots independent start vectors");
-    {
-        // the start vectors get an exact FP64 sigma, so the first residuals are certified
-        int rc = apply_sigma(0, m, true);
-        if (rc) return rc;
-    }
+    // the start vectors get an exact FP64 sigma, so the first residuals are certified
+    rc = S.apply_sigma(0, m, true);
+    if (rc) return rc;
     std::vector<double> T((size_t)ms * ms, 0.0);
-    for (int j = 0; j < m; ++j) {
-        std::vector<double> col;
-        int rc = project(V, m, W + (size_t)j * N, col);
-        if (rc) return rc;
-        for (int i = 0; i < m; ++i) T[i * ms + j] = col[i];
-    }
+    rc = S.rebuild_T(m, T);
+    if (rc) return rc;
 
-    std::vector<double> theta(k, 0.0), rnorm(k, INFINITY);
+    std::vector<double> theta(k, 0.0), rnorm(k, INFINITY), tnorm(k, 0.0);
     std::vector<double> evals, Z;
     int it = 0;
     bool converged = false;
-    double last_true_r = INFINITY;
+    double last_true_r = INFINITY, best_inner = INFINITY;
+    int since_cert = 0;
+    bool certified = true;  // residuals computed from an all-FP64 W
     int hist_n = 0;
     std::vector<double> hist_theta, hist_time;
     int status = SBD_OK;
-    bool certified = true;  // residuals computed from an all-FP64 W
-    double best_inner = INFINITY;
-    int since_cert = 0;
     while (true) {
         ++it;
         auto tu0 = clk::now();
-        // small eigenproblem on the symmetrised T
         std::vector<double> Tm((size_t)m * m);
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j) Tm[i * m + j] = 0.5 * (T[i * ms + j] + T[j * ms + i]);
         jacobi_eigh(m, Tm, evals, Z);
         for (int r = 0; r < k; ++r) theta[r] = evals[r];
-        // residuals + preconditioned corrections into tmp[r]
-        for (int r = 0; r < k; ++r) {
-            std::vector<double> y(m);
-            for (int i = 0; i < m; ++i) y[i] = Z[i * m + r];
-            SBD_HIP(hipMemcpyAsync(sm + 64, y.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
-            hipError_t ee = launch_residual_precond(V, W, m, sm + 64, theta[r], diag, o.precond_delta,
-                                                    tmp + (size_t)r * N, N, sm + 128, part, st);
-            if (ee != hipSuccess) return hip_fail(ee, "residual");
-            double rr[2];
-            SBD_HIP(hipMemcpyAsync(rr, sm + 128, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+        // fused residual / preconditioner for all roots with the first projections V^T t_q
+        const bool rproj = pass_fits(m, k);  // else each t_q is projected on its own
+        std::vector<double> red(2 * k + (rproj ? (size_t)m * k : 0));
+        {
+            std::vector<double> Y((size_t)m * k);
+            for (int j = 0; j < m; ++j)
+                for (int q = 0; q < k; ++q) Y[j * k + q] = Z[j * m + q];
+            SBD_HIP(hipMemcpyAsync(sm + kY, Y.data(), sizeof(double) * m * k, hipMemcpyHostToDevice, st));
+            SBD_HIP(hipMemcpyAsync(sm + kTheta, theta.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+            SBD_HIP(pass_resid(S.V.as<double>(), S.W.as<double>(), m, k, sm + kY, sm + kTheta, diag,
+                               o.precond_delta, tmp, N, rproj, part, sm + kRed, st));
+            SBD_HIP(hipMemcpyAsync(red.data(), sm + kRed, sizeof(double) * red.size(), hipMemcpyDeviceToHost, st));
             SBD_HIP(hipStreamSynchronize(st));
-            rnorm[r] = std::sqrt(std::max(rr[0], 0.0));
-            if (!std::isfinite(rr[0]) || !std::isfinite(rr[1]) || !std::isfinite(theta[r]))
-                return fail(SBD_ERR_NUMERIC, "non-finite residual in Davidson");
+            for (int q = 0; q < k; ++q) {
+                if (!std::isfinite(red[q]) || !std::isfinite(red[k + q]) || !std::isfinite(theta[q]))
+                    return fail(SBD_ERR_NUMERIC, "non-finite residual in Davidson");
+                rnorm[q] = std::sqrt(std::max(red[q], 0.0));
+                tnorm[q] = std::sqrt(std::max(red[k + q], 0.0));
+            }
         }
         if (hist_n < 512) {
             hist_theta.push_back(theta[0]);
@@ -334,58 +409,44 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
             ++hist_n;
         }
         if (o.verbose)
-            std::fprintf(stderr, "[sbd] it %d m %d theta0 %.12f |r|max %.3e\n", it, m, theta[0],
-                         *std::max_element(rnorm.begin(), rnorm.end()));
+            std::fprintf(stderr, "[sbd] it %d m %d theta0 %.12f |r|max %.3e%s\n", it, m, theta[0],
+                         *std::max_element(rnorm.begin(), rnorm.end()), certified ? " (exact)" : "");
         bool inner_conv = true;
         for (int r = 0; r < k; ++r) inner_conv = inner_conv && (rnorm[r] <= o.tol_residual);
+        t_update += ms_since(tu0);
         if (inner_conv && certified) {
             converged = true;
-            t_update += ms_since(tu0);
             break;
         }
-        if (it >= o.max_iter) {
-            t_update += ms_since(tu0);
-            break;
-        }
-        t_update += ms_since(tu0);
+        if (it >= o.max_iter) break;
 
-        double rmax = *std::max_element(rnorm.begin(), rnorm.end());
+        const double rmax = *std::max_element(rnorm.begin(), rnorm.end());
         bool refine = false;
         if (certified) {
             last_true_r = rmax;
             best_inner = INFINITY;
             since_cert = 0;
         } else {
-            // inner residuals carry the FP32 sigma error: refine when they reach the
-            // target, drop well below the last certified value, stop improving, or
-            // when the subspace is full
             ++since_cert;
-            bool stagnant = since_cert >= 3 && rmax > 0.7 * best_inner;
+            const bool stagnant = since_cert >= 3 && rmax > 0.7 * best_inner;
             refine = inner_conv || rmax <= 0.1 * last_true_r || stagnant || (m + k > ms);
             best_inner = std::min(best_inner, rmax);
         }
-        if (mixed && refine) {
-            // Refinement step: collapse onto the Ritz vectors and recompute their
-            // sigma in FP64; the residuals of the next pass are then exact.
+        if (S.mixed && refine) {
+            // collapse onto the Ritz vectors and recompute their sigma in FP64
             auto tr0 = clk::now();
-            const int kk = std::min(keep, m);
-            std::vector<double> Y((size_t)m * kk);
-            for (int i = 0; i < m; ++i)
-                for (int c = 0; c < kk; ++c) Y[i * kk + c] = Z[i * m + c];
-            double* dY = sm + 256;
-            SBD_HIP(hipMemcpyAsync(dY, Y.data(), sizeof(double) * m * kk, hipMemcpyHostToDevice, st));
-            SBD_HIP(launch_combination(V, m, dY, kk, kk, tmp, N, st));
-            SBD_HIP(hipMemcpyAsync(V, tmp, sizeof(double) * kk * N, hipMemcpyDeviceToDevice, st));
+            const int kk = std::min(S.keep, m);
+            rc = S.collapse(Z, m, kk, false);
+            if (rc) return rc;
             m = kk;
             t_update += ms_since(tr0);
-            int rc = apply_sigma(0, m, true);
+            rc = S.apply_sigma(0, m, true);
             if (rc) return rc;
-            for (int j = 0; j < m; ++j) {
-                std::vector<double> col;
-                rc = project(V, m, W + (size_t)j * N, col);
-                if (rc) return rc;
-                for (int i = 0; i < m; ++i) T[i * ms + j] = col[i];
-            }
+            auto tr1 = clk::now();
+            std::fill(T.begin(), T.end(), 0.0);
+            rc = S.rebuild_T(m, T);
+            if (rc) return rc;
+            t_update += ms_since(tr1);
             ++restarts;
             certified = true;
             continue;
@@ -395,34 +456,40 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         int nnew = 0;
         for (int r = 0; r < k; ++r)
             if (rnorm[r] > o.tol_residual) ++nnew;
+        bool h1_valid = rproj;  // the residual pass projected every t_q on V[0..m)
         if (m + nnew > ms) {
             // thick restart: V <- V Y_keep, W <- W Y_keep, T <- diag(theta)
-            const int kk = std::min(keep, m);
-            std::vector<double> Y((size_t)m * kk);
-            for (int i = 0; i < m; ++i)
-                for (int c = 0; c < kk; ++c) Y[i * kk + c] = Z[i * m + c];
-            double* dY = sm + 256;
-            SBD_HIP(hipMemcpyAsync(dY, Y.data(), sizeof(double) * m * kk, hipMemcpyHostToDevice, st));
-            // the corrections in tmp survive; the collapse goes through scr
-            SBD_HIP(launch_combination(V, m, dY, kk, kk, w.scr.as<double>(), N, st));
-            SBD_HIP(hipMemcpyAsync(V, w.scr.p, sizeof(double) * kk * N, hipMemcpyDeviceToDevice, st));
-            SBD_HIP(launch_combination(W, m, dY, kk, kk, w.scr.as<double>(), N, st));
-            SBD_HIP(hipMemcpyAsync(W, w.scr.p, sizeof(double) * kk * N, hipMemcpyDeviceToDevice, st));
+            const int kk = std::min(S.keep, m);
+            rc = S.collapse(Z, m, kk, true);
+            if (rc) return rc;
             std::fill(T.begin(), T.end(), 0.0);
             for (int c = 0; c < kk; ++c) T[c * ms + c] = evals[c];
             m = kk;
             ++restarts;
+            h1_valid = false;
         }
-        int m_old = m;
+        const int m_old = m;
         for (int r = 0; r < k; ++r) {
             if (rnorm[r] <= o.tol_residual) continue;
             double* t = tmp + (size_t)r * N;
-            double n0, n1;
-            int rc = orthogonalise(t, m, n0, n1);
+            if (h1_valid && m == m_old) {
+                // projection of root r from the residual pass: rows [2k + j*k + r)
+                std::vector<double> h1(m);
+                for (int j = 0; j < m; ++j) h1[j] = red[2 * k + j * k + r];
+                SBD_HIP(hipMemcpyAsync(sm + kH1, h1.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+            } else {
+                rc = S.first_projection(t, m);
+                if (rc) return rc;
+            }
+            std::vector<double> u;
+            bool ok = false;
+            rc = S.orthonormalise(t, m, m_old, tnorm[r], u, ok);
             if (rc) return rc;
-            if (!(n1 > 1e-12 * std::max(n0, 1e-300))) continue;
-            SBD_HIP(hipMemcpyAsync(V + (size_t)m * N, t, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-            SBD_HIP(launch_scale(V + (size_t)m * N, N, 1.0 / n1, st));
+            if (!ok) continue;
+            for (int j = 0; j < m_old; ++j) {
+                T[j * ms + m] = u[j];
+                T[m * ms + j] = u[j];
+            }
             ++m;
         }
         t_update += ms_since(tu1);
@@ -430,18 +497,18 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
             status = SBD_NOT_CONVERGED;  // stagnation: no new direction
             break;
         }
-        int rc = apply_sigma(m_old, m - m_old, false);
+        rc = S.apply_sigma(m_old, m - m_old, false);
         if (rc) return rc;
-        if (mixed) certified = false;
+        if (S.mixed) certified = false;
         auto tu2 = clk::now();
-        for (int j = m_old; j < m; ++j) {
-            std::vector<double> col;
-            rc = project(V, m, W + (size_t)j * N, col);
+        // T entries among the new vectors: V_new^T W_new (one pass)
+        {
+            const int nn = m - m_old;
+            std::vector<double> g;
+            rc = S.project(S.Vr(m_old), nn, S.Wr(m_old), nn, g);
             if (rc) return rc;
-            for (int i = 0; i < m; ++i) {
-                T[i * ms + j] = col[i];
-                T[j * ms + i] = col[i];
-            }
+            for (int i = 0; i < nn; ++i)
+                for (int j = 0; j < nn; ++j) T[(m_old + i) * ms + m_old + j] = g[i * nn + j];
         }
         t_update += ms_since(tu2);
     }
@@ -452,30 +519,31 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         std::vector<double> Y((size_t)m * k);
         for (int i = 0; i < m; ++i)
             for (int c = 0; c < k; ++c) Y[i * k + c] = Z[i * m + c];
-        double* dY = sm + 256;
-        SBD_HIP(hipMemcpyAsync(dY, Y.data(), sizeof(double) * m * k, hipMemcpyHostToDevice, st));
-        SBD_HIP(launch_combination(V, m, dY, k, k, vectors, N, st));
+        SBD_HIP(hipMemcpyAsync(sm + kYc, Y.data(), sizeof(double) * m * k, hipMemcpyHostToDevice, st));
+        SBD_HIP(launch_combination(S.V.as<double>(), m, sm + kYc, k, k, vectors, N, st));
     }
     double ortho = 0.0;
-    for (int j = 0; j < m; ++j) {
-        std::vector<double> col;
-        int rc = project(V, m, V + (size_t)j * N, col);
+    for (int j0 = 0; j0 < m; j0 += 8) {
+        const int kc = std::min(8, m - j0);
+        std::vector<double> g;
+        rc = S.project(S.V.as<double>(), m, S.Vr(j0), kc, g);
         if (rc) return rc;
-        for (int i = 0; i < m; ++i) {
-            double d = col[i] - (i == j ? 1.0 : 0.0);
-            ortho += d * d;
-        }
+        for (int i = 0; i < m; ++i)
+            for (int q = 0; q < kc; ++q) {
+                const double dd = g[i * kc + q] - (i == j0 + q ? 1.0 : 0.0);
+                ortho += dd * dd;
+            }
     }
     SBD_HIP(hipStreamSynchronize(st));
     if (report) {
         report->iterations = it;
-        report->sigma_calls = sigma_calls;
-        report->sigma_calls_fp64 = sigma64;
+        report->sigma_calls = S.sigma_calls;
+        report->sigma_calls_fp64 = S.sigma64;
         report->converged = converged ? 1 : 0;
         report->restarts = restarts;
         for (int r = 0; r < 64; ++r) report->residual[r] = r < k ? rnorm[r] : 0.0;
         report->ortho_loss = std::sqrt(ortho);
-        report->t_sigma_ms = t_sigma;
+        report->t_sigma_ms = S.t_sigma;
         report->t_update_ms = t_update;
         report->t_total_ms = ms_since(t_start);
         report->n_history = hist_n;

@@ -73,6 +73,9 @@ struct Table {
     DevBuf orb;      // uint32[nnz]: i | j<<8 | a<<16 | b<<24 (double); i | a<<8 (single)
     DevBuf sign;     // int8[nnz]
     DevBuf pack;     // singles only: uint64 J | i << 32 | a << 40 | (sign < 0) << 48
+    DevBuf sell;     // singles only: pack entries in sliced-ELL order (64-string slices)
+    DevBuf sell_off; // int64[nslice+1]: first entry of each slice (slot-major, 64 per slot)
+    int64_t sell_entries = 0;
 };
 }  // namespace sbd
 
@@ -143,6 +146,10 @@ hipError_t launch_exc_fill(const uint64_t* d_s, int64_t n, const int64_t* rp1, c
                            int8_t* sg2, hipStream_t st);
 hipError_t launch_pack_singles(int64_t nnz, const int32_t* J, const uint32_t* orb, const int8_t* sg,
                                uint64_t* pack, hipStream_t st);
+// sliced-ELL: slots[slice] = 64 * longest row of the slice; then fill from the scan
+hipError_t launch_sell_len(const int64_t* rp, int64_t n, int64_t* slots, hipStream_t st);
+hipError_t launch_sell_fill(const int64_t* rp, const uint64_t* pack, int64_t n, const int64_t* off,
+                            uint64_t* sell, hipStream_t st);
 
 // Hamiltonian pieces.
 hipError_t launch_string_diag(const uint64_t* d_s, int64_t n, int norb, const double* h,
@@ -172,6 +179,7 @@ struct SigmaArgs {
     // beta tables
     const int64_t* b1p; const int32_t* b1J; const T* b1c; const int32_t* b1ps;
     const uint64_t* b1pack;
+    const uint64_t* b1sell; const int64_t* b1sell_off;
     const int64_t* b2p; const int32_t* b2J; const T* b2c;
     const T* Ga;   // [npair][na]  sum_{k in alpha(ia)} (pair|kk)
     const T* Gb;   // [npair][nb]
@@ -183,26 +191,17 @@ struct SigmaArgs {
 // Workspace bytes needed by launch_sigma for nvec vectors of type T.
 size_t sigma_workspace_bytes(int64_t N, int nvec, int layout, size_t elem);
 
+// ev (nullable): six events recorded on st around the five launches of the
+// first vector (transpose, alpha stream, beta stream, alpha-beta, transpose-add).
 template <class T>
 hipError_t launch_sigma(const SigmaArgs<T>& A, int nvec, const T* c, T* y, int layout, void* ws,
-                        const SigmaTune& tune, hipStream_t st);
+                        const SigmaTune& tune, hipStream_t st, hipEvent_t* ev = nullptr);
 
 // Dense vector kernels for Davidson (FP64 unless noted).  Vectors are rows
 // of length N stored contiguously: A + j*N.
-// out[j] (device) = sum_i A[j][i] x[i], j < m.  Deterministic two-stage reduction.
-hipError_t launch_multidot(const double* A, int m, const double* x, int64_t N, double* d_out,
-                           double* d_part, hipStream_t st);
-// x[i] -= sum_j A[j][i] h[j]  (h on device)
-hipError_t launch_sub_combination(const double* A, int m, const double* d_h, double* x, int64_t N,
-                                  hipStream_t st);
 // out[r][i] = sum_j A[j][i] Y[j*ldy + r], r < k (Y on device, m x k column block)
 hipError_t launch_combination(const double* A, int m, const double* d_Y, int ldy, int k,
                               double* out, int64_t N, hipStream_t st);
-// t[i] = (W y - theta V y)_i / damp(diag_i - theta); part sums of r^2 into d_part (block partials)
-hipError_t launch_residual_precond(const double* V, const double* W, int m, const double* d_y,
-                                   double theta, const double* diag, double delta, double* t,
-                                   int64_t N, double* d_out /*[2]: r2, t2*/, double* d_part,
-                                   hipStream_t st);
 hipError_t launch_scale(double* x, int64_t N, double s, hipStream_t st);
 hipError_t launch_copy(const double* x, double* y, int64_t N, hipStream_t st);
 // lexicographic successor minimum: smallest (v,i) > (vprev, iprev); writes value/index
@@ -210,6 +209,29 @@ hipError_t launch_argmin_after(const double* v, int64_t N, double vprev, int64_t
                                double* d_val, int64_t* d_idx, double* d_part_v,
                                int64_t* d_part_i, hipStream_t st);
 hipError_t launch_set_unit(double* x, int64_t N, int64_t idx, hipStream_t st);
+
+hipError_t launch_fill_pattern(void* p, int64_t n, int prec, hipStream_t st);
+hipError_t launch_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
+hipError_t launch_f32_to_f64_axpy(const float* y32, const double* x, double shift, double* y,
+                                  int64_t n, hipStream_t st);
+
+// Tall-skinny passes of the Davidson update (k_project.hip).  Each reduces its
+// rows into out (device) in a fixed order; part holds rows x 1024 partials.
+// pass_fits(mp, k): whether mp rows x k outputs fit one pass's register budget.
+bool pass_fits(int mp, int k);
+// pass_resid rows: [0,k) |r_q|^2, [k,2k) |t_q|^2, then (proj) [2k + j*k + q) V_j . t_q
+hipError_t pass_resid(const double* V, const double* W, int m, int k, const double* Y,
+                      const double* theta, const double* diag, double delta, double* T, int64_t N,
+                      bool proj, double* part, double* out, hipStream_t st);
+// t <- t - V h;  rows [0] |t|^2, [1 + j) V_j . t
+hipError_t pass_sub1(const double* V, int m, const double* h, double* t, int64_t N, double* part,
+                     double* out, hipStream_t st);
+// dst <- t - V h;  rows [0] |dst|^2, [1 + j) W_j . dst  (j < mw)
+hipError_t pass_sub2(const double* V, int m, const double* h, const double* t, double* dst,
+                     const double* W, int mw, int64_t N, double* part, double* out, hipStream_t st);
+// rows [j*k + q) = P_j . X_q   (mp <= 48, k <= 8; split into row groups as needed)
+hipError_t pass_project(const double* P, int mp, const double* X, int k, int64_t N, double* part,
+                        double* out, hipStream_t st);
 
 // Reduction scratch sizing.
 constexpr int kRedBlocks = 1024;

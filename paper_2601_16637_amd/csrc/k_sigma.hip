@@ -116,12 +116,13 @@ __device__ __forceinline__ Vec<T, W> vload(const T* p) {
 // tile (and so the per-XCD working set in[:, tile]) at the same bytes per load
 // instruction.  Each row's entry list is fetched with one vector load per 64/RW
 // entries and broadcast lane by lane (v_readlane), so ket-row loads never wait
-// on scalar memory; four ket rows are in flight per step.
+// on scalar memory; 8 (narrow elements) or 4 ket rows are in flight per step.
 template <class T, int NV, int VEC, int RW>
 __global__ void __launch_bounds__(256) k_stream(StreamArgs<T> A, const T* __restrict__ in,
                                                 T* __restrict__ out) {
     constexpr int W = NV * VEC;
     constexpr int HL = 64 / RW;  // lanes per row
+    constexpr int UNR = W <= 2 ? 8 : 4;  // ket rows in flight per step
     const int lane = threadIdx.x & 63;
     const int half = RW == 2 ? (lane >> 5) : 0;
     const int hl = lane & (HL - 1);
@@ -196,7 +197,7 @@ __global__ void __launch_bounds__(256) k_stream(StreamArgs<T> A, const T* __rest
             }
         }
     }
-    // doubles: coefficient per entry; four ket rows in flight
+    // doubles: coefficient per entry; UNR ket rows in flight
     {
         const int64_t a0 = A.p2[r0], a1 = A.p2[r0 + 1];
         const int64_t b0 = A.p2[r1], b1 = (RW == 2 && r1 != r0) ? A.p2[r1 + 1] : b0;
@@ -209,11 +210,11 @@ __global__ void __launch_bounds__(256) k_stream(StreamArgs<T> A, const T* __rest
             const int mj = hl < cnt ? A.J2[my0 + base + hl] : 0;
             const T mc = hl < cnt ? A.c2[my0 + base + hl] : T(0);
             const int lim = (int)((nmax - base) < HL ? (nmax - base) : HL);
-            for (int k = 0; k < lim; k += 4) {
-                int j[4];
-                T f[4];
+            for (int k = 0; k < lim; k += UNR) {
+                int j[UNR];
+                T f[UNR];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < UNR; ++u) {
                     const int kk = (k + u) < HL ? (k + u) : (HL - 1);
                     int jv = bcast(mj, kk);
                     T fv = bcast(mc, kk);
@@ -227,11 +228,11 @@ __global__ void __launch_bounds__(256) k_stream(StreamArgs<T> A, const T* __rest
                     j[u] = ok ? jv : (int)rr;   // padded entries read a valid row with weight 0
                     f[u] = ok ? fv : T(0);
                 }
-                Vec<T, W> x[4];
+                Vec<T, W> x[UNR];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) x[u] = vload<T, W>(in + ((int64_t)j[u] * ncol + cc) * NV);
+                for (int u = 0; u < UNR; ++u) x[u] = vload<T, W>(in + ((int64_t)j[u] * ncol + cc) * NV);
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < UNR; ++u)
 #pragma unroll
                     for (int i = 0; i < W; ++i) acc[i] += f[u] * x[u].x[i];
             }
@@ -252,7 +253,7 @@ struct AbArgs {
     int64_t win;        // ket-row window staged in LDS (determinants)
     int krows;          // alpha singles (ket rows) staged together
     const int64_t* a1p; const uint64_t* a1pack;
-    const int64_t* b1p; const uint64_t* b1pack;
+    const uint64_t* b1sell; const int64_t* b1sell_off;  // beta singles, sliced-ELL
     const T* eri;
 };
 
@@ -282,9 +283,10 @@ __device__ __forceinline__ void stage_row(T* __restrict__ dst, const T* __restri
 // One workgroup = one bra row ia and a block of Q*blockDim columns.  The
 // alpha singles (Ja, i_a -> a_a) of ia are taken K at a time: their ket rows
 // c[Ja][:] (or a window of them) and integral slices (a_a i_a | . .) are staged
-// in LDS, then each thread walks the beta singles of its Q columns.  Each
-// beta-single entry is loaded once per group of K rows, and the entries of the
-// Q columns are fetched step by step so their loads are independent.
+// in LDS, then each thread walks the beta singles of its Q columns.  The beta
+// singles are read from the sliced-ELL table, so entry s of a wavefront's 64
+// columns is one coalesced load; each entry is loaded once per group of K
+// rows, and the Q columns' entries are fetched step by step (independent loads).
 template <class T, int NV, int Q>
 __global__ void __launch_bounds__(1024) k_ab(AbArgs<T> A, const T* __restrict__ c,
                                              T* __restrict__ y) {
@@ -301,15 +303,20 @@ __global__ void __launch_bounds__(1024) k_ab(AbArgs<T> A, const T* __restrict__ 
     const int64_t t0 = A.a1p[ia], t1 = A.a1p[ia + 1];
     if (t0 == t1) return;  // no alpha single: nothing to add (uniform exit)
 
+    // beta singles of the wave's 64-column slices: one slice per q, read slot-major
+    const int lane = threadIdx.x & 63;
+    const int64_t wcol0 = (int64_t)blockIdx.y * blockDim.x * Q + (threadIdx.x & ~63);
     T acc[Q][NV];
-    int u0[Q], len[Q];
+    int64_t soff[Q];
+    int slen[Q];
     int maxlen = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int64_t ib = col0 + (int64_t)q * blockDim.x;
-        u0[q] = (ib < nb) ? (int)A.b1p[ib] : 0;
-        len[q] = (ib < nb) ? (int)(A.b1p[ib + 1] - A.b1p[ib]) : 0;
-        maxlen = len[q] > maxlen ? len[q] : maxlen;
+        const int64_t ibw = wcol0 + (int64_t)q * blockDim.x;
+        const int64_t sl = ibw >> 6;
+        soff[q] = (ibw < nb) ? A.b1sell_off[sl] : 0;
+        slen[q] = (ibw < nb) ? (int)((A.b1sell_off[sl + 1] - soff[q]) >> 6) : 0;
+        maxlen = slen[q] > maxlen ? slen[q] : maxlen;
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[q][v] = T(0);
     }
@@ -335,7 +342,8 @@ __global__ void __launch_bounds__(1024) k_ab(AbArgs<T> A, const T* __restrict__ 
             for (int s = 0; s < maxlen; ++s) {
                 uint64_t pb[Q];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) pb[q] = (s < len[q]) ? A.b1pack[u0[q] + s] : ~0ull;
+                for (int q = 0; q < Q; ++q)
+                    pb[q] = (s < slen[q]) ? A.b1sell[soff[q] + (int64_t)s * 64 + lane] : ~0ull;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
                     if (pb[q] == ~0ull) continue;
@@ -434,9 +442,9 @@ hipError_t ab_launch(const AbArgs<T>& A, const T* c, T* y, int threads, size_t l
 // accumulators and entry bounds within 64 VGPRs (1024-thread workgroups allow 128).
 template <class T, int NV>
 constexpr int ab_qmax() {
-    constexpr int per_q = NV * (int)sizeof(T) / 4 + 4;
-    constexpr int q = 48 / per_q;
-    return q >= 8 ? 8 : (q >= 6 ? 6 : (q >= 4 ? 4 : (q >= 2 ? 2 : 1)));
+    constexpr int per_q = NV * (int)sizeof(T) / 4 + 2;
+    constexpr int q = 40 / per_q;
+    return q >= 12 ? 12 : (q >= 10 ? 10 : (q >= 8 ? 8 : (q >= 6 ? 6 : (q >= 4 ? 4 : (q >= 2 ? 2 : 1)))));
 }
 
 template <class T, int NV>
@@ -447,7 +455,7 @@ hipError_t alpha_beta(AbArgs<T> A, const T* c, T* y, const SigmaTune& tune, hipS
     // column passes (each restages the ket rows), columns spread evenly over them
     const int64_t passes = (A.nb + (int64_t)threads * QM - 1) / ((int64_t)threads * QM);
     const int64_t per = (A.nb + passes * threads - 1) / (passes * threads);  // columns per thread
-    constexpr int steps[5] = {1, 2, 4, 6, 8};
+    constexpr int steps[7] = {1, 2, 4, 6, 8, 10, 12};
     int Q = 1;
     for (int s : steps)
         if (s <= QM) {
@@ -476,15 +484,21 @@ hipError_t alpha_beta(AbArgs<T> A, const T* c, T* y, const SigmaTune& tune, hipS
         case 2: return ab_launch<T, NV, (QM < 2 ? QM : 2)>(A, c, y, threads, lds, passes, st);
         case 4: return ab_launch<T, NV, (QM < 4 ? QM : 4)>(A, c, y, threads, lds, passes, st);
         case 6: return ab_launch<T, NV, (QM < 6 ? QM : 6)>(A, c, y, threads, lds, passes, st);
+        case 8: return ab_launch<T, NV, (QM < 8 ? QM : 8)>(A, c, y, threads, lds, passes, st);
+        case 10: return ab_launch<T, NV, (QM < 10 ? QM : 10)>(A, c, y, threads, lds, passes, st);
         default: return ab_launch<T, NV, QM>(A, c, y, threads, lds, passes, st);
     }
 }
 
+// Optional per-stage timing: events[0..5] recorded around the five launches.
 template <class T, int NV>
 hipError_t sigma_nv(const SigmaArgs<T>& A, const T* c, T* y, T* cT, T* yT, const SigmaTune& tune,
-                    hipStream_t st) {
+                    hipStream_t st, hipEvent_t* ev) {
     const int64_t na = A.na, nb = A.nb;
-    hipError_t e = transpose<T, NV, false>(c, cT, na, nb, st);
+    auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
+    hipError_t e = mark(0);
+    if (e == hipSuccess) e = transpose<T, NV, false>(c, cT, na, nb, st);
+    if (e == hipSuccess) e = mark(1);
     if (e != hipSuccess) return e;
     StreamArgs<T> Sa{};
     Sa.nrow = na; Sa.ncol = nb;
@@ -492,6 +506,7 @@ hipError_t sigma_nv(const SigmaArgs<T>& A, const T* c, T* y, T* cT, T* yT, const
     Sa.p2 = A.a2p; Sa.J2 = A.a2J; Sa.c2 = A.a2c;
     Sa.G = A.Gb; Sa.diag = A.diag; Sa.shift = A.shift;
     e = stream<T, NV>(Sa, c, y, tune, st);
+    if (e == hipSuccess) e = mark(2);
     if (e != hipSuccess) return e;
     StreamArgs<T> Sb{};
     Sb.nrow = nb; Sb.ncol = na;
@@ -499,13 +514,18 @@ hipError_t sigma_nv(const SigmaArgs<T>& A, const T* c, T* y, T* cT, T* yT, const
     Sb.p2 = A.b2p; Sb.J2 = A.b2J; Sb.c2 = A.b2c;
     Sb.G = A.Ga; Sb.diag = nullptr; Sb.shift = 0.0;
     e = stream<T, NV>(Sb, cT, yT, tune, st);
+    if (e == hipSuccess) e = mark(3);
     if (e != hipSuccess) return e;
     AbArgs<T> B{};
     B.na = na; B.nb = nb; B.norb = A.norb;
-    B.a1p = A.a1p; B.a1pack = A.a1pack; B.b1p = A.b1p; B.b1pack = A.b1pack; B.eri = A.eri;
+    B.a1p = A.a1p; B.a1pack = A.a1pack; B.b1sell = A.b1sell; B.b1sell_off = A.b1sell_off;
+    B.eri = A.eri;
     e = alpha_beta<T, NV>(B, c, y, tune, st);
+    if (e == hipSuccess) e = mark(4);
     if (e != hipSuccess) return e;
-    return transpose<T, NV, true>(yT, y, nb, na, st);
+    e = transpose<T, NV, true>(yT, y, nb, na, st);
+    if (e == hipSuccess) e = mark(5);
+    return e;
 }
 
 }  // namespace
@@ -517,7 +537,7 @@ size_t sigma_workspace_bytes(int64_t N, int nvec, int layout, size_t elem) {
 
 template <class T>
 hipError_t launch_sigma(const SigmaArgs<T>& A, int nvec, const T* c, T* y, int layout, void* ws,
-                        const SigmaTune& tune, hipStream_t st) {
+                        const SigmaTune& tune, hipStream_t st, hipEvent_t* ev) {
     if (A.na == 0 || A.nb == 0) return hipSuccess;
     const int64_t N = A.na * A.nb;
     const int nv = layout == 0 ? 1 : nvec;
@@ -525,23 +545,23 @@ hipError_t launch_sigma(const SigmaArgs<T>& A, int nvec, const T* c, T* y, int l
     T* yT = cT + (size_t)N * nv;
     if (layout == 0) {
         for (int v = 0; v < nvec; ++v) {
-            hipError_t e = sigma_nv<T, 1>(A, c + v * N, y + v * N, cT, yT, tune, st);
+            hipError_t e = sigma_nv<T, 1>(A, c + v * N, y + v * N, cT, yT, tune, st, v == 0 ? ev : nullptr);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     }
     switch (nvec) {
-        case 1: return sigma_nv<T, 1>(A, c, y, cT, yT, tune, st);
-        case 2: return sigma_nv<T, 2>(A, c, y, cT, yT, tune, st);
-        case 4: return sigma_nv<T, 4>(A, c, y, cT, yT, tune, st);
-        case 8: return sigma_nv<T, 8>(A, c, y, cT, yT, tune, st);
+        case 1: return sigma_nv<T, 1>(A, c, y, cT, yT, tune, st, ev);
+        case 2: return sigma_nv<T, 2>(A, c, y, cT, yT, tune, st, ev);
+        case 4: return sigma_nv<T, 4>(A, c, y, cT, yT, tune, st, ev);
+        case 8: return sigma_nv<T, 8>(A, c, y, cT, yT, tune, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
 
 template hipError_t launch_sigma<double>(const SigmaArgs<double>&, int, const double*, double*,
-                                         int, void*, const SigmaTune&, hipStream_t);
+                                         int, void*, const SigmaTune&, hipStream_t, hipEvent_t*);
 template hipError_t launch_sigma<float>(const SigmaArgs<float>&, int, const float*, float*, int,
-                                        void*, const SigmaTune&, hipStream_t);
+                                        void*, const SigmaTune&, hipStream_t, hipEvent_t*);
 
 }  // namespace sbd

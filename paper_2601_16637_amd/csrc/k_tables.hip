@@ -223,6 +223,38 @@ __global__ void k_pack_singles(int64_t nnz, const int32_t* __restrict__ J,
               ((uint64_t)((o >> 8) & 255) << 40) | ((uint64_t)(sg[e] < 0 ? 1 : 0) << 48);
 }
 
+// Sliced-ELL copy of a singles table: slices of 64 consecutive strings, each
+// padded to its longest row and stored slot-major (entry s of the slice's 64
+// rows is contiguous), so one wavefront reading entry s of 64 consecutive
+// columns issues one coalesced load.  Padding entries are ~0.
+__global__ void k_sell_len(const int64_t* __restrict__ rp, int64_t n, int64_t nslice,
+                           int64_t* slots) {
+    const int64_t sl = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (sl >= nslice) return;
+    const int64_t i = sl * 64 + lane;
+    int len = (i < n) ? (int)(rp[i + 1] - rp[i]) : 0;
+    for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(len, off, 64);
+        len = o > len ? o : len;
+    }
+    if (lane == 0) slots[sl] = (int64_t)len * 64;
+}
+
+__global__ void k_sell_fill(const int64_t* __restrict__ rp, const uint64_t* __restrict__ pack,
+                            int64_t n, int64_t nslice, const int64_t* __restrict__ off,
+                            uint64_t* sell) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nslice * 64) return;
+    const int64_t sl = g >> 6;
+    const int lane = (int)(g & 63);
+    const int64_t len = (off[sl + 1] - off[sl]) / 64;
+    const int64_t i = g;
+    const int64_t r0 = (i < n) ? rp[i] : 0, rl = (i < n) ? rp[i + 1] - rp[i] : 0;
+    for (int64_t s = 0; s < len; ++s)
+        sell[off[sl] + s * 64 + lane] = (s < rl) ? pack[r0 + s] : ~0ull;
+}
+
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -265,6 +297,23 @@ hipError_t launch_exc_fill(const uint64_t* d_s, int64_t n, const int64_t* rp1, c
                            int8_t* sg2, hipStream_t st) {
     hipLaunchKernelGGL(k_exc_fill, dim3(blocks_for(n, kExcWaves)), dim3(kExcWaves * 64), 0, st,
                        d_s, n, rp1, rp2, J1, orb1, sg1, J2, orb2, sg2);
+    return hipGetLastError();
+}
+
+hipError_t launch_sell_len(const int64_t* rp, int64_t n, int64_t* slots, hipStream_t st) {
+    const int64_t nslice = (n + 63) / 64;
+    if (nslice > 0)
+        hipLaunchKernelGGL(k_sell_len, dim3(blocks_for(nslice, 4)), dim3(256), 0, st, rp, n, nslice,
+                           slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_sell_fill(const int64_t* rp, const uint64_t* pack, int64_t n, const int64_t* off,
+                            uint64_t* sell, hipStream_t st) {
+    const int64_t nslice = (n + 63) / 64;
+    if (nslice > 0)
+        hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(nslice * 64, 256)), dim3(256), 0, st, rp,
+                           pack, n, nslice, off, sell);
     return hipGetLastError();
 }
 
