@@ -181,8 +181,8 @@ int sbd_sigma_timed(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h,
 
 /*
  * Tall-skinny projection out = A^T X (the Gram-Schmidt / Rayleigh-Ritz
- * projections of the Davidson update, Sec. II-C), computed on the FP64 matrix
- * cores.  A: ma device vectors of N doubles at A + j*N (1 <= ma <= 48);
+ * projections of the Davidson update, Sec. II-C), one HBM sweep per row group
+ * on the FP64 vector units.  A: ma device vectors of N doubles at A + j*N (1 <= ma <= 48);
  * X: k device vectors at X + q*N (1 <= k <= 8).  out: host array of ma*k
  * doubles, out[j*k + q] = A_j . X_q, summed in a fixed order (deterministic).
  * Synchronises the stream.  Errors: SBD_ERR_ARG, SBD_ERR_NOMEM, SBD_ERR_HIP.
@@ -209,7 +209,9 @@ typedef struct {
     int sigma_calls;       /* sigma applications (vectors)                                          */
     int sigma_calls_fp64;  /* of which in FP64                                                      */
     int converged;         /* 1 if every root met tol_residual                                      */
-    int restarts;
+    int restarts;          /* thick restarts (subspace full)                                        */
+    int refinements;       /* SBD_FP32: FP64 refreshes of the Ritz basis                            */
+    double fp32_error_scale; /* SBD_FP32: calibrated ||sigma32(v) - sigma64(v)|| per unit vector    */
     double residual[64];   /* final ||r||_2 per root                                                */
     double ortho_loss;     /* ||V^T V - I||_F at exit                                               */
     double t_sigma_ms, t_update_ms, t_total_ms;
@@ -239,6 +241,67 @@ void sbd_davidson_default_opts(sbd_davidson_opts* o);
 int sbd_davidson(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h, int nroots,
                  const sbd_davidson_opts* opts, double* energies, double* vectors,
                  sbd_davidson_report* report, void* stream);
+
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of whole solves (one SQD iteration each: the classical
+ * diagonalisation that follows every sampling round, Sec. I and Sec. II).
+ * A server owns one device slab of hbm_budget_bytes and max_inflight worker
+ * threads, each with its own HIP stream (default priority).  A submitted
+ * request is copied, queued in arrival order, and admitted when a worker is
+ * free and a contiguous region of its estimated size (sbd_serve_estimate) is
+ * free in the slab; every device buffer of the request (basis, tables,
+ * Hamiltonian, Davidson vectors) is carved from that region, so requests run
+ * concurrently on the device with their vectors resident, and no device
+ * allocation or free happens on the serving path.  The region returns to the
+ * slab after the request's stream has synchronised.  A request's results do
+ * not depend on what else runs (every kernel is deterministic and uses only
+ * its own region), except through opts.use_autotune, which times launches.
+ */
+typedef struct sbd_server sbd_server;
+
+typedef struct {
+    int norb, n_alpha, n_beta;
+    const uint64_t* alpha_strings; /* host, n_alpha_in strings, any order, duplicates allowed */
+    int64_t n_alpha_in;
+    const uint64_t* beta_strings;  /* host */
+    int64_t n_beta_in;
+    const double* h1;              /* host, norb*norb */
+    const double* eri;             /* host, norb^4, chemists' (pq|rs) */
+    double e_core;
+    int nroots;                    /* 1..8 */
+    sbd_davidson_opts opts;        /* opts.guess must be NULL */
+} sbd_request;
+
+typedef struct {
+    int status;                    /* status of the solve (or of the first step that failed) */
+    char message[256];             /* sbd_last_error() of the worker when status < 0 */
+    double energies[8];
+    sbd_davidson_report report;
+    int64_t ndet;                  /* N of the request's basis */
+    double queue_ms;               /* submit -> admission */
+    double run_ms;                 /* admission -> result */
+    double latency_ms;             /* submit -> result */
+    double admit_at_ms, done_at_ms;  /* admission and completion, ms since the server was created */
+    size_t region_bytes;           /* reserved for the request */
+    size_t peak_bytes;             /* actually carved from the region */
+} sbd_result;
+
+/* Upper bound on the device bytes one request needs (its region size).
+ * Errors: SBD_ERR_ARG. */
+int sbd_serve_estimate(const sbd_request* req, size_t* bytes);
+/* Allocates the slab (hbm_budget_bytes) and starts max_inflight (1..64)
+ * workers on the current device.  Errors: SBD_ERR_ARG, SBD_ERR_NOMEM, SBD_ERR_HIP. */
+int sbd_serve_create(size_t hbm_budget_bytes, int max_inflight, sbd_server** out);
+/* Copies the request's host arrays and queues it; *ticket identifies it.
+ * Errors: SBD_ERR_ARG (bad request), SBD_ERR_NOMEM (its estimate exceeds the
+ * budget, so it could never be admitted), SBD_ERR_STATE (server stopping). */
+int sbd_serve_submit(sbd_server* s, const sbd_request* req, uint64_t* ticket);
+/* Blocks until the request has finished and moves its result to *out (each
+ * ticket can be waited once).  Returns SBD_OK or SBD_ERR_ARG (unknown ticket). */
+int sbd_serve_wait(sbd_server* s, uint64_t ticket, sbd_result* out);
+/* Finishes the running requests, fails the queued ones, joins the workers and
+ * frees the slab.  Results not yet waited for are discarded. */
+void sbd_serve_destroy(sbd_server* s);
 
 #ifdef __cplusplus
 }

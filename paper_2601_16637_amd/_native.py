@@ -28,7 +28,8 @@ EXPORTED = ["sbd_last_error", "sbd_version", "sbd_build_basis", "sbd_basis_sizes
             "sbd_basis_strings", "sbd_free_basis", "sbd_build_excitations", "sbd_exc_count",
             "sbd_exc_export", "sbd_free_exc", "sbd_set_hamiltonian", "sbd_ham_diag",
             "sbd_free_ham", "sbd_sigma", "sbd_sigma_timed", "sbd_autotune", "sbd_get_tune", "sbd_set_tune", "sbd_gram",
-            "sbd_davidson_default_opts", "sbd_davidson"]
+            "sbd_davidson_default_opts", "sbd_davidson", "sbd_serve_estimate", "sbd_serve_create",
+            "sbd_serve_submit", "sbd_serve_wait", "sbd_serve_destroy"]
 
 
 class SBDError(RuntimeError):
@@ -48,7 +49,8 @@ class DavidsonOpts(ctypes.Structure):
 class DavidsonReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("sigma_calls", ctypes.c_int),
                 ("sigma_calls_fp64", ctypes.c_int), ("converged", ctypes.c_int),
-                ("restarts", ctypes.c_int), ("residual", ctypes.c_double * 64),
+                ("restarts", ctypes.c_int), ("refinements", ctypes.c_int),
+                ("fp32_error_scale", ctypes.c_double), ("residual", ctypes.c_double * 64),
                 ("ortho_loss", ctypes.c_double), ("t_sigma_ms", ctypes.c_double),
                 ("t_update_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("n_history", ctypes.c_int), ("theta_history", ctypes.c_double * 512),
@@ -58,11 +60,30 @@ class DavidsonReport(ctypes.Structure):
         n = self.n_history
         return dict(iterations=self.iterations, sigma_calls=self.sigma_calls,
                     sigma_calls_fp64=self.sigma_calls_fp64, converged=bool(self.converged),
-                    restarts=self.restarts, residual=list(self.residual[:nroots]),
+                    restarts=self.restarts, refinements=self.refinements,
+                    fp32_error_scale=self.fp32_error_scale,
+                    residual=list(self.residual[:nroots]),
                     ortho_loss=self.ortho_loss, t_sigma_ms=self.t_sigma_ms,
                     t_update_ms=self.t_update_ms, t_total_ms=self.t_total_ms,
                     theta_history=list(self.theta_history[:n]),
                     time_history_ms=list(self.time_history_ms[:n]))
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("norb", ctypes.c_int), ("n_alpha", ctypes.c_int), ("n_beta", ctypes.c_int),
+                ("alpha_strings", ctypes.c_void_p), ("n_alpha_in", ctypes.c_int64),
+                ("beta_strings", ctypes.c_void_p), ("n_beta_in", ctypes.c_int64),
+                ("h1", ctypes.c_void_p), ("eri", ctypes.c_void_p), ("e_core", ctypes.c_double),
+                ("nroots", ctypes.c_int), ("opts", DavidsonOpts)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("message", ctypes.c_char * 256),
+                ("energies", ctypes.c_double * 8), ("report", DavidsonReport),
+                ("ndet", ctypes.c_int64), ("queue_ms", ctypes.c_double),
+                ("run_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
+                ("admit_at_ms", ctypes.c_double), ("done_at_ms", ctypes.c_double),
+                ("region_bytes", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -106,9 +127,15 @@ def load():
     L.sbd_davidson_default_opts.restype = None
     L.sbd_davidson.argtypes = [P, P, P, i32, ctypes.POINTER(DavidsonOpts), P, P,
                                ctypes.POINTER(DavidsonReport), P]
+    L.sbd_serve_estimate.argtypes = [ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_size_t)]
+    L.sbd_serve_create.argtypes = [ctypes.c_size_t, i32, PP]
+    L.sbd_serve_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.sbd_serve_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
+    L.sbd_serve_destroy.argtypes = [P]
+    L.sbd_serve_destroy.restype = None
     for name in EXPORTED:
         if name not in ("sbd_last_error", "sbd_version", "sbd_free_basis", "sbd_free_exc",
-                        "sbd_free_ham", "sbd_davidson_default_opts"):
+                        "sbd_free_ham", "sbd_davidson_default_opts", "sbd_serve_destroy"):
             getattr(L, name).restype = i32
     _lib = L
     return L
@@ -302,3 +329,66 @@ def davidson(ham: Hamiltonian, nroots: int = 1, vectors=None, stream=None, **kw)
                                    ctypes.byref(o), _host(e), _dptr(vectors), ctypes.byref(rep),
                                    _stream(stream)))
     return e, rep.as_dict(nroots), st
+
+
+def _opts(**kw) -> DavidsonOpts:
+    o = default_opts()
+    for k, v in kw.items():
+        if not hasattr(o, k) or k == "guess":
+            raise TypeError(f"unknown or unsupported option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _request(norb, n_alpha, n_beta, alpha, beta, h1, eri, e_core, nroots, **opts):
+    a = np.ascontiguousarray(alpha, dtype=np.uint64)
+    b = np.ascontiguousarray(beta, dtype=np.uint64)
+    h = np.ascontiguousarray(h1, dtype=np.float64)
+    g = np.ascontiguousarray(eri, dtype=np.float64)
+    if h.size != norb * norb or g.size != norb ** 4:
+        raise ValueError("integral arrays have the wrong size for norb")
+    q = Request(int(norb), int(n_alpha), int(n_beta), _host(a), a.size, _host(b), b.size,
+                _host(h), _host(g), float(e_core), int(nroots), _opts(**opts))
+    return q, (a, b, h, g)  # the arrays must outlive the call that reads them
+
+
+def serve_estimate(norb, n_alpha, n_beta, alpha, beta, h1, eri, e_core, nroots, **opts) -> int:
+    """Device bytes a request reserves in a server's slab (sbd_serve_estimate)."""
+    q, keep = _request(norb, n_alpha, n_beta, alpha, beta, h1, eri, e_core, nroots, **opts)
+    n = ctypes.c_size_t()
+    check(load().sbd_serve_estimate(ctypes.byref(q), ctypes.byref(n)))
+    return n.value
+
+
+class Server:
+    """Continuous-batching solve server (sbd_serve_*): one HBM slab, several
+    worker streams; requests are admitted in arrival order as workers and
+    slab space free up."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 4):
+        h = ctypes.c_void_p()
+        check(load().sbd_serve_create(int(hbm_budget_bytes), int(max_inflight), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, norb, n_alpha, n_beta, alpha, beta, h1, eri, e_core, nroots=1, **opts) -> int:
+        q, keep = _request(norb, n_alpha, n_beta, alpha, beta, h1, eri, e_core, nroots, **opts)
+        t = ctypes.c_uint64()
+        check(load().sbd_serve_submit(self._h, ctypes.byref(q), ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int) -> dict:
+        r = Result()
+        check(load().sbd_serve_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(r)))
+        return dict(status=r.status, message=r.message.decode(errors="replace"),
+                    energies=np.array(r.energies[:8]), report=r.report.as_dict(8), ndet=r.ndet,
+                    queue_ms=r.queue_ms, run_ms=r.run_ms, latency_ms=r.latency_ms,
+                    admit_at_ms=r.admit_at_ms, done_at_ms=r.done_at_ms,
+                    region_bytes=r.region_bytes, peak_bytes=r.peak_bytes)
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.sbd_serve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

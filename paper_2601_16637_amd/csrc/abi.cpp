@@ -96,8 +96,9 @@ int sbd_build_basis(int norb, int n_alpha, int n_beta, const uint64_t* alpha_str
         if (e == hipSuccess) {
             b->s[s].n = count;
             b->s[s].host.resize(count);
-            e = hipMemcpy(b->s[s].host.data(), b->s[s].d.p, sizeof(uint64_t) * count,
-                          hipMemcpyDeviceToHost);
+            e = hipMemcpyAsync(b->s[s].host.data(), b->s[s].d.p, sizeof(uint64_t) * count,
+                               hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
         }
         if (e != hipSuccess) {
             delete b;

@@ -19,11 +19,17 @@
 // SBD_FP32 mode (mixed precision): sigma of new basis vectors is computed in
 // FP32 on (H - shift I), shift = lowest diagonal element, and restored in
 // FP64; everything else stays FP64.  Residual-correction refinement: the start
-// vectors get an FP64 sigma, so the first residuals are exact.  When the inner
-// residuals (which carry the FP32 sigma error) reach the target, drop well
-// below the last exact value, stop improving, or the subspace is full, the
-// subspace collapses onto the Ritz vectors and their sigma is recomputed in
-// FP64; convergence is only declared on such exact residuals.
+// vectors get an FP64 sigma, so the first residuals are exact.  Every basis
+// vector carries a bound e_j on the error of its sigma (0 for FP64, rho for
+// FP32, with rho = ||sigma32(v) - sigma64(v)|| per unit vector), and a
+// combination z carries sqrt(sum_j (z_j e_j)^2).  A Ritz vector made mostly of
+// exact directions plus small FP32 corrections thus has a small error even
+// though each FP32 sigma is only good to ~1e-7 relative.  The subspace is
+// refreshed (collapsed onto the Ritz vectors, their sigma recomputed in FP64)
+// only when the inner residuals reach the target, when a root's error bound
+// exceeds a fifth of its residual, or when the residual stops improving.  Each
+// refresh measures the true error of the collapsed sigma and rescales rho to
+// it.  Convergence is only declared on exact (all-FP64) residuals.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -115,8 +121,10 @@ constexpr int kTheta = 1088;  // Ritz values (<= 8)
 constexpr int kYc = 1152;     // collapse coefficients, m x keep (<= 48 x 16)
 constexpr int kProj = 2048;   // projection results (<= 48 x 8)
 constexpr int kMisc = 3072;   // argmin value
+constexpr int kOne = 3080;    // the constant 1.0 (Gram-Schmidt coefficient of a difference)
+constexpr int kDiff = 3096;   // |sigma32 - sigma64|^2 rows of a refresh (2 per vector, <= 16 vectors)
 constexpr int kSmall = 4096;
-constexpr int kPartRows = 512;
+constexpr int kPartRows = kPassRows;
 
 struct Solver {
     const sbd_exc* x;
@@ -328,6 +336,21 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         }
     }
 
+    // FP32 sigma error per unit vector: start from 2^-24 max|H_ii - shift|, the
+    // rounding of the dominant diagonal term; refreshes calibrate it
+    double rho = 0.0;
+    if (S.mixed) {
+        SBD_HIP(launch_max(diag, N, sm + kMisc, part, st));
+        double dmax = 0.0;
+        const double one = 1.0;
+        SBD_HIP(hipMemcpyAsync(&dmax, sm + kMisc, sizeof(double), hipMemcpyDeviceToHost, st));
+        SBD_HIP(hipMemcpyAsync(sm + kOne, &one, sizeof(double), hipMemcpyHostToDevice, st));
+        SBD_HIP(hipStreamSynchronize(st));
+        rho = std::ldexp(std::max(dmax - S.shift, 1.0), -24);
+    }
+    std::vector<double> ebound(ms + 8, 0.0);  // error bound of each basis vector's sigma
+    int refinements = 0;
+
     // ---- initial subspace: guesses, then unit vectors, orthonormalised
     int m = 0;
     auto add_start = [&](const double* src, int64_t unit) -> int {
@@ -369,9 +392,10 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     std::vector<double> evals, Z;
     int it = 0;
     bool converged = false;
-    double last_true_r = INFINITY, best_inner = INFINITY;
+    double best_inner = INFINITY;
     int since_cert = 0;
     bool certified = true;  // residuals computed from an all-FP64 W
+    std::vector<double> ebnd(k, 0.0);
     int hist_n = 0;
     std::vector<double> hist_theta, hist_time;
     int status = SBD_OK;
@@ -383,9 +407,16 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
             for (int j = 0; j < m; ++j) Tm[i * m + j] = 0.5 * (T[i * ms + j] + T[j * ms + i]);
         jacobi_eigh(m, Tm, evals, Z);
         for (int r = 0; r < k; ++r) theta[r] = evals[r];
+        // error bound of each Ritz vector's sigma; exact when it is zero
+        certified = true;
+        for (int r = 0; r < k; ++r) {
+            double s2 = 0.0;
+            for (int j = 0; j < m; ++j) s2 += (Z[j * m + r] * ebound[j]) * (Z[j * m + r] * ebound[j]);
+            ebnd[r] = std::sqrt(s2);
+            certified = certified && ebnd[r] == 0.0;
+        }
         // fused residual / preconditioner for all roots with the first projections V^T t_q
-        const bool rproj = pass_fits(m, k);  // else each t_q is projected on its own
-        std::vector<double> red(2 * k + (rproj ? (size_t)m * k : 0));
+        std::vector<double> red(2 * k + (size_t)m * k);
         {
             std::vector<double> Y((size_t)m * k);
             for (int j = 0; j < m; ++j)
@@ -393,7 +424,7 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
             SBD_HIP(hipMemcpyAsync(sm + kY, Y.data(), sizeof(double) * m * k, hipMemcpyHostToDevice, st));
             SBD_HIP(hipMemcpyAsync(sm + kTheta, theta.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
             SBD_HIP(pass_resid(S.V.as<double>(), S.W.as<double>(), m, k, sm + kY, sm + kTheta, diag,
-                               o.precond_delta, tmp, N, rproj, part, sm + kRed, st));
+                               o.precond_delta, tmp, N, true, part, sm + kRed, st));
             SBD_HIP(hipMemcpyAsync(red.data(), sm + kRed, sizeof(double) * red.size(), hipMemcpyDeviceToHost, st));
             SBD_HIP(hipStreamSynchronize(st));
             for (int q = 0; q < k; ++q) {
@@ -423,32 +454,57 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         const double rmax = *std::max_element(rnorm.begin(), rnorm.end());
         bool refine = false;
         if (certified) {
-            last_true_r = rmax;
             best_inner = INFINITY;
             since_cert = 0;
         } else {
             ++since_cert;
             const bool stagnant = since_cert >= 3 && rmax > 0.7 * best_inner;
-            refine = inner_conv || rmax <= 0.1 * last_true_r || stagnant || (m + k > ms);
+            bool err_dominated = false;
+            for (int r = 0; r < k; ++r)
+                err_dominated = err_dominated || (rnorm[r] > o.tol_residual && ebnd[r] > 0.2 * rnorm[r]);
+            refine = inner_conv || err_dominated || stagnant;
             best_inner = std::min(best_inner, rmax);
         }
         if (S.mixed && refine) {
-            // collapse onto the Ritz vectors and recompute their sigma in FP64
+            // collapse onto the Ritz vectors and recompute their sigma in FP64;
+            // the collapsed mixed sigma (kept in tmp) calibrates rho
             auto tr0 = clk::now();
             const int kk = std::min(S.keep, m);
-            rc = S.collapse(Z, m, kk, false);
+            std::vector<double> pred(kk, 0.0);
+            for (int c = 0; c < kk; ++c) {
+                double s2 = 0.0;
+                for (int j = 0; j < m; ++j) s2 += (Z[j * m + c] * ebound[j]) * (Z[j * m + c] * ebound[j]);
+                pred[c] = std::sqrt(s2);
+            }
+            rc = S.collapse(Z, m, kk, false);  // also leaves the coefficients at sm + kYc
             if (rc) return rc;
+            SBD_HIP(launch_combination(S.W.as<double>(), m, sm + kYc, kk, kk, tmp, N, st));
             m = kk;
             t_update += ms_since(tr0);
             rc = S.apply_sigma(0, m, true);
             if (rc) return rc;
             auto tr1 = clk::now();
+            std::vector<double> dif(2 * kk);
+            for (int c = 0; c < kk; ++c)
+                SBD_HIP(pass_sub1(S.Wr(c), 1, sm + kOne, tmp + (size_t)c * N, N, part, sm + kDiff + 2 * c, st));
+            SBD_HIP(hipMemcpyAsync(dif.data(), sm + kDiff, sizeof(double) * 2 * kk, hipMemcpyDeviceToHost, st));
+            SBD_HIP(hipStreamSynchronize(st));
+            double amax = 0.0, pmax = 0.0;
+            for (int c = 0; c < kk; ++c) {
+                amax = std::max(amax, std::sqrt(std::max(dif[2 * c], 0.0)));
+                pmax = std::max(pmax, pred[c]);
+            }
+            if (pmax > 0.0 && std::isfinite(amax))
+                rho *= std::min(1e3, std::max(1e-3, amax / pmax));
+            for (int c = 0; c < ms + 8; ++c) ebound[c] = 0.0;
             std::fill(T.begin(), T.end(), 0.0);
             rc = S.rebuild_T(m, T);
             if (rc) return rc;
             t_update += ms_since(tr1);
-            ++restarts;
-            certified = true;
+            ++refinements;
+            if (o.verbose)
+                std::fprintf(stderr, "[sbd] refresh: sigma32 error %.3e (bound %.3e), rho %.3e\n", amax,
+                             pmax, rho);
             continue;
         }
 
@@ -456,10 +512,17 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         int nnew = 0;
         for (int r = 0; r < k; ++r)
             if (rnorm[r] > o.tol_residual) ++nnew;
-        bool h1_valid = rproj;  // the residual pass projected every t_q on V[0..m)
+        bool h1_valid = true;  // the residual pass projected every t_q on V[0..m)
         if (m + nnew > ms) {
             // thick restart: V <- V Y_keep, W <- W Y_keep, T <- diag(theta)
             const int kk = std::min(S.keep, m);
+            std::vector<double> en(kk, 0.0);
+            for (int c = 0; c < kk; ++c) {
+                double s2 = 0.0;
+                for (int j = 0; j < m; ++j) s2 += (Z[j * m + c] * ebound[j]) * (Z[j * m + c] * ebound[j]);
+                en[c] = std::sqrt(s2);
+            }
+            for (int c = 0; c < ms + 8; ++c) ebound[c] = c < kk ? en[c] : 0.0;
             rc = S.collapse(Z, m, kk, true);
             if (rc) return rc;
             std::fill(T.begin(), T.end(), 0.0);
@@ -499,7 +562,7 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         }
         rc = S.apply_sigma(m_old, m - m_old, false);
         if (rc) return rc;
-        if (S.mixed) certified = false;
+        for (int j = m_old; j < m; ++j) ebound[j] = S.mixed ? rho : 0.0;
         auto tu2 = clk::now();
         // T entries among the new vectors: V_new^T W_new (one pass)
         {
@@ -541,6 +604,8 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         report->sigma_calls_fp64 = S.sigma64;
         report->converged = converged ? 1 : 0;
         report->restarts = restarts;
+        report->refinements = refinements;
+        report->fp32_error_scale = S.mixed ? rho : 0.0;
         for (int r = 0; r < 64; ++r) report->residual[r] = r < k ? rnorm[r] : 0.0;
         report->ortho_loss = std::sqrt(ortho);
         report->t_sigma_ms = S.t_sigma;

@@ -26,10 +26,25 @@ int hip_fail(hipError_t e, const char* what);
         if (e_ != hipSuccess) return ::sbd::hip_fail(e_, #call); \
     } while (0)
 
+// Region of a serving slab that one request allocates from (serve.cpp).  While
+// a thread has a region installed, every DevBuf it allocates is carved from the
+// region by a bump pointer and released with it when the request has finished
+// (after its stream synchronised), so the serving path never calls hipMalloc
+// or hipFree, and hipFree's device-wide synchronisation never stalls other
+// requests' work.
+struct Region {
+    char* base = nullptr;
+    size_t size = 0;
+    size_t used = 0;  // bump pointer
+    size_t peak = 0;
+};
+Region* current_region();
+
 // Device buffer owned by a handle.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool regional = false;  // carved from a serving region: nothing to free here
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
@@ -38,12 +53,25 @@ struct DevBuf {
         release();
         bytes = n;
         if (n == 0) return hipSuccess;
+        if (Region* r = current_region()) {
+            const size_t off = (r->used + 255) & ~size_t(255);
+            if (off + n > r->size) {
+                bytes = 0;
+                return hipErrorOutOfMemory;
+            }
+            p = r->base + off;
+            r->used = off + n;
+            if (r->used > r->peak) r->peak = r->used;
+            regional = true;
+            return hipSuccess;
+        }
         return hipMalloc(&p, n);
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !regional) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        regional = false;
     }
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
@@ -209,6 +237,8 @@ hipError_t launch_argmin_after(const double* v, int64_t N, double vprev, int64_t
                                double* d_val, int64_t* d_idx, double* d_part_v,
                                int64_t* d_part_i, hipStream_t st);
 hipError_t launch_set_unit(double* x, int64_t N, int64_t idx, hipStream_t st);
+// *d_val = max_i v[i]; d_part holds kRedBlocks partials
+hipError_t launch_max(const double* v, int64_t N, double* d_val, double* d_part, hipStream_t st);
 
 hipError_t launch_fill_pattern(void* p, int64_t n, int prec, hipStream_t st);
 hipError_t launch_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
@@ -216,9 +246,8 @@ hipError_t launch_f32_to_f64_axpy(const float* y32, const double* x, double shif
                                   int64_t n, hipStream_t st);
 
 // Tall-skinny passes of the Davidson update (k_project.hip).  Each reduces its
-// rows into out (device) in a fixed order; part holds rows x 1024 partials.
-// pass_fits(mp, k): whether mp rows x k outputs fit one pass's register budget.
-bool pass_fits(int mp, int k);
+// rows into out (device) in a fixed order; part holds kPassRows x kRedBlocks
+// partials.  m, mp, mw <= 48 and k <= 8.
 // pass_resid rows: [0,k) |r_q|^2, [k,2k) |t_q|^2, then (proj) [2k + j*k + q) V_j . t_q
 hipError_t pass_resid(const double* V, const double* W, int m, int k, const double* Y,
                       const double* theta, const double* diag, double delta, double* T, int64_t N,
@@ -235,5 +264,6 @@ hipError_t pass_project(const double* P, int mp, const double* X, int k, int64_t
 
 // Reduction scratch sizing.
 constexpr int kRedBlocks = 1024;
+constexpr int kPassRows = 512;
 
 }  // namespace sbd

@@ -1,36 +1,44 @@
 // Tall-skinny passes of the Davidson update (Sec. II-C).
 //
-// Every pass walks the N determinants in tiles of 256 (one element per
-// thread).  An elementwise phase computes up to eight output vectors for the
-// tile (residual + damped preconditioner, or a Gram-Schmidt subtraction
-// t - V h, or just loads the vectors to project) and stages them in LDS.  A
-// contraction phase then accumulates G += P[:, tile]^T out[tile, :]: wavefront
-// w owns the rows j = w, w+4, ... of P and re-reads them with one coalesced
-// 512-byte load per 64 determinants (the rows were just streamed by the
-// elementwise phase, so these loads hit L2), multiplying with the outputs in
-// LDS.  Each (row, output) accumulator lives in exactly one wavefront, so the
-// register budget is (rows per wave) x (outputs) and HBM sees every byte once.
+// Every pass is one sweep over the N determinants; each thread owns EPT
+// determinants per grid-stride step and keeps, in registers, the values of all
+// subspace rows it needs for them (at most MB rows, loaded back to back so a
+// wavefront has MB-deep memory-level parallelism).  From those registers it
+// computes the elementwise result (residual + damped preconditioner, or the
+// Gram-Schmidt subtraction t - V h, or just the vectors to project), writes
+// it, and accumulates the projections G[j][q] = P_j . out_q in registers.  HBM
+// sees every byte once; nothing is re-read and the sweep has no barrier.
 //
-// Each block writes its partial sums to part[row][block]; rows are reduced in a
-// fixed order afterwards (deterministic).  Row layout:
+// The projections are a tall-skinny product with at most eight columns: well
+// under one FP64 flop per byte of HBM traffic, so the pass is bound by HBM and
+// runs on the vector ALUs (on gfx950 the FP64 matrix-core peak is no higher
+// than the FP64 vector peak).
+//
+// Each block reduces its accumulators (wavefront shuffles, then the four
+// wavefronts in LDS in a fixed order) and writes part[row][block]; rows are
+// reduced across blocks in a fixed order afterwards, so results are bitwise
+// repeatable.  Row layout:
 //   [0, NR)              norms (mode dependent, see below)
 //   [NR + j*k + q)       G[j][q] = P_j . out_q   for j < mp, q < k
+// When a projection does not fit the register budget of a pass, the pass runs
+// without it and a separate projection pass fills the same rows.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace sbd {
 namespace {
 
-constexpr int kTB = 256;       // threads per block = determinants per tile
+constexpr int kTB = 256;       // threads per block
 constexpr int kMaxOut = 8;     // output vectors per pass
 
 enum Mode { RESID = 0, SUB1 = 1, SUB2 = 2, PROJ = 3 };
 
 struct PassArgs {
     int64_t N;
-    int mode;
-    int m;            // rows of V used by the elementwise phase
+    int m;            // rows of V combined elementwise (RESID, SUB1, SUB2)
     int k;            // output vectors
-    int mp;           // rows of the projected matrix P
+    int mp;           // rows of the projected matrix P (0: no projection)
     const double* V;  // subspace basis, row j at V + j*N
     const double* W;  // sigma of the basis
     const double* P;  // projected matrix (V or W or A)
@@ -49,123 +57,173 @@ __device__ __forceinline__ double damped_inv(double d, double delta) {
     return (d >= 0.0 ? 1.0 : -1.0) / den;
 }
 
-// JW = rows of P per wavefront (mp <= 4*JW), KO = outputs (k <= KO).
-template <int JW, int KO>
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+constexpr int ept_for(int mb) { return mb <= 8 ? 2 : 1; }
+
+// MODE: pass kind; MB: bound on rows held per determinant (m and mp <= MB);
+// KO: bound on outputs (k <= KO); PRJ: whether the pass accumulates projections.
+template <int MODE, int MB, int KO, bool PRJ>
 __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
-    __shared__ double ot[KO][kTB];          // outputs of the tile, [q][e]
-    __shared__ double cs[64 * kMaxOut];     // Y or h
-    __shared__ double th[kMaxOut];
-    __shared__ double nsum[4][2 * kMaxOut];
+    constexpr int EPT = ept_for(MB);
+    constexpr int NAJ = PRJ ? MB : 1;                  // accumulator rows
+    constexpr int NAQ = (MODE == RESID || MODE == PROJ) ? KO : 1;
+    __shared__ double red[4][2 * kMaxOut + MB * KO];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = A.m, k = A.k, mp = A.mp;
-    const int ncoef = (A.mode == RESID) ? m * k : ((A.mode == PROJ) ? 0 : m);
-    for (int i = tid; i < ncoef; i += kTB) cs[i] = A.coef[i];
-    if (A.mode == RESID && tid < k) th[tid] = A.theta[tid];
-    __syncthreads();
+    const int64_t N = A.N;
+    const double* __restrict__ cf = A.coef;
 
-    double acc[JW][KO];
+    double acc[NAJ][NAQ];
 #pragma unroll
-    for (int jj = 0; jj < JW; ++jj)
+    for (int j = 0; j < NAJ; ++j)
 #pragma unroll
-        for (int q = 0; q < KO; ++q) acc[jj][q] = 0.0;
+        for (int q = 0; q < NAQ; ++q) acc[j][q] = 0.0;
     double nrm[2 * KO];
 #pragma unroll
     for (int q = 0; q < 2 * KO; ++q) nrm[q] = 0.0;
+    double th[KO];
+#pragma unroll
+    for (int q = 0; q < KO; ++q) th[q] = (MODE == RESID && q < k) ? A.theta[q] : 0.0;
 
-    const int64_t N = A.N;
-    for (int64_t c0 = (int64_t)blockIdx.x * kTB; c0 < N; c0 += (int64_t)gridDim.x * kTB) {
-        const int64_t i = c0 + tid;
-        const bool in = i < N;
-        // ---- elementwise phase: one determinant per thread
-        if (A.mode == RESID) {
-            double vy[KO], wy[KO];
+    const int64_t step = (int64_t)gridDim.x * kTB * EPT;
+    for (int64_t base = (int64_t)blockIdx.x * kTB * EPT + tid; base < N; base += step) {
+        int64_t ix[EPT];
+        bool in[EPT];
 #pragma unroll
-            for (int q = 0; q < KO; ++q) vy[q] = wy[q] = 0.0;
-            if (in) {
-#pragma unroll 4
-                for (int j = 0; j < m; ++j) {
-                    const double vj = A.V[(size_t)j * N + i];
-                    const double wj = A.W[(size_t)j * N + i];
+        for (int u = 0; u < EPT; ++u) {
+            ix[u] = base + (int64_t)u * kTB;
+            in[u] = ix[u] < N;
+        }
+        if constexpr (MODE == RESID) {
+            double v[MB][EPT], w[MB][EPT], d[EPT];
 #pragma unroll
-                    for (int q = 0; q < KO; ++q)
-                        if (q < k) {
-                            vy[q] += vj * cs[j * k + q];
-                            wy[q] += wj * cs[j * k + q];
-                        }
+            for (int j = 0; j < MB; ++j)
+                if (j < m) {
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) {
+                        v[j][u] = in[u] ? A.V[(size_t)j * N + ix[u]] : 0.0;
+                        w[j][u] = in[u] ? A.W[(size_t)j * N + ix[u]] : 0.0;
+                    }
                 }
-            }
-            const double d = in ? A.diag[i] : 0.0;
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) d[u] = in[u] ? A.diag[ix[u]] : 0.0;
 #pragma unroll
             for (int q = 0; q < KO; ++q) {
                 if (q < k) {
-                    const double r = wy[q] - th[q] * vy[q];
-                    const double tq = in ? r * damped_inv(d - th[q], A.delta) : 0.0;
-                    if (in) A.out[(size_t)q * N + i] = tq;
-                    nrm[q] += in ? r * r : 0.0;
-                    nrm[KO + q] += tq * tq;
-                    ot[q][tid] = tq;
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    double vy = 0.0, wy = 0.0;
+#pragma unroll
+                    for (int j = 0; j < MB; ++j)
+                        if (j < m) {
+                            vy += v[j][u] * cf[j * k + q];
+                            wy += w[j][u] * cf[j * k + q];
+                        }
+                    const double r = wy - th[q] * vy;
+                    const double t = in[u] ? r * damped_inv(d[u] - th[q], A.delta) : 0.0;
+                    if (in[u]) A.out[(size_t)q * N + ix[u]] = t;
+                    nrm[q] += r * r;
+                    nrm[KO + q] += t * t;
+                    if constexpr (PRJ) {
+#pragma unroll
+                        for (int j = 0; j < MB; ++j)
+                            if (j < mp) acc[j][q] += v[j][u] * t;
+                    }
+                }
                 }
             }
-        } else if (A.mode == SUB1 || A.mode == SUB2) {
-            double s = 0.0;
-            if (in) {
-#pragma unroll 4
-                for (int j = 0; j < m; ++j) s += A.V[(size_t)j * N + i] * cs[j];
+        } else if constexpr (MODE == SUB1 || MODE == SUB2) {
+            double v[MB][EPT], x[EPT];
+            double w[PRJ && MODE == SUB2 ? MB : 1][EPT];
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) x[u] = in[u] ? A.X[ix[u]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+                if (j < m) {
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) v[j][u] = in[u] ? A.V[(size_t)j * N + ix[u]] : 0.0;
+                }
+            if constexpr (PRJ && MODE == SUB2) {
+#pragma unroll
+                for (int j = 0; j < MB; ++j)
+                    if (j < mp) {
+#pragma unroll
+                        for (int u = 0; u < EPT; ++u) w[j][u] = in[u] ? A.W[(size_t)j * N + ix[u]] : 0.0;
+                    }
             }
-            const double tv = in ? A.X[i] - s : 0.0;
-            if (in) A.out[i] = tv;
-            nrm[0] += tv * tv;
-            ot[0][tid] = tv;
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                double sv = 0.0;
+#pragma unroll
+                for (int j = 0; j < MB; ++j)
+                    if (j < m) sv += v[j][u] * cf[j];
+                const double t = in[u] ? x[u] - sv : 0.0;
+                if (in[u]) A.out[ix[u]] = t;
+                nrm[0] += t * t;
+                if constexpr (PRJ) {
+#pragma unroll
+                    for (int j = 0; j < MB; ++j)
+                        if (j < mp) acc[j][0] += (MODE == SUB1 ? v[j][u] : w[MODE == SUB2 ? j : 0][u]) * t;
+                }
+            }
         } else {  // PROJ
+            double p[MB][EPT], x[KO][EPT];
 #pragma unroll
             for (int q = 0; q < KO; ++q)
-                if (q < k) ot[q][tid] = in ? A.X[(size_t)q * N + i] : 0.0;
+                if (q < k) {
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) x[q][u] = in[u] ? A.X[(size_t)q * N + ix[u]] : 0.0;
+                }
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+                if (j < mp) {
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) p[j][u] = in[u] ? A.P[(size_t)j * N + ix[u]] : 0.0;
+                }
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+                if (j < mp) {
+#pragma unroll
+                    for (int q = 0; q < KO; ++q)
+                        if (q < k) {
+#pragma unroll
+                            for (int u = 0; u < EPT; ++u) acc[j][q] += p[j][u] * x[q][u];
+                        }
+                }
         }
-        __syncthreads();
-        // ---- contraction phase: wave wv owns rows j = wv + 4*jj of P
-#pragma unroll
-        for (int jj = 0; jj < JW; ++jj) {
-            const int j = wv + 4 * jj;
-            if (j >= mp) break;  // uniform within the wave
-            const double* pr = A.P + (size_t)j * N + c0;
-#pragma unroll
-            for (int g = 0; g < kTB / 64; ++g) {
-                const int e = 64 * g + lane;
-                const double a = (c0 + e < N) ? pr[e] : 0.0;
-#pragma unroll
-                for (int q = 0; q < KO; ++q)
-                    if (q < k) acc[jj][q] += a * ot[q][e];
-            }
-        }
-        __syncthreads();
     }
-    // ---- reductions: norms over the block, projections within their wave
+
+    // ---- block reduction: wavefront shuffles, then the four wavefronts in order
+    const int NR = (MODE == RESID) ? 2 * k : ((MODE == PROJ) ? 0 : 1);
+    const int kq = (MODE == RESID || MODE == PROJ) ? k : 1;
 #pragma unroll
     for (int q = 0; q < 2 * KO; ++q) {
-        double x = nrm[q];
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        if (lane == 0) nsum[wv][q] = x;
-    }
-    __syncthreads();
-    const int NR = (A.mode == RESID) ? 2 * k : ((A.mode == PROJ) ? 0 : 1);
-    const int nblk = gridDim.x;
-    if (tid < NR) {
-        // RESID rows: [0,k) |r_q|^2 = nrm[q], [k,2k) |t_q|^2 = nrm[KO+q];  SUB rows: [0] = nrm[0]
-        const int src = (A.mode == RESID && tid >= k) ? (KO + tid - k) : tid;
-        double sum = 0.0;
-        for (int w = 0; w < 4; ++w) sum += nsum[w][src];
-        A.part[(size_t)tid * nblk + blockIdx.x] = sum;
-    }
-#pragma unroll
-    for (int jj = 0; jj < JW; ++jj) {
-        const int j = wv + 4 * jj;
-#pragma unroll
-        for (int q = 0; q < KO; ++q) {
-            double x = acc[jj][q];
-            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-            if (lane == 0 && j < mp && q < k) A.part[(size_t)(NR + j * k + q) * nblk + blockIdx.x] = x;
+        const double x = wave_sum(nrm[q]);
+        if (lane == 0) {
+            // RESID: [0,k) |r_q|^2, [k,2k) |t_q|^2;  SUB: [0] |t|^2
+            if (MODE == RESID && q < KO && q < k) red[wv][q] = x;
+            if (MODE == RESID && q >= KO && q - KO < k) red[wv][k + q - KO] = x;
+            if ((MODE == SUB1 || MODE == SUB2) && q == 0) red[wv][0] = x;
         }
     }
+    if constexpr (PRJ) {
+#pragma unroll
+        for (int j = 0; j < NAJ; ++j)
+#pragma unroll
+            for (int q = 0; q < NAQ; ++q) {
+                const double x = wave_sum(acc[j][q]);
+                if (lane == 0 && j < mp && q < kq) red[wv][NR + j * kq + q] = x;
+            }
+    }
+    __syncthreads();
+    const int rows = NR + (PRJ ? mp * kq : 0);
+    for (int r = tid; r < rows; r += kTB)
+        A.part[(size_t)r * gridDim.x + blockIdx.x] = ((red[0][r] + red[1][r]) + red[2][r]) + red[3][r];
 }
 
 // out[r] = sum_b part[r][b], fixed order, one block per row
@@ -183,37 +241,107 @@ __global__ void k_reduce(const double* __restrict__ part, int nblk, double* __re
     if (threadIdx.x == 0) out[r] = sh[0];
 }
 
-unsigned pass_blocks(int64_t N) {
-    int64_t b = (N + kTB - 1) / kTB;
-    if (b < 1) b = 1;
-    if (b > kRedBlocks) b = kRedBlocks;
-    return (unsigned)b;
+// Register budget (FP64 values held per thread, two VGPRs each): the row
+// values of the pass plus its accumulators.  Beyond it a projection is split off.
+constexpr int kRegBudget = 96;
+
+int mb_for(int rows) {
+    const int steps[] = {4, 8, 16, 24, 32, 48};
+    for (int s : steps)
+        if (rows <= s) return s;
+    return -1;
+}
+int ko_for(int k) { return k <= 1 ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : (k <= 8 ? 8 : -1))); }
+
+// FP64 values held per thread by an instantiation: row values plus accumulators
+constexpr int held(int mode, int mb, int ko, bool prj) {
+    return ept_for(mb) *
+           ((mode == RESID)  ? 2 * mb + (prj ? mb * ko : 0)
+            : (mode == SUB1) ? mb + (prj ? mb : 0)
+            : (mode == SUB2) ? mb + (prj ? 2 * mb : 0)
+                             : mb + ko + mb * ko);
+}
+// Instantiations that exist: the PRJ forms within the budget; the non-PRJ
+// Gram-Schmidt forms (also used with no subspace yet, m = 0); the non-PRJ
+// residual forms where the PRJ form of the same size does not fit.
+constexpr bool exists(int mode, int mb, int ko, bool prj) {
+    return (mode == SUB1 || mode == SUB2) && ko != 1 ? false
+           : prj                                    ? held(mode, mb, ko, true) <= kRegBudget
+           : mode == PROJ                           ? false
+           : mode == RESID                          ? held(mode, mb, ko, true) > kRegBudget
+                                                    : true;
 }
 
-template <int JW, int KO>
-void launch_k(const PassArgs& A, unsigned nb, hipStream_t st) {
-    hipLaunchKernelGGL((k_pass<JW, KO>), dim3(nb), dim3(kTB), 0, st, A);
+template <int MODE, int MB, int KO, bool PRJ>
+hipError_t launch_k(const PassArgs& A, unsigned* nb_out, hipStream_t st) {
+    if constexpr (!exists(MODE, MB, KO, PRJ)) {
+        return hipErrorInvalidValue;
+    } else {
+    // one resident wave of blocks per CU slot: fill the chip once, then grid-stride
+    // (thread-safe one-time query per instantiation; single-device library state)
+    static const int slots = [] {
+        int dev = 0, cus = 0, nbk = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbk, k_pass<MODE, MB, KO, PRJ>, kTB, 0) !=
+                hipSuccess)
+            return 256;
+        return std::max(1, nbk) * std::max(1, cus);
+    }();
+    const int64_t per_block = (int64_t)kTB * ept_for(MB);
+    int64_t nb = (A.N + per_block - 1) / per_block;
+    const int64_t cap = std::min<int64_t>(slots, kRedBlocks);
+    if (nb > cap) nb = cap;
+    if (nb < 1) nb = 1;
+    *nb_out = (unsigned)nb;
+    hipLaunchKernelGGL((k_pass<MODE, MB, KO, PRJ>), dim3((unsigned)nb), dim3(kTB), 0, st, A);
+    return hipGetLastError();
+    }
 }
 
-// Register budget of the contraction: JW * KO <= 32 accumulators per lane.
-hipError_t run_pass(const PassArgs& A, int rows, double* out, hipStream_t st) {
-    const unsigned nb = pass_blocks(A.N);
-    if (A.k < 1 || A.k > kMaxOut || A.mp > 48 || A.m > 64 || rows > 512) return hipErrorInvalidValue;
-    const int jw = A.mp <= 16 ? 4 : (A.mp <= 32 ? 8 : 12);
-    const int ko = A.k <= 1 ? 1 : (A.k <= 2 ? 2 : (A.k <= 4 ? 4 : 8));
-    if (jw * ko > 32) return hipErrorInvalidValue;
-    switch (jw * 100 + ko) {
-        case 401: launch_k<4, 1>(A, nb, st); break;
-        case 402: launch_k<4, 2>(A, nb, st); break;
-        case 404: launch_k<4, 4>(A, nb, st); break;
-        case 408: launch_k<4, 8>(A, nb, st); break;
-        case 801: launch_k<8, 1>(A, nb, st); break;
-        case 802: launch_k<8, 2>(A, nb, st); break;
-        case 804: launch_k<8, 4>(A, nb, st); break;
-        case 1201: launch_k<12, 1>(A, nb, st); break;
-        case 1202: launch_k<12, 2>(A, nb, st); break;
+template <int MODE, int KO, bool PRJ>
+hipError_t by_mb(int mb, const PassArgs& A, unsigned* nb, hipStream_t st) {
+    switch (mb) {
+        case 4: return launch_k<MODE, 4, KO, PRJ>(A, nb, st);
+        case 8: return launch_k<MODE, 8, KO, PRJ>(A, nb, st);
+        case 16: return launch_k<MODE, 16, KO, PRJ>(A, nb, st);
+        case 24: return launch_k<MODE, 24, KO, PRJ>(A, nb, st);
+        case 32: return launch_k<MODE, 32, KO, PRJ>(A, nb, st);
+        case 48: return launch_k<MODE, 48, KO, PRJ>(A, nb, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <int MODE, bool PRJ>
+hipError_t by_ko(int ko, int mb, const PassArgs& A, unsigned* nb, hipStream_t st) {
+    switch (ko) {
+        case 1: return by_mb<MODE, 1, PRJ>(mb, A, nb, st);
+        case 2: return by_mb<MODE, 2, PRJ>(mb, A, nb, st);
+        case 4: return by_mb<MODE, 4, PRJ>(mb, A, nb, st);
+        case 8: return by_mb<MODE, 8, PRJ>(mb, A, nb, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool fits(int mode, int rows, int k, bool prj) {
+    const int mb = mb_for(rows), ko = ko_for(k);
+    return mb > 0 && ko > 0 && held(mode, mb, (mode == SUB1 || mode == SUB2) ? 1 : ko, prj) <= kRegBudget;
+}
+
+// One pass; `rows` results reduced into out.  The caller checked fits().
+hipError_t run_pass(int mode, const PassArgs& A, int rows, double* out, hipStream_t st) {
+    const bool prj = A.mp > 0;
+    const int need = std::max(mode == PROJ ? 0 : A.m, A.mp);
+    const int mb = mb_for(need < 1 ? 1 : need);
+    const int ko = (mode == RESID || mode == PROJ) ? ko_for(A.k) : 1;
+    if (mb < 0 || ko < 0 || rows > kPassRows) return hipErrorInvalidValue;
+    unsigned nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (mode == RESID) e = prj ? by_ko<RESID, true>(ko, mb, A, &nb, st) : by_ko<RESID, false>(ko, mb, A, &nb, st);
+    else if (mode == SUB1) e = prj ? by_mb<SUB1, 1, true>(mb, A, &nb, st) : by_mb<SUB1, 1, false>(mb, A, &nb, st);
+    else if (mode == SUB2) e = prj ? by_mb<SUB2, 1, true>(mb, A, &nb, st) : by_mb<SUB2, 1, false>(mb, A, &nb, st);
+    else e = by_ko<PROJ, true>(ko, mb, A, &nb, st);
+    if (e != hipSuccess) return e;
     if (rows > 0) hipLaunchKernelGGL(k_reduce, dim3(rows), dim3(kTB), 0, st, A.part, (int)nb, out);
     return hipGetLastError();
 }
@@ -223,53 +351,61 @@ hipError_t run_pass(const PassArgs& A, int rows, double* out, hipStream_t st) {
 
 namespace sbd {
 
-hipError_t pass_resid(const double* V, const double* W, int m, int k, const double* Y,
-                      const double* theta, const double* diag, double delta, double* T, int64_t N,
-                      bool proj, double* part, double* out, hipStream_t st) {
-    PassArgs A{};
-    A.N = N; A.mode = RESID; A.m = m; A.k = k; A.mp = proj ? m : 0;
-    if (proj && !pass_fits(m, k)) return hipErrorInvalidValue;
-    A.V = V; A.W = W; A.P = V; A.out = T; A.coef = Y; A.theta = theta; A.diag = diag;
-    A.delta = delta; A.part = part;
-    return run_pass(A, 2 * k + A.mp * k, out, st);
-}
-
-hipError_t pass_sub1(const double* V, int m, const double* h, double* t, int64_t N, double* part,
-                     double* out, hipStream_t st) {
-    PassArgs A{};
-    A.N = N; A.mode = SUB1; A.m = m; A.k = 1; A.mp = m;
-    A.V = V; A.P = V; A.X = t; A.out = t; A.coef = h; A.part = part;
-    return run_pass(A, 1 + m, out, st);
-}
-
-hipError_t pass_sub2(const double* V, int m, const double* h, const double* t, double* dst,
-                     const double* W, int mw, int64_t N, double* part, double* out, hipStream_t st) {
-    PassArgs A{};
-    A.N = N; A.mode = SUB2; A.m = m; A.k = 1; A.mp = mw;
-    A.V = V; A.W = W; A.P = W; A.X = t; A.out = dst; A.coef = h; A.part = part;
-    return run_pass(A, 1 + mw, out, st);
-}
-
 hipError_t pass_project(const double* P, int mp, const double* X, int k, int64_t N, double* part,
                         double* out, hipStream_t st) {
-    // row groups small enough for the register budget; each group is one pass over X
+    if (mp < 1 || mp > 48 || k < 1 || k > kMaxOut) return hipErrorInvalidValue;
+    // row groups small enough for the register budget; each group is one sweep over X
     int step = mp;
-    while (!pass_fits(step, k)) step = (step + 1) / 2;
+    while (step > 1 && !fits(PROJ, step, k, true)) step = (step + 1) / 2;
+    if (!fits(PROJ, step, k, true)) return hipErrorInvalidValue;
     for (int j0 = 0; j0 < mp; j0 += step) {
         PassArgs A{};
-        const int g = mp - j0 < step ? mp - j0 : step;
-        A.N = N; A.mode = PROJ; A.m = 0; A.k = k; A.mp = g;
+        const int g = std::min(step, mp - j0);
+        A.N = N; A.m = 0; A.k = k; A.mp = g;
         A.P = P + (size_t)j0 * N; A.X = X; A.part = part;
-        hipError_t e = run_pass(A, g * k, out + (size_t)j0 * k, st);
+        hipError_t e = run_pass(PROJ, A, g * k, out + (size_t)j0 * k, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-bool pass_fits(int mp, int k) {
-    const int jw = mp <= 16 ? 4 : (mp <= 32 ? 8 : 12);
-    const int ko = k <= 1 ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));
-    return mp <= 48 && k <= 8 && jw * ko <= 32;
+hipError_t pass_resid(const double* V, const double* W, int m, int k, const double* Y,
+                      const double* theta, const double* diag, double delta, double* T, int64_t N,
+                      bool proj, double* part, double* out, hipStream_t st) {
+    if (m < 1 || m > 48 || k < 1 || k > kMaxOut) return hipErrorInvalidValue;
+    // the fused form whenever it fits (without proj its projection rows are not reduced)
+    const bool fused = fits(RESID, m, k, true);
+    PassArgs A{};
+    A.N = N; A.m = m; A.k = k; A.mp = fused ? m : 0;
+    A.V = V; A.W = W; A.P = V; A.out = T; A.coef = Y; A.theta = theta; A.diag = diag;
+    A.delta = delta; A.part = part;
+    hipError_t e = run_pass(RESID, A, 2 * k + (proj ? A.mp * k : 0), out, st);
+    if (e == hipSuccess && proj && !fused) e = pass_project(V, m, T, k, N, part, out + 2 * k, st);
+    return e;
+}
+
+hipError_t pass_sub1(const double* V, int m, const double* h, double* t, int64_t N, double* part,
+                     double* out, hipStream_t st) {
+    if (m < 0 || m > 48) return hipErrorInvalidValue;
+    const bool fused = m > 0 && fits(SUB1, m, 1, true);
+    PassArgs A{};
+    A.N = N; A.m = m; A.k = 1; A.mp = fused ? m : 0;
+    A.V = V; A.P = V; A.X = t; A.out = t; A.coef = h; A.part = part;
+    hipError_t e = run_pass(SUB1, A, 1 + A.mp, out, st);
+    if (e == hipSuccess && m > 0 && !fused) e = pass_project(V, m, t, 1, N, part, out + 1, st);
+    return e;
+}
+
+hipError_t pass_sub2(const double* V, int m, const double* h, const double* t, double* dst,
+                     const double* W, int mw, int64_t N, double* part, double* out, hipStream_t st) {
+    if (m < 0 || m > 48 || mw < 0 || mw > 48) return hipErrorInvalidValue;
+    const bool fused = mw > 0 && fits(SUB2, std::max(m, mw), 1, true);
+    PassArgs A{};
+    A.N = N; A.m = m; A.k = 1; A.mp = fused ? mw : 0;
+    A.V = V; A.W = W; A.P = W; A.X = t; A.out = dst; A.coef = h; A.part = part;
+    hipError_t e = run_pass(SUB2, A, 1 + A.mp, out, st);
+    if (e == hipSuccess && mw > 0 && !fused) e = pass_project(W, mw, dst, 1, N, part, out + 1, st);
+    return e;
 }
 
 }  // namespace sbd

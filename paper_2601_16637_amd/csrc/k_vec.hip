@@ -1,9 +1,8 @@
-// Dense FP64 vector kernels of the Davidson update (Sec. II-C): projections
-// V^T x, linear combinations V Y, the fused residual + damped diagonal
-// preconditioner (Eqs. 6-7), and reductions.  All reductions are two-stage
-// with a fixed block count and a fixed combination order, so results do not
-// depend on scheduling.  These kernels are bound by HBM bandwidth: each pass
-// streams the subspace vectors once.
+// Dense FP64 vector kernels of the Davidson driver (Sec. II-C): linear
+// combinations V Y (collapse and restart), scaling, precision conversions for
+// the FP32 sigma, start-vector selection and small reductions.  Reductions are
+// two-stage with a fixed block count and a fixed combination order, so results
+// do not depend on scheduling.  These kernels are bound by HBM bandwidth.
 #include "internal.h"
 
 namespace sbd {
@@ -101,6 +100,28 @@ __global__ void k_argmin_final(const double* pv, const int64_t* pi, int nblk, do
     *oi = bi;
 }
 
+// block maxima of v, then the maximum of the block values
+__global__ void __launch_bounds__(kVB) k_max(const double* __restrict__ v, int64_t N, double* pv) {
+    double b = -INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * kVB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kVB)
+        b = fmax(b, v[i]);
+    __shared__ double sv[kVB];
+    sv[threadIdx.x] = b;
+    __syncthreads();
+    for (int off = kVB / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sv[threadIdx.x] = fmax(sv[threadIdx.x], sv[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) pv[blockIdx.x] = sv[0];
+}
+
+__global__ void k_max_final(const double* pv, int nblk, double* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double b = -INFINITY;
+    for (int i = 0; i < nblk; ++i) b = fmax(b, pv[i]);
+    *out = b;
+}
+
 __global__ void k_set_unit(double* x, int64_t N, int64_t idx) {
     for (int64_t i = (int64_t)blockIdx.x * kVB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kVB)
         x[i] = (i == idx) ? 1.0 : 0.0;
@@ -161,6 +182,13 @@ hipError_t launch_argmin_after(const double* v, int64_t N, double vprev, int64_t
                        d_part_i);
     hipLaunchKernelGGL(k_argmin_final, dim3(1), dim3(64), 0, st, d_part_v, d_part_i, (int)nb,
                        d_val, d_idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_max(const double* v, int64_t N, double* d_val, double* d_part, hipStream_t st) {
+    unsigned nb = red_blocks(N);
+    hipLaunchKernelGGL(k_max, dim3(nb), dim3(kVB), 0, st, v, N, d_part);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(64), 0, st, d_part, (int)nb, d_val);
     return hipGetLastError();
 }
 

@@ -79,3 +79,38 @@ def test_norb64_strings_accepted_by_validation():
     st = _status(lambda: sbd.Basis(64, 64, 64, full, full))
     # on a machine without a GPU the call gets past validation and fails in HIP
     assert st in (0, -6)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the option, report, request and result structs
+    have the C header's sizes and field offsets (compiled with gcc)."""
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_2601_16637_amd import _native as nat
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"sbd_davidson_opts": nat.DavidsonOpts, "sbd_davidson_report": nat.DavidsonReport,
+               "sbd_request": nat.Request, "sbd_result": nat.Result}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sbd.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            c, f, v = line.split()
+            got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -308,6 +308,25 @@ def test_davidson_mixed_precision(nroots):
     assert np.abs(e - ro.energies).max() <= 1e-6
 
 
+@pytest.mark.parametrize("nroots", [1, 3])
+def test_davidson_mixed_residual_certified_by_oracle(nroots):
+    """Mixed precision declares convergence only on exact residuals: the
+    oracle's FP64 sigma of the returned vectors meets the tolerance, and the
+    FP32 error scale was calibrated (positive, finite)."""
+    W = wl.make_config("sel16", nstr=400)
+    _, _, ham = from_workload(W)
+    vec = torch.empty(nroots * W.ndet, device=DEV, dtype=torch.float64)
+    e, rep, st = sbd.davidson(ham, nroots, vectors=vec, tol_residual=1e-6, sigma_prec=sbd.FP32)
+    assert st == 0 and rep["converged"]
+    assert 0.0 < rep["fp32_error_scale"] < 1e-3
+    S = oracle.OracleSystem.from_workload(W)
+    U = vec.cpu().numpy().reshape(nroots, W.ndet)
+    for r in range(nroots):
+        res = S.sigma(U[r]) - e[r] * U[r]
+        assert np.linalg.norm(res) <= 1e-6 + 1e-9
+        assert abs(np.linalg.norm(U[r]) - 1.0) <= 1e-12
+
+
 def test_davidson_full_sel16_residual_by_oracle():
     """Full-size solve; the oracle checks the returned eigenpair on sampled rows."""
     W = wl.make_config("sel16")
