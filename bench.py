@@ -77,6 +77,12 @@ def sigma_stages(sbd, H, N, prec, stream, reps=10):
     return {k: v / reps for k, v in acc.items()}
 
 
+def stream_kernel_name(tune):
+    """Instantiation of the FP32 single-vector row stream that a tune selects
+    (columns per lane: 2, or 4 with 16-byte loads; output rows per wavefront)."""
+    return f"k_stream<float,1,{4 if tune['stream_wide'] else 2},{tune['stream_rw']}>"
+
+
 def kernel_only(sbd, W, stream):
     """Short run for hardware-counter passes: five FP32 sigma launches and one
     device copy of known size (2 * N * 4 bytes) used to calibrate the counters."""
@@ -92,9 +98,10 @@ def kernel_only(sbd, W, stream):
     z = torch.empty_like(x)
     z.copy_(x)
     torch.cuda.synchronize()
+    tune = H.get_tune(sbd.FP32)
     print(json.dumps(dict(kernel_only=True, workload=W.name, ndet=W.ndet,
                           copy_bytes_read=4 * W.ndet, copy_bytes_written=4 * W.ndet,
-                          tune=H.get_tune(sbd.FP32))))
+                          tune=tune, stream_kernel=stream_kernel_name(tune))))
 
 
 def cpu_baseline(W, target_s=15.0):
@@ -152,6 +159,82 @@ def serving(sbd, wl, nreq=256, budget=96 << 30, inflight=8):
                 max_request_ndet=int(max(r["ndet"] for _, r in res)))
 
 
+def _csv_rows(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _col(row, *names):
+    low = {k.lower(): v for k, v in row.items()}
+    for n in names:
+        if n.lower() in low:
+            return low[n.lower()]
+    raise KeyError(names)
+
+
+def _short(name):
+    """Kernel name without namespaces, return type and argument list."""
+    n = name.replace("sbd::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
+    if n.startswith("void "):
+        n = n[5:]
+    depth = 0
+    for i, ch in enumerate(n):
+        depth += ch == "<"
+        depth -= ch == ">"
+        if ch == "(" and depth == 0:
+            n = n[:i]
+            break
+    return n.replace(", ", ",").strip()
+
+
+def stats_summary(csv_path, top=25):
+    """Markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv)."""
+    rows = _csv_rows(csv_path)
+    rows.sort(key=lambda r: -float(_col(r, "TotalDurationNs")))
+    out = ["| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append(f"| `{_short(_col(r, 'Name'))}` | {_col(r, 'Calls')} | "
+                   f"{float(_col(r, 'TotalDurationNs')) / 1e6:.2f} | "
+                   f"{float(_col(r, 'AverageNs')) / 1e3:.1f} | {float(_col(r, 'Percentage')):.1f} |")
+    return "\n".join(out)
+
+
+def _counter_means(csv_path, counter):
+    """Mean counter value per dispatch, per short kernel name."""
+    acc = {}
+    per_dispatch = {}
+    for r in _csv_rows(csv_path):
+        if _col(r, "Counter_Name") != counter:
+            continue
+        key = (_col(r, "Dispatch_Id"), _short(_col(r, "Kernel_Name")))
+        per_dispatch[key] = per_dispatch.get(key, 0.0) + float(_col(r, "Counter_Value"))
+    for (_, k), v in per_dispatch.items():
+        acc.setdefault(k, []).append(v)
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def traffic_summary(fetch_csv, write_csv, kernel_json, workload):
+    """HBM bytes per launch of `kernel` from FETCH_SIZE / WRITE_SIZE runs (KiB per
+    dispatch), each scaled by what the counter reads for the calibration copy of
+    known size in the same --kernel-only run."""
+    info = json.loads([l for l in open(kernel_json) if l.startswith("{")][-1])
+    kernel = info["stream_kernel"]
+    fetch = _counter_means(fetch_csv, "FETCH_SIZE")
+    write = _counter_means(write_csv, "WRITE_SIZE")
+    copy = next(k for k in fetch if "copyBuffer" in k or "copy" in k.lower())
+    f_scale = info["copy_bytes_read"] / (1024.0 * fetch[copy])
+    w_scale = info["copy_bytes_written"] / (1024.0 * write[copy])
+    kf, kw = fetch[kernel] * 1024.0, write[kernel] * 1024.0
+    total = kf * f_scale + kw * w_scale
+    lines = [f"# {kernel} on {workload}: FETCH_SIZE {fetch[kernel]:.0f} KiB/dispatch (x{f_scale:.3f}), "
+             f"WRITE_SIZE {write[kernel]:.0f} KiB/dispatch (x{w_scale:.3f}); calibration copy "
+             f"{copy}: read {info['copy_bytes_read']} B, FETCH_SIZE {fetch[copy]:.0f} KiB, "
+             f"WRITE_SIZE {write[copy]:.0f} KiB",
+             f"{kernel} {workload} {kernel_source_hash()} {total:.0f}"]
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,7 +246,17 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a few sigma launches and a calibration copy (counter runs)")
+    ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
+                    help="print a markdown summary of a rocprofv3 --stats run and exit")
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_ONLY_LOG"),
+                    help="print calibrated HBM bytes per launch of the dominant kernel and exit")
     args = ap.parse_args()
+    if args.stats_summary:
+        print(stats_summary(args.stats_summary))
+        return
+    if args.traffic_summary:
+        print(traffic_summary(*args.traffic_summary, workload=args.workload))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU path is not built "
               "(--gpus must be 1)", file=sys.stderr)
@@ -246,6 +339,7 @@ def main():
     X = sbd.Excitations(B, stream=stream)
     H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
     H.autotune(sbd.FP32, stream=stream)
+    kname = stream_kernel_name(H.get_tune(sbd.FP32))
     stages32 = sigma_stages(sbd, H, N, sbd.FP32, stream)
     H.autotune(sbd.FP64, stream=stream)
     stages64 = sigma_stages(sbd, H, N, sbd.FP64, stream)
@@ -260,11 +354,11 @@ def main():
     achieved = (f_alpha + f_beta) / t_stream
     t_sig32 = sum(stages32.values()) * 1e-3
     t_sig64 = sum(stages64.values()) * 1e-3
-    traffic = traffic_for("k_stream<float,1,2,1>", W.name)
+    traffic = traffic_for(kname, W.name)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
                     unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU,
                     traffic=None if traffic is None else traffic,
-                    kernel="k_stream<float,1,2,1> (alpha and beta launches of one FP32 sigma)",
+                    kernel=f"{kname} (alpha and beta launches of one FP32 sigma)",
                     launch_ms=1e3 * t_stream / 2, algorithmic_flops_per_launch=(f_alpha + f_beta) / 2,
                     sigma_fp32_stage_ms=stages32, sigma_fp64_stage_ms=stages64,
                     sigma_fp32_det_per_s=N / t_sig32, sigma_fp64_det_per_s=N / t_sig64,

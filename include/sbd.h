@@ -65,6 +65,9 @@ const char* sbd_last_error(void);
 
 /* Library version as major*10000 + minor*100 + patch. */
 int sbd_version(void);
+/* Hash of the sources the library was built from (16 hex digits); bindings
+ * compare it with their own sources to refuse a stale build. */
+const char* sbd_source_hash(void);
 
 typedef struct sbd_basis sbd_basis;
 typedef struct sbd_exc sbd_exc;
@@ -164,9 +167,12 @@ int sbd_autotune(const sbd_basis* b, const sbd_exc* e, sbd_ham* h, int prec, int
                  int layout, void* stream, double* best_ms);
 /* Read or set the sigma launch configuration of a handle for one precision
  * (stream_rw in {1, 2}: output rows per wavefront of the stream kernel;
- * ab_lds_bytes in [4096, 1 MiB], capped at the device's LDS per workgroup). */
-int sbd_get_tune(const sbd_ham* h, int prec, int* stream_rw, int* ab_lds_bytes);
-int sbd_set_tune(sbd_ham* h, int prec, int stream_rw, int ab_lds_bytes);
+ * ab_lds_bytes in [4096, 1 MiB], capped at the device's LDS per workgroup;
+ * stream_wide in {0, 1}: 16-byte instead of 8-byte lane loads in the row
+ * streams where the vector width and row alignment allow).  Any output
+ * pointer of sbd_get_tune may be NULL. */
+int sbd_get_tune(const sbd_ham* h, int prec, int* stream_rw, int* ab_lds_bytes, int* stream_wide);
+int sbd_set_tune(sbd_ham* h, int prec, int stream_rw, int ab_lds_bytes, int stream_wide);
 
 /*
  * sbd_sigma with HIP events recorded on `stream` around its five launches;
@@ -197,7 +203,9 @@ typedef struct {
     int max_space;         /* subspace size before restart; default 20 (>= 2*nroots+1)             */
     double precond_delta;  /* delta of the damped denominators (Eq. 7); default 1e-8 Ha            */
     int sigma_prec;        /* SBD_FP64 (plain) or SBD_FP32 (FP32 sigma + FP64 refinement)          */
-    int use_graph;         /* reserved (0)                                                          */
+    int use_graph;         /* 1: replay each sigma launch sequence (conversions, the five sigma
+                              launches, restore) from a HIP graph captured on its second use; the
+                              solve then runs on a private stream ordered after `stream`          */
     int use_autotune;      /* 1: run sbd_autotune for the sigma shapes this solve uses             */
     const double* guess;   /* optional device pointer, n_guess x N initial vectors (NULL = none)   */
     int n_guess;

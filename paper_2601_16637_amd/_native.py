@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "SBD_OK", 1: "SBD_NOT_CONVERGED", -1: "SBD_ERR_ARG", -2: "SBD
                 -6: "SBD_ERR_HIP", -7: "SBD_ERR_NUMERIC", -8: "SBD_ERR_STATE"}
 
 # Every symbol include/sbd.h declares.
-EXPORTED = ["sbd_last_error", "sbd_version", "sbd_build_basis", "sbd_basis_sizes",
+EXPORTED = ["sbd_last_error", "sbd_version", "sbd_source_hash", "sbd_build_basis", "sbd_basis_sizes",
             "sbd_basis_strings", "sbd_free_basis", "sbd_build_excitations", "sbd_exc_count",
             "sbd_exc_export", "sbd_free_exc", "sbd_set_hamiltonian", "sbd_ham_diag",
             "sbd_free_ham", "sbd_sigma", "sbd_sigma_timed", "sbd_autotune", "sbd_get_tune", "sbd_set_tune", "sbd_gram",
@@ -98,6 +98,13 @@ def load():
         raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
                            "(run __graft_entry__.build() or python -m paper_2601_16637_amd.build)")
     L = ctypes.CDLL(LIB_PATH)
+    L.sbd_source_hash.restype = ctypes.c_char_p
+    L.sbd_source_hash.argtypes = []
+    from .build import source_hash
+    built, here = L.sbd_source_hash().decode(), source_hash()
+    if built != here:
+        raise RuntimeError(f"{LIB_PATH} was built from other sources (hash {built}, sources "
+                           f"{here}): rebuild it (python -m paper_2601_16637_amd.build)")
     P, i32, i64, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     PP = ctypes.POINTER(ctypes.c_void_p)
     L.sbd_last_error.restype = ctypes.c_char_p
@@ -120,8 +127,8 @@ def load():
     L.sbd_sigma.argtypes = [P, P, P, i32, i32, d, P, P, i32, P]
     L.sbd_sigma_timed.argtypes = [P, P, P, i32, i32, d, P, P, i32, P, P]
     L.sbd_autotune.argtypes = [P, P, P, i32, i32, i32, P, ctypes.POINTER(d)]
-    L.sbd_get_tune.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
-    L.sbd_set_tune.argtypes = [P, i32, i32, i32]
+    L.sbd_get_tune.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.sbd_set_tune.argtypes = [P, i32, i32, i32, i32]
     L.sbd_gram.argtypes = [P, i32, P, i32, i64, P, P]
     L.sbd_davidson_default_opts.argtypes = [ctypes.POINTER(DavidsonOpts)]
     L.sbd_davidson_default_opts.restype = None
@@ -134,7 +141,8 @@ def load():
     L.sbd_serve_destroy.argtypes = [P]
     L.sbd_serve_destroy.restype = None
     for name in EXPORTED:
-        if name not in ("sbd_last_error", "sbd_version", "sbd_free_basis", "sbd_free_exc",
+        if name not in ("sbd_last_error", "sbd_version", "sbd_source_hash", "sbd_free_basis",
+                        "sbd_free_exc",
                         "sbd_free_ham", "sbd_davidson_default_opts", "sbd_serve_destroy"):
             getattr(L, name).restype = i32
     _lib = L
@@ -260,12 +268,15 @@ class Hamiltonian:
         return ms.value
 
     def get_tune(self, prec: int = FP64):
-        rw, lds = ctypes.c_int(), ctypes.c_int()
-        check(load().sbd_get_tune(self._h, int(prec), ctypes.byref(rw), ctypes.byref(lds)))
-        return dict(stream_rw=rw.value, ab_lds_bytes=lds.value)
+        rw, lds, wide = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(load().sbd_get_tune(self._h, int(prec), ctypes.byref(rw), ctypes.byref(lds),
+                                  ctypes.byref(wide)))
+        return dict(stream_rw=rw.value, ab_lds_bytes=lds.value, stream_wide=wide.value)
 
-    def set_tune(self, prec: int = FP64, stream_rw: int = 1, ab_lds_bytes: int = 98304):
-        check(load().sbd_set_tune(self._h, int(prec), int(stream_rw), int(ab_lds_bytes)))
+    def set_tune(self, prec: int = FP64, stream_rw: int = 1, ab_lds_bytes: int = 98304,
+                 stream_wide: int = 0):
+        check(load().sbd_set_tune(self._h, int(prec), int(stream_rw), int(ab_lds_bytes),
+                                  int(stream_wide)))
 
     def diag_into(self, out, stream=None):
         check(load().sbd_ham_diag(self._h, _dptr(out), _stream(stream)))

@@ -1,4 +1,9 @@
-"""Compile the HIP library libsbd.so for gfx950 in-tree with hipcc."""
+"""Compile the HIP library libsbd.so for gfx950 in-tree with hipcc.
+
+The library records a hash of the sources it was built from
+(``sbd_source_hash``); the Python binding refuses to load a library whose
+hash differs from the sources next to it, so a stale build fails loudly."""
+import hashlib
 import os
 import subprocess
 import sys
@@ -16,9 +21,23 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 
-def _compile(src):
+def source_hash() -> str:
+    """Hash of every source and header the library is built from."""
+    h = hashlib.sha256()
+    names = sorted(SOURCES) + ["internal.h"]
+    for n in names:
+        h.update(n.encode())
+        with open(os.path.join(CSRC, n), "rb") as f:
+            h.update(f.read())
+    with open(os.path.join(HERE, "..", "include", "sbd.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src, digest):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, f'-DSBD_SOURCE_HASH="{digest}"', "-x", "hip", "-c",
+           os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
@@ -28,8 +47,9 @@ def _compile(src):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    digest = source_hash()
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        results = list(ex.map(_compile, SOURCES))
+        results = list(ex.map(lambda s: _compile(s, digest), SOURCES))
     if verbose:
         for _, w in results:
             if w.strip():

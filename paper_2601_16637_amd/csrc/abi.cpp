@@ -53,6 +53,10 @@ extern "C" {
 const char* sbd_last_error(void) { return g_err.c_str(); }
 
 int sbd_version(void) { return 100; }
+#ifndef SBD_SOURCE_HASH
+#define SBD_SOURCE_HASH "unknown"
+#endif
+const char* sbd_source_hash(void) { return SBD_SOURCE_HASH; }
 
 // ------------------------------------------------------------------ basis
 int sbd_build_basis(int norb, int n_alpha, int n_beta, const uint64_t* alpha_strings,

@@ -34,6 +34,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
@@ -126,6 +128,16 @@ constexpr int kDiff = 3096;   // |sigma32 - sigma64|^2 rows of a refresh (2 per 
 constexpr int kSmall = 4096;
 constexpr int kPartRows = kPassRows;
 
+struct OwnedStream {
+    hipStream_t s = nullptr;
+    ~OwnedStream() {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+    }
+};
+
 struct Solver {
     const sbd_exc* x;
     const sbd_ham* H;
@@ -134,10 +146,20 @@ struct Solver {
     int ms, k, keep;
     bool mixed;
     double shift = 0.0;
-    DevBuf V, W, tmp, scr, part, small, idx, x32, y32, sws;
+    DevBuf V, W, tmp, scr, part, small, idx, x32, y32, sws, x64, y64;
     double* sm = nullptr;
     double t_sigma = 0.0;
     int sigma_calls = 0, sigma64 = 0;
+    int nvmax = 1;           // widest interleaved block sigma the staging buffers hold
+    bool use_graph = false;  // replay each sigma launch sequence from a captured HIP graph
+    // captured sigma sequences, keyed by (first row, count, width, FP64); a key is
+    // captured on its second use (the first runs eagerly)
+    std::map<std::tuple<int, int, int, bool>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, int, int, bool>, int> seen;
+
+    ~Solver() {
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    }
 
     double* Vr(int j) { return V.as<double>() + (size_t)j * N; }
     double* Wr(int j) { return W.as<double>() + (size_t)j * N; }
@@ -150,30 +172,88 @@ struct Solver {
         if (e == hipSuccess) e = part.alloc(sizeof(double) * kPartRows * kRedBlocks);
         if (e == hipSuccess) e = small.alloc(sizeof(double) * kSmall);
         if (e == hipSuccess) e = idx.alloc(sizeof(int64_t) * (kRedBlocks + 1));
-        if (e == hipSuccess) e = sws.alloc(sigma_workspace_bytes(N, 1, 0, sizeof(double)));
-        if (mixed && e == hipSuccess) e = x32.alloc(sizeof(float) * (size_t)ms * N);
-        if (mixed && e == hipSuccess) e = y32.alloc(sizeof(float) * (size_t)ms * N);
+        if (e == hipSuccess) e = sws.alloc(sigma_workspace_bytes(N, nvmax, nvmax > 1 ? 1 : 0, sizeof(double)));
+        if (nvmax > 1 && e == hipSuccess) e = x64.alloc(sizeof(double) * (size_t)nvmax * N);
+        if (nvmax > 1 && e == hipSuccess) e = y64.alloc(sizeof(double) * (size_t)nvmax * N);
+        if (mixed && e == hipSuccess) e = x32.alloc(sizeof(float) * (size_t)std::max(ms, nvmax) * N);
+        if (mixed && e == hipSuccess) e = y32.alloc(sizeof(float) * (size_t)std::max(ms, nvmax) * N);
         if (e != hipSuccess) return hip_fail(e, "sbd_davidson workspace");
         sm = small.as<double>();
+        return SBD_OK;
+    }
+
+    // Width of the interleaved sigma for cnt vectors: 1 (one launch sequence per
+    // vector) or the next power of two >= cnt (one gather walk for all of them).
+    int block_width(int cnt) const {
+        if (cnt < 2 || nvmax < 2) return 1;
+        const int nv = cnt <= 2 ? 2 : (cnt <= 4 ? 4 : 8);
+        return nv <= nvmax ? nv : 1;
+    }
+
+    // Device work of W[j .. j+c) = H V[j .. j+c): conversions, sigma, restore.
+    int sigma_launches(int j, int c, int nv, bool p64) {
+        int rc = SBD_OK;
+        hipError_t e = hipSuccess;
+        if (nv == 1) {
+            if (p64) return sigma_internal(x, H, c, SBD_FP64, 0.0, Vr(j), Wr(j), 0, sws.p, st);
+            e = launch_f64_to_f32(Vr(j), x32.as<float>(), (int64_t)c * N, st);
+            if (e == hipSuccess) rc = sigma_internal(x, H, c, SBD_FP32, shift, x32.p, y32.p, 0, sws.p, st);
+            if (e == hipSuccess && !rc)
+                e = launch_f32_to_f64_axpy(y32.as<float>(), Vr(j), shift, Wr(j), (int64_t)c * N, st);
+        } else if (p64) {
+            e = launch_interleave<double>(Vr(j), c, nv, N, x64.as<double>(), st);
+            if (e == hipSuccess) rc = sigma_internal(x, H, nv, SBD_FP64, 0.0, x64.p, y64.p, 1, sws.p, st);
+            if (e == hipSuccess && !rc)
+                e = launch_deinterleave<double>(y64.as<double>(), c, nv, N, nullptr, 0.0, Wr(j), st);
+        } else {
+            e = launch_interleave<float>(Vr(j), c, nv, N, x32.as<float>(), st);
+            if (e == hipSuccess) rc = sigma_internal(x, H, nv, SBD_FP32, shift, x32.p, y32.p, 1, sws.p, st);
+            if (e == hipSuccess && !rc)
+                e = launch_deinterleave<float>(y32.as<float>(), c, nv, N, Vr(j), shift, Wr(j), st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "sigma staging");
+        return rc;
+    }
+
+    // The same work, replayed from a captured graph when use_graph is set.
+    int sigma_group(int j, int c, int nv, bool p64) {
+        if (!use_graph) return sigma_launches(j, c, nv, p64);
+        const auto key = std::make_tuple(j, c, nv, p64);
+        auto it = graphs.find(key);
+        if (it == graphs.end()) {
+            if (seen[key]++ == 0) return sigma_launches(j, c, nv, p64);  // first use: eager
+            SBD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            const int rc = sigma_launches(j, c, nv, p64);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(st, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_fail(e, "sigma capture");
+            hipGraphExec_t ex = nullptr;
+            const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e2 != hipSuccess) return hip_fail(e2, "sigma graph instantiate");
+            it = graphs.emplace(key, ex).first;
+        }
+        SBD_HIP(hipGraphLaunch(it->second, st));
         return SBD_OK;
     }
 
     // W[j0 .. j0+cnt) = H V[j0 .. j0+cnt)
     int apply_sigma(int j0, int cnt, bool fp64) {
         auto t0 = clk::now();
-        int rc;
-        if (!mixed || fp64) {
-            rc = sigma_internal(x, H, cnt, SBD_FP64, 0.0, Vr(j0), Wr(j0), 0, sws.p, st);
-            sigma64 += cnt;
-        } else {
-            hipError_t e = launch_f64_to_f32(Vr(j0), x32.as<float>(), (int64_t)cnt * N, st);
-            if (e != hipSuccess) return hip_fail(e, "to f32");
-            rc = sigma_internal(x, H, cnt, SBD_FP32, shift, x32.p, y32.p, 0, sws.p, st);
+        const bool p64 = !mixed || fp64;
+        for (int d = 0; d < cnt;) {
+            int c = std::min(cnt - d, 8);
+            const int nv = block_width(c);
+            if (nv == 1) c = 1;
+            const int rc = sigma_group(j0 + d, c, nv, p64);
             if (rc) return rc;
-            e = launch_f32_to_f64_axpy(y32.as<float>(), Vr(j0), shift, Wr(j0), (int64_t)cnt * N, st);
-            if (e != hipSuccess) return hip_fail(e, "from f32");
+            d += c;
         }
-        if (rc) return rc;
+        if (p64) sigma64 += cnt;
         sigma_calls += cnt;
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "sigma");
@@ -296,6 +376,15 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         if (rc) return rc;
     }
 
+    // graph capture needs a stream of its own (the legacy default stream cannot
+    // be captured): the solve then runs on a private stream ordered after `stream`
+    OwnedStream own;
+    if (o.use_graph) {
+        SBD_HIP(hipStreamSynchronize(st));
+        SBD_HIP(hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking));
+        st = own.s;
+    }
+
     Solver S;
     S.x = x;
     S.H = H;
@@ -305,6 +394,9 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     S.k = k;
     S.keep = std::max(k, std::min(2 * k, ms - k));
     S.mixed = (o.sigma_prec == SBD_FP32);
+    // block solves gather all new vectors of an iteration in one interleaved sigma
+    S.nvmax = k < 2 ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));
+    S.use_graph = o.use_graph != 0;
     int rc = S.alloc();
     if (rc) return rc;
     double* sm = S.sm;

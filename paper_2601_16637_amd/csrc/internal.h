@@ -123,6 +123,7 @@ struct SigmaTune {
     int ab_lds_bytes = 98304;    // LDS budget for the staged row of the alpha-beta kernel
     int stream_rows = 4;         // wavefronts per stream workgroup
     int stream_rw = 1;           // output rows per stream wavefront (1 or 2)
+    int stream_wide = 0;         // 1: 16-byte lane loads in the row streams where possible
 };
 
 struct SpinCoef {
@@ -237,6 +238,13 @@ hipError_t launch_argmin_after(const double* v, int64_t N, double vprev, int64_t
                                double* d_val, int64_t* d_idx, double* d_part_v,
                                int64_t* d_part_i, hipStream_t st);
 hipError_t launch_set_unit(double* x, int64_t N, int64_t idx, hipStream_t st);
+// Block sigma staging: out[i*nv + v] = src row v (v < cnt), zero for cnt <= v < nv;
+// dst row v = y[., v] (+ shift * x row v when x is given).
+template <class T>
+hipError_t launch_interleave(const double* src, int cnt, int nv, int64_t N, T* out, hipStream_t st);
+template <class T>
+hipError_t launch_deinterleave(const T* y, int cnt, int nv, int64_t N, const double* x, double shift,
+                               double* dst, hipStream_t st);
 // *d_val = max_i v[i]; d_part holds kRedBlocks partials
 hipError_t launch_max(const double* v, int64_t N, double* d_val, double* d_part, hipStream_t st);
 

@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(256) k_stream(StreamArgs<T> A, const T* __rest
                                                 T* __restrict__ out) {
     constexpr int W = NV * VEC;
     constexpr int HL = 64 / RW;  // lanes per row
-    constexpr int UNR = W <= 2 ? 8 : 4;  // ket rows in flight per step
+    constexpr int UNR = W * (int)sizeof(T) <= 16 ? 8 : 4;  // ket rows in flight per step
     const int lane = threadIdx.x & 63;
     const int half = RW == 2 ? (lane >> 5) : 0;
     const int hl = lane & (HL - 1);
@@ -397,30 +397,36 @@ hipError_t stream_vec(StreamArgs<T> S, const T* in, T* out, int rows_per_wg, hip
     return hipGetLastError();
 }
 
-// Columns per lane: wide enough for 8-byte lane loads of FP32 single vectors
-// when every row starts on a multiple of VEC columns; RW rows per wavefront.
+template <class T, int NV, int VEC>
+hipError_t stream_rw(StreamArgs<T> S, const T* in, T* out, const SigmaTune& tune, hipStream_t st) {
+    if (tune.stream_rw == 2) return stream_vec<T, NV, VEC, 2>(S, in, out, tune.stream_rows, st);
+    return stream_vec<T, NV, VEC, 1>(S, in, out, tune.stream_rows, st);
+}
+
+// Columns per lane: B gives 8-byte lane loads (FP32 single vectors take two
+// columns); the wide form doubles that to 16-byte loads where the vector width
+// allows.  Both need every row to start on a multiple of VEC columns.
 template <class T, int NV>
 hipError_t stream(StreamArgs<T> S, const T* in, T* out, const SigmaTune& tune, hipStream_t st) {
-    constexpr int want = (NV * sizeof(T) >= 8) ? 1 : 2;
-    const bool vec2 = want == 2 && S.ncol % 2 == 0;
-    const int rows = tune.stream_rows;
-    if (tune.stream_rw == 2) {
-        if (vec2) return stream_vec<T, NV, (want == 2 ? 2 : 1), 2>(S, in, out, rows, st);
-        return stream_vec<T, NV, 1, 2>(S, in, out, rows, st);
+    constexpr int B = NV * (int)sizeof(T) >= 8 ? 1 : 8 / (NV * (int)sizeof(T));
+    constexpr bool CAN_WIDE = NV * (int)sizeof(T) * B * 2 <= 16;
+    if constexpr (CAN_WIDE) {
+        if (tune.stream_wide && S.ncol % (2 * B) == 0) return stream_rw<T, NV, 2 * B>(S, in, out, tune, st);
     }
-    if (vec2) return stream_vec<T, NV, (want == 2 ? 2 : 1), 1>(S, in, out, rows, st);
-    return stream_vec<T, NV, 1, 1>(S, in, out, rows, st);
+    if constexpr (B > 1) {
+        if (S.ncol % B != 0) return stream_rw<T, NV, 1>(S, in, out, tune, st);
+    }
+    return stream_rw<T, NV, B>(S, in, out, tune, st);
 }
 
 int max_lds_per_block() {
-    static int v = -1;
-    if (v < 0) {
+    static const int v = [] {
         int dev = 0, x = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
             x = 65536;
-        v = x;
-    }
+        return x;
+    }();
     return v;
 }
 
@@ -428,11 +434,14 @@ template <class T, int NV, int Q>
 hipError_t ab_launch(const AbArgs<T>& A, const T* c, T* y, int threads, size_t lds, int64_t passes,
                      hipStream_t st) {
     auto kern = k_ab<T, NV, Q>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+    // raise the dynamic LDS limit to the hardware maximum once per instantiation (thread-safe,
+    // and never inside a stream capture after the first eager launch)
+    static const hipError_t attr = max_lds_per_block() > 65536
+                                       ? hipFuncSetAttribute((const void*)kern,
+                                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                             max_lds_per_block())
+                                       : hipSuccess;
+    if (lds > 65536 && attr != hipSuccess) return attr;
     hipLaunchKernelGGL(kern, dim3((unsigned)A.na, (unsigned)passes), dim3(threads), lds, st, A, c,
                        y);
     return hipGetLastError();

@@ -100,6 +100,27 @@ __global__ void k_argmin_final(const double* pv, const int64_t* pi, int nblk, do
     *oi = bi;
 }
 
+// out[i*nv + v] = src[v*N + i] for v < cnt (as T), 0 for cnt <= v < nv: the
+// interleaved layout of a block sigma, k values of one determinant contiguous
+template <class T>
+__global__ void __launch_bounds__(kVB) k_interleave(const double* __restrict__ src, int cnt, int nv,
+                                                    int64_t N, T* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * kVB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kVB)
+        for (int v = 0; v < nv; ++v) out[i * nv + v] = v < cnt ? (T)src[(size_t)v * N + i] : (T)0;
+}
+
+// dst[v*N + i] = y[i*nv + v] (+ shift * x[v*N + i] when x is given), v < cnt
+template <class T>
+__global__ void __launch_bounds__(kVB) k_deinterleave(const T* __restrict__ y, int cnt, int nv,
+                                                      int64_t N, const double* __restrict__ x,
+                                                      double shift, double* __restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * kVB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kVB)
+        for (int v = 0; v < cnt; ++v) {
+            const double a = (double)y[i * nv + v];
+            dst[(size_t)v * N + i] = x ? a + shift * x[(size_t)v * N + i] : a;
+        }
+}
+
 // block maxima of v, then the maximum of the block values
 __global__ void __launch_bounds__(kVB) k_max(const double* __restrict__ v, int64_t N, double* pv) {
     double b = -INFINITY;
@@ -184,6 +205,26 @@ hipError_t launch_argmin_after(const double* v, int64_t N, double vprev, int64_t
                        d_val, d_idx);
     return hipGetLastError();
 }
+
+template <class T>
+hipError_t launch_interleave(const double* src, int cnt, int nv, int64_t N, T* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_interleave<T>, dim3(red_blocks(N)), dim3(kVB), 0, st, src, cnt, nv, N, out);
+    return hipGetLastError();
+}
+template hipError_t launch_interleave<double>(const double*, int, int, int64_t, double*, hipStream_t);
+template hipError_t launch_interleave<float>(const double*, int, int, int64_t, float*, hipStream_t);
+
+template <class T>
+hipError_t launch_deinterleave(const T* y, int cnt, int nv, int64_t N, const double* x, double shift,
+                               double* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_deinterleave<T>, dim3(red_blocks(N)), dim3(kVB), 0, st, y, cnt, nv, N, x,
+                       shift, dst);
+    return hipGetLastError();
+}
+template hipError_t launch_deinterleave<double>(const double*, int, int, int64_t, const double*, double,
+                                                double*, hipStream_t);
+template hipError_t launch_deinterleave<float>(const float*, int, int, int64_t, const double*, double,
+                                               double*, hipStream_t);
 
 hipError_t launch_max(const double* v, int64_t N, double* d_val, double* d_part, hipStream_t st) {
     unsigned nb = red_blocks(N);

@@ -29,13 +29,15 @@ std::map<Key, SigmaTune> g_cache;
 
 std::vector<SigmaTune> tune_candidates() {
     std::vector<SigmaTune> out;
-    for (int rw : {1, 2})
-        for (int lds : {49152, 98304, 147456}) {
-            SigmaTune t;
-            t.stream_rw = rw;
-            t.ab_lds_bytes = lds;
-            out.push_back(t);
-        }
+    for (int wide : {0, 1})
+        for (int rw : {1, 2})
+            for (int lds : {49152, 98304, 147456}) {
+                SigmaTune t;
+                t.stream_rw = rw;
+                t.ab_lds_bytes = lds;
+                t.stream_wide = wide;
+                out.push_back(t);
+            }
     return out;
 }
 
@@ -113,18 +115,22 @@ extern "C" int sbd_autotune(const sbd_basis* b, const sbd_exc* x, sbd_ham* H, in
     return SBD_OK;
 }
 
-extern "C" int sbd_get_tune(const sbd_ham* H, int prec, int* stream_rw, int* ab_lds_bytes) {
+extern "C" int sbd_get_tune(const sbd_ham* H, int prec, int* stream_rw, int* ab_lds_bytes,
+                            int* stream_wide) {
     if (!H || (prec != SBD_FP64 && prec != SBD_FP32)) return fail(SBD_ERR_ARG, "bad argument");
     if (stream_rw) *stream_rw = H->tune[prec].stream_rw;
     if (ab_lds_bytes) *ab_lds_bytes = H->tune[prec].ab_lds_bytes;
+    if (stream_wide) *stream_wide = H->tune[prec].stream_wide;
     return SBD_OK;
 }
 
-extern "C" int sbd_set_tune(sbd_ham* H, int prec, int stream_rw, int ab_lds_bytes) {
+extern "C" int sbd_set_tune(sbd_ham* H, int prec, int stream_rw, int ab_lds_bytes, int stream_wide) {
     if (!H || (prec != SBD_FP64 && prec != SBD_FP32)) return fail(SBD_ERR_ARG, "bad argument");
     if (stream_rw != 1 && stream_rw != 2) return fail(SBD_ERR_ARG, "stream_rw must be 1 or 2");
     if (ab_lds_bytes < 4096 || ab_lds_bytes > (1 << 20)) return fail(SBD_ERR_ARG, "bad LDS budget");
+    if (stream_wide != 0 && stream_wide != 1) return fail(SBD_ERR_ARG, "stream_wide must be 0 or 1");
     H->tune[prec].stream_rw = stream_rw;
     H->tune[prec].ab_lds_bytes = ab_lds_bytes;
+    H->tune[prec].stream_wide = stream_wide;
     return SBD_OK;
 }

@@ -327,6 +327,28 @@ def test_davidson_mixed_residual_certified_by_oracle(nroots):
         assert abs(np.linalg.norm(U[r]) - 1.0) <= 1e-12
 
 
+@pytest.mark.parametrize("nroots,prec", [(1, 0), (1, 1), (3, 0), (4, 1)])
+def test_davidson_graph_replay_identical(nroots, prec):
+    """Sigma sequences replayed from captured HIP graphs (captured on second
+    use, replayed many times with the solver's own eager passes and host
+    synchronisations in between) give bitwise the same solve as eager
+    launches: energies, iteration counts and eigenvectors.  nroots > 1 also
+    exercises the interleaved block sigma."""
+    W = wl.make_config("sel16", nstr=300)
+    _, _, ham = from_workload(W)
+    out = []
+    for g in (0, 1):
+        vec = torch.empty(nroots * W.ndet, device=DEV, dtype=torch.float64)
+        e, rep, st = sbd.davidson(ham, nroots, vectors=vec, tol_residual=1e-7, sigma_prec=prec,
+                                  use_graph=g)
+        assert st == 0
+        out.append((e, rep, vec.cpu().numpy()))
+    (e0, r0, v0), (e1, r1, v1) = out
+    assert np.array_equal(e0, e1)
+    assert r0["iterations"] == r1["iterations"] and r0["sigma_calls"] == r1["sigma_calls"]
+    assert np.array_equal(v0, v1)
+
+
 def test_davidson_full_sel16_residual_by_oracle():
     """Full-size solve; the oracle checks the returned eigenpair on sampled rows."""
     W = wl.make_config("sel16")
@@ -384,26 +406,32 @@ def test_error_paths_on_gpu():
 # ------------------------------------------------------------------ launch configurations
 @pytest.mark.parametrize("rw,lds", [(1, 4096), (2, 4096), (1, 49152), (2, 147456)])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_sigma_every_launch_config(rw, lds, prec):
+@pytest.mark.parametrize("wide", [0, 1])
+@pytest.mark.parametrize("na_str,nb_str", [(333, 257), (336, 260)])
+def test_sigma_every_launch_config(rw, lds, prec, wide, na_str, nb_str):
     """Every schedule the autotuner can pick gives the oracle's sigma: windowed
     alpha-beta staging (tiny LDS budget), several ket rows per group, one or
-    two rows per stream wavefront, odd row counts."""
+    two rows per stream wavefront, 8- or 16-byte lane loads (the wide form
+    applies when the row lengths are multiples of the lane width: 336 x 260),
+    odd row counts; single vectors and two interleaved vectors."""
     norb = 14
-    A = wl.sample_strings(norb, 6, 333, 51)
-    B = wl.sample_strings(norb, 5, 257, 52)
+    A = wl.sample_strings(norb, 6, na_str, 51)
+    B = wl.sample_strings(norb, 5, nb_str, 52)
     h, eri, ec = wl.make_integrals(norb, 53)
     _, _, ham = gpu_system(norb, 6, 5, A, B, h, eri, ec)
-    ham.set_tune(prec, rw, lds)
-    assert ham.get_tune(prec) == dict(stream_rw=rw, ab_lds_bytes=lds)
+    ham.set_tune(prec, rw, lds, wide)
+    assert ham.get_tune(prec) == dict(stream_rw=rw, ab_lds_bytes=lds, stream_wide=wide)
     S = oracle.OracleSystem(norb, A, B, h, eri, ec)
-    x = wl.random_vector(S.N, 54)[0]
-    if prec == 0:
-        assert rel(gpu_sigma(ham, x), S.sigma(x)) <= 1e-12
-    else:
-        shift = S.diag().min()
-        x32 = x.astype(np.float32).astype(np.float64)
-        y = gpu_sigma(ham, x32, prec=1, shift=shift)
-        assert rel(y, S.sigma(x32) - shift * x32) <= 2e-5
+    X = wl.random_vector(S.N, 54, nvec=2)
+    shift = 0.0 if prec == 0 else S.diag().min()
+    if prec == 1:
+        X = X.astype(np.float32).astype(np.float64)
+    ref = [S.sigma(X[v]) - shift * X[v] for v in range(2)]
+    tol = 1e-12 if prec == 0 else 2e-5
+    assert rel(gpu_sigma(ham, X[0], prec=prec, shift=shift), ref[0]) <= tol
+    Y = gpu_sigma(ham, X.T.reshape(-1), prec=prec, shift=shift, nvec=2, layout=1).reshape(S.N, 2)
+    for v in range(2):
+        assert rel(Y[:, v], ref[v]) <= tol
 
 
 def test_autotune_then_sigma():
