@@ -200,8 +200,8 @@ def stats_summary(csv_path, top=25):
     return "\n".join(out)
 
 
-def _counter_means(csv_path, counter):
-    """Mean counter value per dispatch, per short kernel name."""
+def _counter_values(csv_path, counter):
+    """Counter value of every dispatch, per short kernel name."""
     acc = {}
     per_dispatch = {}
     for r in _csv_rows(csv_path):
@@ -211,7 +211,7 @@ def _counter_means(csv_path, counter):
         per_dispatch[key] = per_dispatch.get(key, 0.0) + float(_col(r, "Counter_Value"))
     for (_, k), v in per_dispatch.items():
         acc.setdefault(k, []).append(v)
-    return {k: sum(v) / len(v) for k, v in acc.items()}
+    return acc
 
 
 def traffic_summary(fetch_csv, write_csv, kernel_json, workload):
@@ -220,9 +220,13 @@ def traffic_summary(fetch_csv, write_csv, kernel_json, workload):
     known size in the same --kernel-only run."""
     info = json.loads([l for l in open(kernel_json) if l.startswith("{")][-1])
     kernel = info["stream_kernel"]
-    fetch = _counter_means(fetch_csv, "FETCH_SIZE")
-    write = _counter_means(write_csv, "WRITE_SIZE")
-    copy = next(k for k in fetch if "copyBuffer" in k or "copy" in k.lower())
+    fv = _counter_values(fetch_csv, "FETCH_SIZE")
+    wv = _counter_values(write_csv, "WRITE_SIZE")
+    # the calibration copy is the largest blit of the run (the others upload inputs)
+    copy = next(k for k in fv if "copyBuffer" in k)
+    fetch = {k: sum(v) / len(v) for k, v in fv.items()}
+    write = {k: sum(v) / len(v) for k, v in wv.items()}
+    fetch[copy], write[copy] = max(fv[copy]), max(wv[copy])
     f_scale = info["copy_bytes_read"] / (1024.0 * fetch[copy])
     w_scale = info["copy_bytes_written"] / (1024.0 * write[copy])
     kf, kw = fetch[kernel] * 1024.0, write[kernel] * 1024.0
@@ -231,6 +235,7 @@ def traffic_summary(fetch_csv, write_csv, kernel_json, workload):
              f"WRITE_SIZE {write[kernel]:.0f} KiB/dispatch (x{w_scale:.3f}); calibration copy "
              f"{copy}: read {info['copy_bytes_read']} B, FETCH_SIZE {fetch[copy]:.0f} KiB, "
              f"WRITE_SIZE {write[copy]:.0f} KiB",
+             f"# mean over {len(fv[kernel])} dispatches (alpha and beta launches)",
              f"{kernel} {workload} {kernel_source_hash()} {total:.0f}"]
     return "\n".join(lines)
 
