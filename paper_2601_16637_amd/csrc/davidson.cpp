@@ -27,7 +27,8 @@
 // though each FP32 sigma is only good to ~1e-7 relative.  The subspace is
 // refreshed (collapsed onto the Ritz vectors, their sigma recomputed in FP64)
 // only when the inner residuals reach the target, when a root's error bound
-// exceeds a fifth of its residual, or when the residual stops improving.  Each
+// exceeds a fifth of its residual (or, as a fallback, after 2*max_space
+// iterations without an exact residual).  Each
 // refresh measures the true error of the collapsed sigma and rescales rho to
 // it.  Convergence is only declared on exact (all-FP64) residuals.
 #include <algorithm>
@@ -484,7 +485,6 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     std::vector<double> evals, Z;
     int it = 0;
     bool converged = false;
-    double best_inner = INFINITY;
     int since_cert = 0;
     bool certified = true;  // residuals computed from an all-FP64 W
     std::vector<double> ebnd(k, 0.0);
@@ -543,19 +543,20 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         }
         if (it >= o.max_iter) break;
 
-        const double rmax = *std::max_element(rnorm.begin(), rnorm.end());
         bool refine = false;
         if (certified) {
-            best_inner = INFINITY;
             since_cert = 0;
         } else {
             ++since_cert;
-            const bool stagnant = since_cert >= 3 && rmax > 0.7 * best_inner;
+            // No refresh merely because the residual progresses slowly: a refresh
+            // collapses the subspace, and collapsing during a plateau keeps the
+            // solver from ever finding a lower state the subspace is building towards.
+            // The long-run fallback covers a mis-calibrated error scale.
+            const bool overdue = since_cert >= 2 * ms;
             bool err_dominated = false;
             for (int r = 0; r < k; ++r)
                 err_dominated = err_dominated || (rnorm[r] > o.tol_residual && ebnd[r] > 0.2 * rnorm[r]);
-            refine = inner_conv || err_dominated || stagnant;
-            best_inner = std::min(best_inner, rmax);
+            refine = inner_conv || err_dominated || overdue;
         }
         if (S.mixed && refine) {
             // collapse onto the Ritz vectors and recompute their sigma in FP64;

@@ -23,7 +23,6 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from itertools import combinations
 
 import numpy as np
 
@@ -66,11 +65,20 @@ def make_integrals(norb: int, seed: int):
 
 
 def all_strings(norb: int, n: int) -> np.ndarray:
-    """Every occupation string with ``n`` of ``norb`` bits set, ascending."""
-    out = np.fromiter((sum(1 << p for p in c) for c in combinations(range(norb), n)),
-                      dtype=np.uint64, count=math.comb(norb, n))
+    """Every occupation string with ``n`` of ``norb`` bits set, ascending.
+
+    Built by the recurrence S(m, k) = S(m-1, k) + (S(m-1, k-1) with bit m-1 set)."""
+    level = [np.zeros(1, dtype=np.uint64)] + [np.zeros(0, dtype=np.uint64)] * n  # m = 0
+    for m in range(1, norb + 1):
+        bit = np.uint64(1) << np.uint64(m - 1)
+        level = [level[0]] + [np.concatenate([level[k], level[k - 1] | bit])
+                              for k in range(1, n + 1)]
+    out = level[n].copy()
     out.sort()
     return out
+
+
+_POPCOUNT8 = np.array([bin(i).count("1") for i in range(256)], dtype=np.int64)
 
 
 def _level(strings: np.ndarray, n: int) -> np.ndarray:
@@ -78,8 +86,7 @@ def _level(strings: np.ndarray, n: int) -> np.ndarray:
     x = strings & ~aufbau
     # popcount of uint64 via byte table
     b = x.view(np.uint8).reshape(-1, 8)
-    table = np.array([bin(i).count("1") for i in range(256)], dtype=np.int64)
-    return table[b].sum(axis=1)
+    return _POPCOUNT8[b].sum(axis=1)
 
 
 def sample_strings(norb: int, n: int, count: int, seed: int,
@@ -117,17 +124,26 @@ def sample_strings(norb: int, n: int, count: int, seed: int,
     ks = np.arange(kmax + 1)
     wk = np.array([math.comb(n, k) * math.comb(norb - n, k) * math.exp(-decay * k) for k in ks])
     pk = wk / wk.sum()
-    chosen = {aufbau}
+    # candidates in batches, in draw order: level k, then k holes among the
+    # occupied and k particles among the empty orbitals (random orders, first k);
+    # the first occurrence of each string is kept until `count` are chosen
+    chosen, seen = [aufbau], {aufbau}
+    one = np.uint64(1)
     while len(chosen) < count:
-        k = int(rng.choice(kmax + 1, p=pk))
-        holes = rng.choice(n, k, replace=False)
-        parts = rng.choice(norb - n, k, replace=False) + n
-        s = aufbau
-        for q in holes:
-            s &= ~(1 << int(q))
-        for q in parts:
-            s |= 1 << int(q)
-        chosen.add(s)
+        M = max(1024, 2 * (count - len(chosen)))
+        ks = rng.choice(kmax + 1, size=M, p=pk)
+        holes = np.argsort(rng.random((M, n)), axis=1)[:, :kmax].astype(np.uint64)
+        parts = (np.argsort(rng.random((M, norb - n)), axis=1)[:, :kmax] + n).astype(np.uint64)
+        cand = np.full(M, np.uint64(aufbau), dtype=np.uint64)
+        for j in range(kmax):
+            sel = ks > j
+            cand[sel] = (cand[sel] & ~(one << holes[sel, j])) | (one << parts[sel, j])
+        for v in cand.tolist():
+            if v not in seen:
+                seen.add(v)
+                chosen.append(v)
+                if len(chosen) == count:
+                    break
     return np.array(sorted(chosen), dtype=np.uint64)
 
 
