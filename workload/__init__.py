@@ -67,12 +67,25 @@ def make_integrals(norb: int, seed: int):
 def all_strings(norb: int, n: int) -> np.ndarray:
     """Every occupation string with ``n`` of ``norb`` bits set, ascending.
 
-    Built by the recurrence S(m, k) = S(m-1, k) + (S(m-1, k-1) with bit m-1 set)."""
-    level = [np.zeros(1, dtype=np.uint64)] + [np.zeros(0, dtype=np.uint64)] * n  # m = 0
+    Built by the recurrence S(m, k) = S(m-1, k) + (S(m-1, k-1) with bit m-1 set),
+    keeping only the k that can still reach n; for n > norb/2 the strings are the
+    complements of the (norb - n)-subsets."""
+    if 2 * n > norb:
+        full = np.uint64((1 << norb) - 1)
+        out = all_strings(norb, norb - n) ^ full
+        out.sort()
+        return out
+    level = {0: np.zeros(1, dtype=np.uint64)}
     for m in range(1, norb + 1):
         bit = np.uint64(1) << np.uint64(m - 1)
-        level = [level[0]] + [np.concatenate([level[k], level[k - 1] | bit])
-                              for k in range(1, n + 1)]
+        lo, hi = max(0, n - (norb - m)), min(m, n)
+        nxt = {}
+        for k in range(lo, hi + 1):
+            parts = [level[k]] if k in level else []
+            if k - 1 in level:
+                parts.append(level[k - 1] | bit)
+            nxt[k] = np.concatenate(parts) if parts else np.zeros(0, dtype=np.uint64)
+        level = nxt
     out = level[n].copy()
     out.sort()
     return out
