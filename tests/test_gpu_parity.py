@@ -236,22 +236,33 @@ def test_sigma_deterministic_bitwise():
 
 
 @pytest.mark.parametrize("name", ["sel16", "sel26"])
-def test_sigma_full_size_sampled(name):
-    """Full-size basis in the launch configuration the benchmark uses: sampled
-    outputs against the oracle computed one determinant at a time."""
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sigma_full_size_sampled(name, prec):
+    """Full-size basis in the launch configuration the benchmark uses (autotuned
+    for this shape and precision): sampled outputs against the oracle computed
+    one determinant at a time.  FP32: the oracle takes the FP32-rounded input
+    and the same shift."""
     W = wl.make_config(name)
     _, _, ham = from_workload(W)
+    ham.autotune(prec)
     N = W.ndet
     rng = np.random.default_rng(31)
     x = rng.standard_normal(N)
     x /= np.linalg.norm(x)
-    y = gpu_sigma(ham, x)
     S = oracle.OracleSystem.from_workload(W)
     idx = np.unique(np.concatenate([rng.integers(0, N, 3000), [0, N - 1, W.beta.size - 1,
                                                                W.beta.size, N // 2]]))
-    yo = S.sigma_at(x, idx)
-    assert rel(y[idx], yo) <= 1e-12
-    assert np.abs(y[idx] - yo).max() <= 1e-11 * np.abs(yo).max()
+    if prec == 0:
+        y = gpu_sigma(ham, x)
+        yo = S.sigma_at(x, idx)
+        assert rel(y[idx], yo) <= 1e-12
+        assert np.abs(y[idx] - yo).max() <= 1e-11 * np.abs(yo).max()
+    else:
+        shift = float(S.diag().min())
+        x32 = x.astype(np.float32).astype(np.float64)
+        y = gpu_sigma(ham, x32, prec=1, shift=shift)
+        yo = S.sigma_at(x32, idx) - shift * x32[idx]
+        assert rel(y[idx], yo) <= 2e-5
 
 
 # ------------------------------------------------------------------ a6 Davidson
@@ -361,6 +372,28 @@ def test_davidson_full_sel16_residual_by_oracle():
     idx = np.argsort(-np.abs(u))[:400]
     r = S.sigma_at(u, idx) - e[0] * u[idx]
     assert np.linalg.norm(r) <= 1e-6
+    assert e[0] <= S.diag().min()
+
+
+def test_davidson_full_sel26_chosen_form_residual_by_oracle():
+    """The benchmark's solve (sel26, N = 1e8, FP32 sigma with FP64 refinement,
+    10-vector subspace, autotuned): the oracle's FP64 sigma of the returned
+    vector, on its largest and on random components, leaves a residual within
+    the tolerance, and the energy lies below every diagonal element."""
+    W = wl.make_config("sel26")
+    _, _, ham = from_workload(W)
+    vec = torch.empty(W.ndet, device=DEV, dtype=torch.float64)
+    e, rep, st = sbd.davidson(ham, 1, vectors=vec, tol_residual=1e-6, sigma_prec=sbd.FP32,
+                              max_space=10, use_autotune=1)
+    assert st == 0 and rep["converged"] and rep["sigma_calls_fp64"] < rep["sigma_calls"]
+    u = vec.cpu().numpy()
+    del vec
+    S = oracle.OracleSystem.from_workload(W)
+    rng = np.random.default_rng(41)
+    idx = np.unique(np.concatenate([np.argsort(-np.abs(u))[:300], rng.integers(0, u.size, 300)]))
+    r = S.sigma_at(u, idx) - e[0] * u[idx]
+    assert np.linalg.norm(r) <= 1e-6
+    assert abs(np.linalg.norm(u) - 1.0) <= 1e-12
     assert e[0] <= S.diag().min()
 
 
