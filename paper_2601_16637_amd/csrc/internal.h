@@ -232,7 +232,6 @@ hipError_t launch_sigma(const SigmaArgs<T>& A, int nvec, const T* c, T* y, int l
 hipError_t launch_combination(const double* A, int m, const double* d_Y, int ldy, int k,
                               double* out, int64_t N, hipStream_t st);
 hipError_t launch_scale(double* x, int64_t N, double s, hipStream_t st);
-hipError_t launch_copy(const double* x, double* y, int64_t N, hipStream_t st);
 // lexicographic successor minimum: smallest (v,i) > (vprev, iprev); writes value/index
 hipError_t launch_argmin_after(const double* v, int64_t N, double vprev, int64_t iprev,
                                double* d_val, int64_t* d_idx, double* d_part_v,

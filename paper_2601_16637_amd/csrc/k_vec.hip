@@ -42,11 +42,6 @@ __global__ void k_scale(double* x, int64_t N, double s) {
         x[i] *= s;
 }
 
-__global__ void k_copy(const double* x, double* y, int64_t N) {
-    for (int64_t i = (int64_t)blockIdx.x * kVB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kVB)
-        y[i] = x[i];
-}
-
 __device__ __forceinline__ bool lex_less(double v1, int64_t i1, double v2, int64_t i2) {
     return v1 < v2 || (v1 == v2 && i1 < i2);
 }
@@ -187,11 +182,6 @@ hipError_t launch_combination(const double* A, int m, const double* d_Y, int ldy
 
 hipError_t launch_scale(double* x, int64_t N, double s, hipStream_t st) {
     hipLaunchKernelGGL(k_scale, dim3(red_blocks(N)), dim3(kVB), 0, st, x, N, s);
-    return hipGetLastError();
-}
-
-hipError_t launch_copy(const double* x, double* y, int64_t N, hipStream_t st) {
-    hipLaunchKernelGGL(k_copy, dim3(red_blocks(N)), dim3(kVB), 0, st, x, y, N);
     return hipGetLastError();
 }
 
