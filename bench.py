@@ -38,10 +38,10 @@ def log(*a):
 
 
 def kernel_source_hash():
-    """Hash of the sigma kernel source: traffic figures are valid only for it."""
+    """Hash of the sigma kernel source (the row-stream kernel and its launcher
+    live in k_sigma.hip): traffic figures are valid only for it."""
     h = hashlib.sha256()
-    for f in ("k_sigma.hip", "internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2601_16637_amd", "csrc", f), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_2601_16637_amd", "csrc", "k_sigma.hip"), "rb").read())
     return h.hexdigest()[:16]
 
 
