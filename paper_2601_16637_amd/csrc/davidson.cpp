@@ -560,9 +560,11 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         }
         if (S.mixed && refine) {
             // collapse onto the Ritz vectors and recompute their sigma in FP64;
-            // the collapsed mixed sigma (kept in tmp) calibrates rho
+            // the collapsed mixed sigma (kept in tmp) calibrates rho.  A refresh
+            // that certifies (inner residuals already at the target) keeps only the
+            // k roots: the solve most likely ends with it.
             auto tr0 = clk::now();
-            const int kk = std::min(S.keep, m);
+            const int kk = std::min(inner_conv ? k : S.keep, m);
             std::vector<double> pred(kk, 0.0);
             for (int c = 0; c < kk; ++c) {
                 double s2 = 0.0;
