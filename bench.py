@@ -19,6 +19,11 @@ import os
 import sys
 import time
 
+# One hardware queue per serving worker stream (HIP's default is 4 per process):
+# with fewer, a small request's kernels wait behind a large request's kernels in
+# a shared queue.  Must be set before the runtime starts.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -128,7 +133,7 @@ def cpu_baseline(W, target_s=15.0):
                        f"({dt:.1f} s, C oracle, OpenMP over rows)")
 
 
-def serving(sbd, wl, nreq=256, budget=96 << 30, inflight=8):
+def serving(sbd, wl, nreq=256, budget=96 << 30, inflight=16):
     """Serving stream: Poisson arrivals at 20/s of solves with 1e4-2e7
     determinants (norb 12-32, 1-2 roots, FP32 sigma + FP64 refinement);
     each request is generated at its arrival time and submitted then."""
@@ -155,6 +160,7 @@ def serving(sbd, wl, nreq=256, budget=96 << 30, inflight=8):
     apps = sum(r["ndet"] * r["report"]["sigma_calls"] for _, r in res)
     conv = sum(1 for _, r in res if r["report"]["converged"])
     return dict(requests=nreq, rate_per_s=20.0, budget_bytes=budget, max_inflight=inflight,
+                hw_queues=int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
                 failed=len(bad), converged=conv, wall_s=wall,
                 latency_p50_ms=float(np.percentile(lat, 50)),
                 latency_p99_ms=float(np.percentile(lat, 99)),
