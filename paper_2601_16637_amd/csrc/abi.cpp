@@ -7,6 +7,7 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <numeric>
 #include <string>
 
 #include "internal.h"
@@ -131,6 +132,35 @@ int sbd_basis_strings(const sbd_basis* b, uint64_t* a, uint64_t* bb) {
 void sbd_free_basis(sbd_basis* b) { delete b; }
 
 // ------------------------------------------------------------------ tables
+// Position -> string map of the sliced-ELL singles table.  The alpha-beta
+// kernel's thread t handles positions t + q*W (W = its workgroup size, one per
+// window of W positions), a wavefront 64 consecutive positions per window, and a
+// workgroup lasts as long as its slowest wavefront.  Inside each window the
+// strings are sorted by descending row length (64-position slices of similar
+// lengths: little padding), and the window's slices are rotated by q*(S/2 - 1)
+// (S = slices per window, co-prime with it), so each wavefront meets long and
+// short slices in turn and the wavefronts of a workgroup carry similar work.
+static std::vector<int32_t> sell_positions(const std::vector<int64_t>& rp, int W) {
+    const int64_t n = (int64_t)rp.size() - 1;
+    std::vector<int32_t> pos((size_t)std::max<int64_t>(n, 1));
+    std::vector<int32_t> win;
+    for (int64_t w0 = 0, q = 0; w0 < n; w0 += W, ++q) {
+        const int64_t w1 = std::min<int64_t>(n, w0 + W);
+        win.resize((size_t)(w1 - w0));
+        std::iota(win.begin(), win.end(), (int32_t)w0);
+        std::stable_sort(win.begin(), win.end(), [&](int32_t a, int32_t b) {
+            return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
+        });
+        const int64_t S = (w1 - w0) / 64;  // whole slices (a short last window is not rotated)
+        const int64_t r = (S > 1 && (w1 - w0) % 64 == 0) ? (q * (W / 128 - 1)) % S : 0;
+        for (int64_t j = 0; j < w1 - w0; ++j) {
+            const int64_t sl = j / 64, dst = r ? ((sl + r) % S) * 64 + j % 64 : j;
+            pos[(size_t)(w0 + dst)] = win[(size_t)j];
+        }
+    }
+    return pos;
+}
+
 int sbd_build_excitations(const sbd_basis* b, void* stream, sbd_exc** out) {
     if (!b || !out) return fail(SBD_ERR_ARG, "null argument");
     *out = nullptr;
@@ -180,12 +210,28 @@ int sbd_build_excitations(const sbd_basis* b, void* stream, sbd_exc** out) {
         if (e == hipSuccess)
             e = launch_pack_singles(t1.nnz, t1.J.as<int32_t>(), t1.orb.as<uint32_t>(),
                                     t1.sign.as<int8_t>(), t1.pack.as<uint64_t>(), st);
-        // sliced-ELL copy of the singles (used when this spin is gathered per lane)
+        // sliced-ELL copy of the singles (used when this spin is gathered per lane),
+        // over positions that balance the work of the alpha-beta kernel's wavefronts
         const int64_t nslice = (n + 63) / 64;
+        std::vector<int64_t> rp_h((size_t)n + 1);
+        std::vector<int32_t> pos;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(rp_h.data(), t1.row_ptr.p, sizeof(int64_t) * (size_t)(n + 1),
+                               hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) {
+            pos = sell_positions(rp_h, ab_block_threads(n));
+            e = t1.sell_pos.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+        }
+        if (e == hipSuccess && n > 0)
+            e = hipMemcpyAsync(t1.sell_pos.p, pos.data(), sizeof(int32_t) * (size_t)n,
+                               hipMemcpyHostToDevice, st);
         DevBuf slots;
         if (e == hipSuccess) e = slots.alloc(sizeof(int64_t) * (size_t)std::max<int64_t>(nslice, 1));
         if (e == hipSuccess) e = t1.sell_off.alloc(sizeof(int64_t) * (size_t)(nslice + 1));
-        if (e == hipSuccess) e = launch_sell_len(t1.row_ptr.as<int64_t>(), n, slots.as<int64_t>(), st);
+        if (e == hipSuccess)
+            e = launch_sell_len(t1.row_ptr.as<int64_t>(), t1.sell_pos.as<int32_t>(), n,
+                                slots.as<int64_t>(), st);
         if (e == hipSuccess)
             e = launch_exclusive_scan(slots.as<int64_t>(), nslice, t1.sell_off.as<int64_t>(), st);
         int64_t sell_total = 0;
@@ -198,8 +244,9 @@ int sbd_build_excitations(const sbd_basis* b, void* stream, sbd_exc** out) {
             e = t1.sell.alloc(sizeof(uint64_t) * (size_t)std::max<int64_t>(sell_total, 1));
         }
         if (e == hipSuccess)
-            e = launch_sell_fill(t1.row_ptr.as<int64_t>(), t1.pack.as<uint64_t>(), n,
-                                 t1.sell_off.as<int64_t>(), t1.sell.as<uint64_t>(), st);
+            e = launch_sell_fill(t1.row_ptr.as<int64_t>(), t1.pack.as<uint64_t>(),
+                                 t1.sell_pos.as<int32_t>(), n, t1.sell_off.as<int64_t>(),
+                                 t1.sell.as<uint64_t>(), st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
             delete x;
@@ -359,6 +406,7 @@ SigmaArgs<double> make_args<double>(const sbd_exc* x, const sbd_ham* H, double s
     A.a2p = a2->row_ptr.as<int64_t>(); A.a2J = a2->J.as<int32_t>(); A.a2c = H->sc[0].c2_64.as<double>();
     A.b1p = b1->row_ptr.as<int64_t>(); A.b1J = b1->J.as<int32_t>(); A.b1pack = b1->pack.as<uint64_t>();
     A.b1sell = b1->sell.as<uint64_t>(); A.b1sell_off = b1->sell_off.as<int64_t>();
+    A.b1sell_pos = b1->sell_pos.as<int32_t>();
     A.b1c = H->sc[1].c1_64.as<double>(); A.b1ps = H->sc[1].ps1.as<int32_t>();
     A.b2p = b2->row_ptr.as<int64_t>(); A.b2J = b2->J.as<int32_t>(); A.b2c = H->sc[1].c2_64.as<double>();
     A.Ga = H->sc[0].G64.as<double>(); A.Gb = H->sc[1].G64.as<double>();
@@ -376,6 +424,7 @@ SigmaArgs<float> make_args<float>(const sbd_exc* x, const sbd_ham* H, double shi
     A.a2p = a2->row_ptr.as<int64_t>(); A.a2J = a2->J.as<int32_t>(); A.a2c = H->sc[0].c2_32.as<float>();
     A.b1p = b1->row_ptr.as<int64_t>(); A.b1J = b1->J.as<int32_t>(); A.b1pack = b1->pack.as<uint64_t>();
     A.b1sell = b1->sell.as<uint64_t>(); A.b1sell_off = b1->sell_off.as<int64_t>();
+    A.b1sell_pos = b1->sell_pos.as<int32_t>();
     A.b1c = H->sc[1].c1_32.as<float>(); A.b1ps = H->sc[1].ps1.as<int32_t>();
     A.b2p = b2->row_ptr.as<int64_t>(); A.b2J = b2->J.as<int32_t>(); A.b2c = H->sc[1].c2_32.as<float>();
     A.Ga = H->sc[0].G32.as<float>(); A.Gb = H->sc[1].G32.as<float>();

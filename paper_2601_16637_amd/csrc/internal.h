@@ -101,8 +101,9 @@ struct Table {
     DevBuf orb;      // uint32[nnz]: i | j<<8 | a<<16 | b<<24 (double); i | a<<8 (single)
     DevBuf sign;     // int8[nnz]
     DevBuf pack;     // singles only: uint64 J | i << 32 | a << 40 | (sign < 0) << 48
-    DevBuf sell;     // singles only: pack entries in sliced-ELL order (64-string slices)
+    DevBuf sell;     // singles only: pack entries in sliced-ELL order (64-position slices)
     DevBuf sell_off; // int64[nslice+1]: first entry of each slice (slot-major, 64 per slot)
+    DevBuf sell_pos; // int32[n]: string held by each sliced-ELL position (see sell_positions)
     int64_t sell_entries = 0;
 };
 }  // namespace sbd
@@ -176,9 +177,15 @@ hipError_t launch_exc_fill(const uint64_t* d_s, int64_t n, const int64_t* rp1, c
 hipError_t launch_pack_singles(int64_t nnz, const int32_t* J, const uint32_t* orb, const int8_t* sg,
                                uint64_t* pack, hipStream_t st);
 // sliced-ELL: slots[slice] = 64 * longest row of the slice; then fill from the scan
-hipError_t launch_sell_len(const int64_t* rp, int64_t n, int64_t* slots, hipStream_t st);
-hipError_t launch_sell_fill(const int64_t* rp, const uint64_t* pack, int64_t n, const int64_t* off,
-                            uint64_t* sell, hipStream_t st);
+// Sliced-ELL copy of a singles table over positions p < n, position p holding
+// string pos[p]: slot count per 64-position slice, then the padded fill.
+hipError_t launch_sell_len(const int64_t* rp, const int32_t* pos, int64_t n, int64_t* slots,
+                           hipStream_t st);
+hipError_t launch_sell_fill(const int64_t* rp, const uint64_t* pack, const int32_t* pos, int64_t n,
+                            const int64_t* off, uint64_t* sell, hipStream_t st);
+// Threads per workgroup of the alpha-beta kernel for nb beta strings; a thread
+// handles the positions lane + q * threads, one per window of `threads` positions.
+inline int ab_block_threads(int64_t nb) { return nb > 512 ? 1024 : (nb > 256 ? 512 : 256); }
 
 // Hamiltonian pieces.
 hipError_t launch_string_diag(const uint64_t* d_s, int64_t n, int norb, const double* h,
@@ -208,7 +215,7 @@ struct SigmaArgs {
     // beta tables
     const int64_t* b1p; const int32_t* b1J; const T* b1c; const int32_t* b1ps;
     const uint64_t* b1pack;
-    const uint64_t* b1sell; const int64_t* b1sell_off;
+    const uint64_t* b1sell; const int64_t* b1sell_off; const int32_t* b1sell_pos;
     const int64_t* b2p; const int32_t* b2J; const T* b2c;
     const T* Ga;   // [npair][na]  sum_{k in alpha(ia)} (pair|kk)
     const T* Gb;   // [npair][nb]

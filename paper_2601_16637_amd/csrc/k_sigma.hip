@@ -254,6 +254,7 @@ struct AbArgs {
     int krows;          // alpha singles (ket rows) staged together
     const int64_t* a1p; const uint64_t* a1pack;
     const uint64_t* b1sell; const int64_t* b1sell_off;  // beta singles, sliced-ELL
+    const int32_t* b1pos;                               // beta string of each ELL position
     const T* eri;
 };
 
@@ -283,10 +284,12 @@ __device__ __forceinline__ void stage_row(T* __restrict__ dst, const T* __restri
 // One workgroup = one bra row ia and a block of Q*blockDim columns.  The
 // alpha singles (Ja, i_a -> a_a) of ia are taken K at a time: their ket rows
 // c[Ja][:] (or a window of them) and integral slices (a_a i_a | . .) are staged
-// in LDS, then each thread walks the beta singles of its Q columns.  The beta
+// in LDS, then each thread walks the beta singles of its Q positions.  The beta
 // singles are read from the sliced-ELL table, so entry s of a wavefront's 64
-// columns is one coalesced load; each entry is loaded once per group of K
-// rows, and the Q columns' entries are fetched step by step (independent loads).
+// positions is one coalesced load; each entry is loaded once per group of K
+// rows, and the Q positions' entries are fetched step by step (independent
+// loads).  Position p holds beta string b1pos[p]: the table's positions are
+// arranged so the workgroup's wavefronts carry similar work (sell_positions).
 template <class T, int NV, int Q>
 __global__ void __launch_bounds__(1024) k_ab(AbArgs<T> A, const T* __restrict__ c,
                                              T* __restrict__ y) {
@@ -364,8 +367,9 @@ __global__ void __launch_bounds__(1024) k_ab(AbArgs<T> A, const T* __restrict__ 
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int64_t ib = col0 + (int64_t)q * blockDim.x;
-        if (ib < nb) {
+        const int64_t p = col0 + (int64_t)q * blockDim.x;  // sliced-ELL position
+        if (p < nb) {
+            const int64_t ib = A.b1pos[p];
             T* dst = y + (ia * nb + ib) * NV;
 #pragma unroll
             for (int v = 0; v < NV; ++v) dst[v] += acc[q][v];
@@ -459,7 +463,7 @@ constexpr int ab_qmax() {
 template <class T, int NV>
 hipError_t alpha_beta(AbArgs<T> A, const T* c, T* y, const SigmaTune& tune, hipStream_t st) {
     if (A.na > 0x7fffffffLL) return hipErrorInvalidValue;
-    const int threads = A.nb > 512 ? 1024 : (A.nb > 256 ? 512 : 256);
+    const int threads = ab_block_threads(A.nb);
     constexpr int QM = ab_qmax<T, NV>();
     // column passes (each restages the ket rows), columns spread evenly over them
     const int64_t passes = (A.nb + (int64_t)threads * QM - 1) / ((int64_t)threads * QM);
@@ -528,6 +532,7 @@ hipError_t sigma_nv(const SigmaArgs<T>& A, const T* c, T* y, T* cT, T* yT, const
     AbArgs<T> B{};
     B.na = na; B.nb = nb; B.norb = A.norb;
     B.a1p = A.a1p; B.a1pack = A.a1pack; B.b1sell = A.b1sell; B.b1sell_off = A.b1sell_off;
+    B.b1pos = A.b1sell_pos;
     B.eri = A.eri;
     e = alpha_beta<T, NV>(B, c, y, tune, st);
     if (e == hipSuccess) e = mark(4);

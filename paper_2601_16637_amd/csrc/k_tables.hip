@@ -227,13 +227,14 @@ __global__ void k_pack_singles(int64_t nnz, const int32_t* __restrict__ J,
 // padded to its longest row and stored slot-major (entry s of the slice's 64
 // rows is contiguous), so one wavefront reading entry s of 64 consecutive
 // columns issues one coalesced load.  Padding entries are ~0.
-__global__ void k_sell_len(const int64_t* __restrict__ rp, int64_t n, int64_t nslice,
-                           int64_t* slots) {
+__global__ void k_sell_len(const int64_t* __restrict__ rp, const int32_t* __restrict__ pos,
+                           int64_t n, int64_t nslice, int64_t* slots) {
     const int64_t sl = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (sl >= nslice) return;
-    const int64_t i = sl * 64 + lane;
-    int len = (i < n) ? (int)(rp[i + 1] - rp[i]) : 0;
+    const int64_t p = sl * 64 + lane;
+    const int64_t i = (p < n) ? pos[p] : 0;
+    int len = (p < n) ? (int)(rp[i + 1] - rp[i]) : 0;
     for (int off = 32; off > 0; off >>= 1) {
         const int o = __shfl_xor(len, off, 64);
         len = o > len ? o : len;
@@ -242,15 +243,15 @@ __global__ void k_sell_len(const int64_t* __restrict__ rp, int64_t n, int64_t ns
 }
 
 __global__ void k_sell_fill(const int64_t* __restrict__ rp, const uint64_t* __restrict__ pack,
-                            int64_t n, int64_t nslice, const int64_t* __restrict__ off,
-                            uint64_t* sell) {
+                            const int32_t* __restrict__ pos, int64_t n, int64_t nslice,
+                            const int64_t* __restrict__ off, uint64_t* sell) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nslice * 64) return;
     const int64_t sl = g >> 6;
     const int lane = (int)(g & 63);
     const int64_t len = (off[sl + 1] - off[sl]) / 64;
-    const int64_t i = g;
-    const int64_t r0 = (i < n) ? rp[i] : 0, rl = (i < n) ? rp[i + 1] - rp[i] : 0;
+    const int64_t i = (g < n) ? pos[g] : 0;
+    const int64_t r0 = (g < n) ? rp[i] : 0, rl = (g < n) ? rp[i + 1] - rp[i] : 0;
     for (int64_t s = 0; s < len; ++s)
         sell[off[sl] + s * 64 + lane] = (s < rl) ? pack[r0 + s] : ~0ull;
 }
@@ -300,20 +301,21 @@ hipError_t launch_exc_fill(const uint64_t* d_s, int64_t n, const int64_t* rp1, c
     return hipGetLastError();
 }
 
-hipError_t launch_sell_len(const int64_t* rp, int64_t n, int64_t* slots, hipStream_t st) {
+hipError_t launch_sell_len(const int64_t* rp, const int32_t* pos, int64_t n, int64_t* slots,
+                           hipStream_t st) {
     const int64_t nslice = (n + 63) / 64;
     if (nslice > 0)
-        hipLaunchKernelGGL(k_sell_len, dim3(blocks_for(nslice, 4)), dim3(256), 0, st, rp, n, nslice,
-                           slots);
+        hipLaunchKernelGGL(k_sell_len, dim3(blocks_for(nslice, 4)), dim3(256), 0, st, rp, pos, n,
+                           nslice, slots);
     return hipGetLastError();
 }
 
-hipError_t launch_sell_fill(const int64_t* rp, const uint64_t* pack, int64_t n, const int64_t* off,
-                            uint64_t* sell, hipStream_t st) {
+hipError_t launch_sell_fill(const int64_t* rp, const uint64_t* pack, const int32_t* pos, int64_t n,
+                            const int64_t* off, uint64_t* sell, hipStream_t st) {
     const int64_t nslice = (n + 63) / 64;
     if (nslice > 0)
         hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(nslice * 64, 256)), dim3(256), 0, st, rp,
-                           pack, n, nslice, off, sell);
+                           pack, pos, n, nslice, off, sell);
     return hipGetLastError();
 }
 
