@@ -22,7 +22,7 @@ import time
 # One hardware queue per serving worker stream (HIP's default is 4 per process):
 # with fewer, a small request's kernels wait behind a large request's kernels in
 # a shared queue.  Must be set before the runtime starts.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 import numpy as np
 
