@@ -219,6 +219,7 @@ typedef struct {
     int converged;         /* 1 if every root met tol_residual                                      */
     int restarts;          /* thick restarts (subspace full)                                        */
     int refinements;       /* SBD_FP32: FP64 refreshes of the Ritz basis                            */
+    int reorthogonalisations; /* second Gram-Schmidt passes taken (|t'| < |t|/sqrt(2))              */
     double fp32_error_scale; /* SBD_FP32: calibrated ||sigma32(v) - sigma64(v)|| per unit vector    */
     double residual[64];   /* final ||r||_2 per root                                                */
     double ortho_loss;     /* ||V^T V - I||_F at exit                                               */
@@ -234,7 +235,8 @@ void sbd_davidson_default_opts(sbd_davidson_opts* o);
  * Lowest nroots eigenpairs by the Davidson method (Sec. II-C): sigma of new
  * basis vectors, projected matrix T = V^T W, smallest Ritz pairs, residual
  * r = W y - theta V y, damped diagonal preconditioner (Eqs. 6-7),
- * orthogonalisation against the subspace with a second pass, restart onto
+ * classical Gram-Schmidt against the subspace with a second pass when the
+ * first removes more than 1 - 1/sqrt(2) of the norm, restart onto
  * the lowest Ritz vectors at max_space, block variant for several roots.
  * Initial vectors: opts->guess, else unit vectors on the nroots lowest
  * diagonal elements (lowest index on ties).

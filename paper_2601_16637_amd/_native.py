@@ -50,6 +50,7 @@ class DavidsonReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("sigma_calls", ctypes.c_int),
                 ("sigma_calls_fp64", ctypes.c_int), ("converged", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("refinements", ctypes.c_int),
+                ("reorthogonalisations", ctypes.c_int),
                 ("fp32_error_scale", ctypes.c_double), ("residual", ctypes.c_double * 64),
                 ("ortho_loss", ctypes.c_double), ("t_sigma_ms", ctypes.c_double),
                 ("t_update_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
@@ -61,6 +62,7 @@ class DavidsonReport(ctypes.Structure):
         return dict(iterations=self.iterations, sigma_calls=self.sigma_calls,
                     sigma_calls_fp64=self.sigma_calls_fp64, converged=bool(self.converged),
                     restarts=self.restarts, refinements=self.refinements,
+                    reorthogonalisations=self.reorthogonalisations,
                     fp32_error_scale=self.fp32_error_scale,
                     residual=list(self.residual[:nroots]),
                     ortho_loss=self.ortho_loss, t_sigma_ms=self.t_sigma_ms,

@@ -8,12 +8,13 @@
 // expansion, and a restart onto the lowest Ritz vectors when the subspace is
 // full.  Several roots are solved together as a block.
 //
-// The vector work is three fused sweeps over the subspace per new vector,
-// each with its projections fused in (k_project.hip):
+// The vector work is fused sweeps over the subspace, each with its projections
+// fused in (k_project.hip):
 //   1. residual + preconditioner together with the first projection V^T t,
-//   2. t <- t - V h1 together with h2 = V^T t,
-//   3. v_new <- t - V h2 together with |v_new| and W^T v_new, which is the new
-//      column of T (T_{j,new} = w_j . v_new = v_j . H v_new).
+//   2. v <- t - V h1 together with |v|, V^T v and W^T v (the new column of T:
+//      T_{j,new} = w_j . v_new = v_j . H v_new),
+//   3. only if the first pass cancelled much of t (|v| < |t|/sqrt(2)): a second
+//      classical pass v <- v - V (V^T v) with |v| and W^T v.
 // Only the reduced scalars travel to the host.
 //
 // SBD_FP32 mode (mixed precision): sigma of new basis vectors is computed in
@@ -126,6 +127,10 @@ constexpr int kProj = 2048;   // projection results (<= 48 x 8)
 constexpr int kMisc = 3072;   // argmin value
 constexpr int kOne = 3080;    // the constant 1.0 (Gram-Schmidt coefficient of a difference)
 constexpr int kDiff = 3096;   // |sigma32 - sigma64|^2 rows of a refresh (2 per vector, <= 16 vectors)
+constexpr int kW1 = 3200;     // fused first Gram-Schmidt pass: |t'|^2, V^T t', W^T t' (<= 1 + 48 + 48)
+// A second classical pass runs only when the first removed more than this
+// fraction of the norm: ||t'|| < ||t|| / sqrt(2) (Daniel-Gragg-Kaufman-Stewart)
+constexpr double kReorth = 0.70710678118654752;
 constexpr int kSmall = 4096;
 constexpr int kPartRows = kPassRows;
 
@@ -151,6 +156,7 @@ struct Solver {
     double* sm = nullptr;
     double t_sigma = 0.0;
     int sigma_calls = 0, sigma64 = 0;
+    int reorth = 0;          // second Gram-Schmidt passes taken
     int nvmax = 1;           // widest interleaved block sigma the staging buffers hold
     bool use_graph = false;  // replay each sigma launch sequence from a captured HIP graph
     // captured sigma sequences, keyed by (first row, count, width, FP64); a key is
@@ -272,20 +278,43 @@ struct Solver {
         return SBD_OK;
     }
 
-    // Orthogonalise t against V[0..m) (two classical passes) into V[m]; the first
-    // projection V^T t must be on the device at sm+kH1.  mw rows of W have a
-    // sigma.  On return u holds W[0..mw)^T v_new / |v_new| and accept tells
-    // whether the vector survived (|v_new| > 1e-12 |t|).
+    // Orthogonalise t against V[0..m) into V[m] by classical Gram-Schmidt: a
+    // first pass, and a second one when the first cancelled much of t (norm
+    // below n0/sqrt(2), n0 = |t| before).  The first projection V^T t must be on
+    // the device at sm+kH1.  mw rows of W have a sigma.  On return u holds
+    // W[0..mw)^T v_new / |v_new| and accept tells whether the vector survived
+    // (|v_new| > 1e-12 |t|).
     int orthonormalise(double* t, int m, int mw, double n0, std::vector<double>& u, bool& accept) {
         double* p = part.as<double>();
-        SBD_HIP(pass_sub1(V.as<double>(), m, sm + kH1, t, N, p, sm + kH2, st));
-        SBD_HIP(pass_sub2(V.as<double>(), m, sm + kH2 + 1, t, Vr(m), W.as<double>(), mw, N, p, sm + kP2, st));
+        u.assign(mw, 0.0);
+        const double* h2 = sm + kH2 + 1;
+        const double* src = t;
+        if (pass_sub1w_fits(m, mw)) {
+            // first pass straight into V[m], with V^T t' and W^T t' in one sweep
+            SBD_HIP(pass_sub1w(V.as<double>(), m, sm + kH1, t, Vr(m), W.as<double>(), mw, N, p,
+                               sm + kW1, st));
+            std::vector<double> r(1 + m + mw);
+            SBD_HIP(hipMemcpyAsync(r.data(), sm + kW1, sizeof(double) * r.size(), hipMemcpyDeviceToHost, st));
+            SBD_HIP(hipStreamSynchronize(st));
+            const double n1 = std::sqrt(std::max(r[0], 0.0));
+            if (std::isfinite(n1) && n1 >= kReorth * n0 && n1 > 0.0) {
+                accept = true;
+                SBD_HIP(launch_scale(Vr(m), N, 1.0 / n1, st));
+                for (int j = 0; j < mw; ++j) u[j] = r[1 + m + j] / n1;
+                return SBD_OK;
+            }
+            h2 = sm + kW1 + 1;  // second pass from t' in V[m] (in place)
+            src = Vr(m);
+        } else {
+            SBD_HIP(pass_sub1(V.as<double>(), m, sm + kH1, t, N, p, sm + kH2, st));
+        }
+        ++reorth;
+        SBD_HIP(pass_sub2(V.as<double>(), m, h2, src, Vr(m), W.as<double>(), mw, N, p, sm + kP2, st));
         std::vector<double> r(mw + 1);
         SBD_HIP(hipMemcpyAsync(r.data(), sm + kP2, sizeof(double) * (mw + 1), hipMemcpyDeviceToHost, st));
         SBD_HIP(hipStreamSynchronize(st));
         const double n1 = std::sqrt(std::max(r[0], 0.0));
         accept = n1 > 1e-12 * std::max(n0, 1e-300) && std::isfinite(n1);
-        u.assign(mw, 0.0);
         if (!accept) return SBD_OK;
         SBD_HIP(launch_scale(Vr(m), N, 1.0 / n1, st));
         for (int j = 0; j < mw; ++j) u[j] = r[1 + j] / n1;
@@ -700,6 +729,7 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         report->converged = converged ? 1 : 0;
         report->restarts = restarts;
         report->refinements = refinements;
+        report->reorthogonalisations = S.reorth;
         report->fp32_error_scale = S.mixed ? rho : 0.0;
         for (int r = 0; r < 64; ++r) report->residual[r] = r < k ? rnorm[r] : 0.0;
         report->ortho_loss = std::sqrt(ortho);

@@ -269,6 +269,11 @@ hipError_t pass_resid(const double* V, const double* W, int m, int k, const doub
 // t <- t - V h;  rows [0] |t|^2, [1 + j) V_j . t
 hipError_t pass_sub1(const double* V, int m, const double* h, double* t, int64_t N, double* part,
                      double* out, hipStream_t st);
+// dst <- t - V h;  rows [0] |dst|^2, [1 + j) V_j . dst (j < m), [1 + m + j) W_j . dst (j < mw);
+// available when pass_sub1w_fits(m, mw) (dst may alias t)
+bool pass_sub1w_fits(int m, int mw);
+hipError_t pass_sub1w(const double* V, int m, const double* h, const double* t, double* dst,
+                      const double* W, int mw, int64_t N, double* part, double* out, hipStream_t st);
 // dst <- t - V h;  rows [0] |dst|^2, [1 + j) W_j . dst  (j < mw)
 hipError_t pass_sub2(const double* V, int m, const double* h, const double* t, double* dst,
                      const double* W, int mw, int64_t N, double* part, double* out, hipStream_t st);

@@ -32,18 +32,19 @@ namespace {
 constexpr int kTB = 256;       // threads per block
 constexpr int kMaxOut = 8;     // output vectors per pass
 
-enum Mode { RESID = 0, SUB1 = 1, SUB2 = 2, PROJ = 3 };
+enum Mode { RESID = 0, SUB1 = 1, SUB2 = 2, PROJ = 3, SUBW = 4 };
 
 struct PassArgs {
     int64_t N;
     int m;            // rows of V combined elementwise (RESID, SUB1, SUB2)
     int k;            // output vectors
     int mp;           // rows of the projected matrix P (0: no projection)
+    int mw;           // SUBW: rows of W projected besides the m rows of V
     const double* V;  // subspace basis, row j at V + j*N
     const double* W;  // sigma of the basis
     const double* P;  // projected matrix (V or W or A)
     const double* X;  // PROJ: k input vectors; SUB1/SUB2: t
-    double* out;      // RESID: k corrections; SUB1: t (in place); SUB2: destination
+    double* out;      // RESID: k corrections; SUB1: t (in place); SUB2, SUBW: destination
     const double* coef;   // RESID: Y (m x k, row-major); SUB: h (m)
     const double* theta;  // RESID: k Ritz values
     const double* diag;
@@ -70,9 +71,9 @@ constexpr int ept_for(int mb) { return mb <= 8 ? 2 : 1; }
 template <int MODE, int MB, int KO, bool PRJ>
 __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
     constexpr int EPT = ept_for(MB);
-    constexpr int NAJ = PRJ ? MB : 1;                  // accumulator rows
+    constexpr int NAJ = PRJ ? (MODE == SUBW ? 2 * MB : MB) : 1;  // accumulator rows
     constexpr int NAQ = (MODE == RESID || MODE == PROJ) ? KO : 1;
-    __shared__ double red[4][2 * kMaxOut + MB * KO];
+    __shared__ double red[4][MODE == SUBW ? 1 + 2 * MB : 2 * kMaxOut + MB * KO];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = A.m, k = A.k, mp = A.mp;
     const int64_t N = A.N;
@@ -171,6 +172,40 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
                         if (j < mp) acc[j][0] += (MODE == SUB1 ? v[j][u] : w[MODE == SUB2 ? j : 0][u]) * t;
                 }
             }
+        } else if constexpr (MODE == SUBW) {
+            // t' = t - V h with both projections V^T t' (a possible second pass) and
+            // W^T t' (the new column of T when one pass suffices)
+            double v[MB][EPT], w[MB][EPT], x[EPT];
+            const int mw = A.mw;
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) x[u] = in[u] ? A.X[ix[u]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+                if (j < m) {
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) v[j][u] = in[u] ? A.V[(size_t)j * N + ix[u]] : 0.0;
+                }
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+                if (j < mw) {
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) w[j][u] = in[u] ? A.W[(size_t)j * N + ix[u]] : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                double sv = 0.0;
+#pragma unroll
+                for (int j = 0; j < MB; ++j)
+                    if (j < m) sv += v[j][u] * cf[j];
+                const double t = in[u] ? x[u] - sv : 0.0;
+                if (in[u]) A.out[ix[u]] = t;
+                nrm[0] += t * t;
+#pragma unroll
+                for (int j = 0; j < MB; ++j) {
+                    if (j < m) acc[j][0] += v[j][u] * t;
+                    if (j < mw) acc[MB + j][0] += w[j][u] * t;
+                }
+            }
         } else {  // PROJ
             double p[MB][EPT], x[KO][EPT];
 #pragma unroll
@@ -208,10 +243,19 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
             // RESID: [0,k) |r_q|^2, [k,2k) |t_q|^2;  SUB: [0] |t|^2
             if (MODE == RESID && q < KO && q < k) red[wv][q] = x;
             if (MODE == RESID && q >= KO && q - KO < k) red[wv][k + q - KO] = x;
-            if ((MODE == SUB1 || MODE == SUB2) && q == 0) red[wv][0] = x;
+            if ((MODE == SUB1 || MODE == SUB2 || MODE == SUBW) && q == 0) red[wv][0] = x;
         }
     }
-    if constexpr (PRJ) {
+    if constexpr (MODE == SUBW) {
+        // rows [1 + j) V_j . t' (j < m), then [1 + m + j) W_j . t' (j < mw)
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            const double xv = wave_sum(acc[j][0]);
+            const double xw = wave_sum(acc[MB + j][0]);
+            if (lane == 0 && j < m) red[wv][1 + j] = xv;
+            if (lane == 0 && j < A.mw) red[wv][1 + m + j] = xw;
+        }
+    } else if constexpr (PRJ) {
 #pragma unroll
         for (int j = 0; j < NAJ; ++j)
 #pragma unroll
@@ -221,7 +265,7 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
             }
     }
     __syncthreads();
-    const int rows = NR + (PRJ ? mp * kq : 0);
+    const int rows = (MODE == SUBW) ? 1 + m + A.mw : NR + (PRJ ? mp * kq : 0);
     for (int r = tid; r < rows; r += kTB)
         A.part[(size_t)r * gridDim.x + blockIdx.x] = ((red[0][r] + red[1][r]) + red[2][r]) + red[3][r];
 }
@@ -259,13 +303,15 @@ constexpr int held(int mode, int mb, int ko, bool prj) {
            ((mode == RESID)  ? 2 * mb + (prj ? mb * ko : 0)
             : (mode == SUB1) ? mb + (prj ? mb : 0)
             : (mode == SUB2) ? mb + (prj ? 2 * mb : 0)
+            : (mode == SUBW) ? 4 * mb
                              : mb + ko + mb * ko);
 }
 // Instantiations that exist: the PRJ forms within the budget; the non-PRJ
 // Gram-Schmidt forms (also used with no subspace yet, m = 0); the non-PRJ
 // residual forms where the PRJ form of the same size does not fit.
 constexpr bool exists(int mode, int mb, int ko, bool prj) {
-    return (mode == SUB1 || mode == SUB2) && ko != 1 ? false
+    return mode == SUBW                                 ? ko == 1 && prj && held(mode, mb, 1, true) <= kRegBudget
+           : (mode == SUB1 || mode == SUB2) && ko != 1 ? false
            : prj                                    ? held(mode, mb, ko, true) <= kRegBudget
            : mode == PROJ                           ? false
            : mode == RESID                          ? held(mode, mb, ko, true) > kRegBudget
@@ -325,21 +371,24 @@ hipError_t by_ko(int ko, int mb, const PassArgs& A, unsigned* nb, hipStream_t st
 
 bool fits(int mode, int rows, int k, bool prj) {
     const int mb = mb_for(rows), ko = ko_for(k);
-    return mb > 0 && ko > 0 && held(mode, mb, (mode == SUB1 || mode == SUB2) ? 1 : ko, prj) <= kRegBudget;
+    return mb > 0 && ko > 0 &&
+           held(mode, mb, (mode == SUB1 || mode == SUB2 || mode == SUBW) ? 1 : ko, prj) <= kRegBudget;
 }
 
 // One pass; `rows` results reduced into out.  The caller checked fits().
 hipError_t run_pass(int mode, const PassArgs& A, int rows, double* out, hipStream_t st) {
     const bool prj = A.mp > 0;
-    const int need = std::max(mode == PROJ ? 0 : A.m, A.mp);
+    const int need = std::max({mode == PROJ ? 0 : A.m, A.mp, mode == SUBW ? A.mw : 0});
     const int mb = mb_for(need < 1 ? 1 : need);
     const int ko = (mode == RESID || mode == PROJ) ? ko_for(A.k) : 1;
     if (mb < 0 || ko < 0 || rows > kPassRows) return hipErrorInvalidValue;
+    if (mode == SUBW && !fits(SUBW, need, 1, true)) return hipErrorInvalidValue;
     unsigned nb = 0;
     hipError_t e = hipErrorInvalidValue;
     if (mode == RESID) e = prj ? by_ko<RESID, true>(ko, mb, A, &nb, st) : by_ko<RESID, false>(ko, mb, A, &nb, st);
     else if (mode == SUB1) e = prj ? by_mb<SUB1, 1, true>(mb, A, &nb, st) : by_mb<SUB1, 1, false>(mb, A, &nb, st);
     else if (mode == SUB2) e = prj ? by_mb<SUB2, 1, true>(mb, A, &nb, st) : by_mb<SUB2, 1, false>(mb, A, &nb, st);
+    else if (mode == SUBW) e = by_mb<SUBW, 1, true>(mb, A, &nb, st);
     else e = by_ko<PROJ, true>(ko, mb, A, &nb, st);
     if (e != hipSuccess) return e;
     if (rows > 0) hipLaunchKernelGGL(k_reduce, dim3(rows), dim3(kTB), 0, st, A.part, (int)nb, out);
@@ -394,6 +443,19 @@ hipError_t pass_sub1(const double* V, int m, const double* h, double* t, int64_t
     hipError_t e = run_pass(SUB1, A, 1 + A.mp, out, st);
     if (e == hipSuccess && m > 0 && !fused) e = pass_project(V, m, t, 1, N, part, out + 1, st);
     return e;
+}
+
+bool pass_sub1w_fits(int m, int mw) {
+    return m >= 1 && mw >= 0 && fits(SUBW, std::max(m, mw), 1, true);
+}
+
+hipError_t pass_sub1w(const double* V, int m, const double* h, const double* t, double* dst,
+                      const double* W, int mw, int64_t N, double* part, double* out, hipStream_t st) {
+    if (!pass_sub1w_fits(m, mw)) return hipErrorInvalidValue;
+    PassArgs A{};
+    A.N = N; A.m = m; A.k = 1; A.mp = m; A.mw = mw;
+    A.V = V; A.W = W; A.X = t; A.out = dst; A.coef = h; A.part = part;
+    return run_pass(SUBW, A, 1 + m + mw, out, st);
 }
 
 hipError_t pass_sub2(const double* V, int m, const double* h, const double* t, double* dst,

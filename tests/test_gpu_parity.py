@@ -305,6 +305,9 @@ def test_davidson_vs_oracle(name, nstr, nroots):
     e, rep, st = sbd.davidson(ham, nroots, tol_residual=1e-8, max_space=24)
     assert st == 0 and ro.converged
     assert np.abs(e - ro.energies).max() <= 1e-8
+    # one classical pass when it suffices, a second one otherwise: the basis stays orthonormal
+    assert rep["ortho_loss"] <= 1e-10
+    assert 0 <= rep["reorthogonalisations"] <= rep["sigma_calls"]
 
 
 @pytest.mark.parametrize("nroots", [1, 2])
