@@ -203,9 +203,11 @@ typedef struct {
     int max_space;         /* subspace size before restart; default 20 (>= 2*nroots+1)             */
     double precond_delta;  /* delta of the damped denominators (Eq. 7); default 1e-8 Ha            */
     int sigma_prec;        /* SBD_FP64 (plain) or SBD_FP32 (FP32 sigma + FP64 refinement)          */
-    int use_graph;         /* 1: replay each sigma launch sequence (conversions, the five sigma
-                              launches, restore) from a HIP graph captured on its second use; the
-                              solve then runs on a private stream ordered after `stream`          */
+    int use_graph;         /* 1: replay each sigma launch sequence (staging, the five sigma
+                              launches, restore) from a HIP graph captured on its second use; one
+                              graph per (vector count, width, precision) serves every basis row
+                              through a device-resident row index.  The solve then runs on a
+                              private stream ordered after `stream`                               */
     int use_autotune;      /* 1: run sbd_autotune for the sigma shapes this solve uses             */
     const double* guess;   /* optional device pointer, n_guess x N initial vectors (NULL = none)   */
     int n_guess;

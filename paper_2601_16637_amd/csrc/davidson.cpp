@@ -159,10 +159,11 @@ struct Solver {
     int reorth = 0;          // second Gram-Schmidt passes taken
     int nvmax = 1;           // widest interleaved block sigma the staging buffers hold
     bool use_graph = false;  // replay each sigma launch sequence from a captured HIP graph
-    // captured sigma sequences, keyed by (first row, count, width, FP64); a key is
-    // captured on its second use (the first runs eagerly)
-    std::map<std::tuple<int, int, int, bool>, hipGraphExec_t> graphs;
-    std::map<std::tuple<int, int, int, bool>, int> seen;
+    // captured sigma sequences, keyed by (count, width, FP64); a key is captured
+    // on its second use (the first runs eagerly) and serves every basis row
+    std::map<std::tuple<int, int, bool>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, int, bool>, int> seen;
+    DevBuf rowsel;           // device int: basis row of the sigma being replayed
 
     ~Solver() {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
@@ -180,8 +181,10 @@ struct Solver {
         if (e == hipSuccess) e = small.alloc(sizeof(double) * kSmall);
         if (e == hipSuccess) e = idx.alloc(sizeof(int64_t) * (kRedBlocks + 1));
         if (e == hipSuccess) e = sws.alloc(sigma_workspace_bytes(N, nvmax, nvmax > 1 ? 1 : 0, sizeof(double)));
-        if (nvmax > 1 && e == hipSuccess) e = x64.alloc(sizeof(double) * (size_t)nvmax * N);
-        if (nvmax > 1 && e == hipSuccess) e = y64.alloc(sizeof(double) * (size_t)nvmax * N);
+        const bool stage64 = nvmax > 1 || use_graph;  // FP64 staging: block sigma or graph replays
+        if (stage64 && e == hipSuccess) e = x64.alloc(sizeof(double) * (size_t)nvmax * N);
+        if (stage64 && e == hipSuccess) e = y64.alloc(sizeof(double) * (size_t)nvmax * N);
+        if (use_graph && e == hipSuccess) e = rowsel.alloc(sizeof(int));
         if (mixed && e == hipSuccess) e = x32.alloc(sizeof(float) * (size_t)std::max(ms, nvmax) * N);
         if (mixed && e == hipSuccess) e = y32.alloc(sizeof(float) * (size_t)std::max(ms, nvmax) * N);
         if (e != hipSuccess) return hip_fail(e, "sbd_davidson workspace");
@@ -208,29 +211,57 @@ struct Solver {
             if (e == hipSuccess && !rc)
                 e = launch_f32_to_f64_axpy(y32.as<float>(), Vr(j), shift, Wr(j), (int64_t)c * N, st);
         } else if (p64) {
-            e = launch_interleave<double>(Vr(j), c, nv, N, x64.as<double>(), st);
+            e = launch_interleave<double>(Vr(j), nullptr, c, nv, N, x64.as<double>(), st);
             if (e == hipSuccess) rc = sigma_internal(x, H, nv, SBD_FP64, 0.0, x64.p, y64.p, 1, sws.p, st);
             if (e == hipSuccess && !rc)
-                e = launch_deinterleave<double>(y64.as<double>(), c, nv, N, nullptr, 0.0, Wr(j), st);
+                e = launch_deinterleave<double>(y64.as<double>(), c, nv, N, nullptr, 0.0, Wr(j), nullptr, st);
         } else {
-            e = launch_interleave<float>(Vr(j), c, nv, N, x32.as<float>(), st);
+            e = launch_interleave<float>(Vr(j), nullptr, c, nv, N, x32.as<float>(), st);
             if (e == hipSuccess) rc = sigma_internal(x, H, nv, SBD_FP32, shift, x32.p, y32.p, 1, sws.p, st);
             if (e == hipSuccess && !rc)
-                e = launch_deinterleave<float>(y32.as<float>(), c, nv, N, Vr(j), shift, Wr(j), st);
+                e = launch_deinterleave<float>(y32.as<float>(), c, nv, N, Vr(j), shift, Wr(j), nullptr, st);
         }
         if (e != hipSuccess) return hip_fail(e, "sigma staging");
         return rc;
     }
 
-    // The same work, replayed from a captured graph when use_graph is set.
+    // Device-indexed form of the same work for graph replays: the basis row is
+    // read from rowsel on the device, so one captured sequence serves every row.
+    // Vectors always pass through the staging buffers (interleaved form, width 1
+    // included), which makes the launch sequence independent of the row.
+    int sigma_launches_indexed(int c, int nv, bool p64) {
+        const int* dj = rowsel.as<int>();
+        int rc = SBD_OK;
+        hipError_t e = hipSuccess;
+        const int layout = nv > 1 ? 1 : 0;
+        if (p64) {
+            e = launch_interleave<double>(V.as<double>(), dj, c, nv, N, x64.as<double>(), st);
+            if (e == hipSuccess) rc = sigma_internal(x, H, nv, SBD_FP64, 0.0, x64.p, y64.p, layout, sws.p, st);
+            if (e == hipSuccess && !rc)
+                e = launch_deinterleave<double>(y64.as<double>(), c, nv, N, nullptr, 0.0, W.as<double>(), dj, st);
+        } else {
+            e = launch_interleave<float>(V.as<double>(), dj, c, nv, N, x32.as<float>(), st);
+            if (e == hipSuccess) rc = sigma_internal(x, H, nv, SBD_FP32, shift, x32.p, y32.p, layout, sws.p, st);
+            if (e == hipSuccess && !rc)
+                e = launch_deinterleave<float>(y32.as<float>(), c, nv, N, V.as<double>(), shift,
+                                               W.as<double>(), dj, st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "sigma staging");
+        return rc;
+    }
+
+    // The same work, replayed from a captured graph when use_graph is set.  The
+    // graph of a (count, width, precision) is captured on its second use and
+    // serves every basis row: the row index is set on the device before a replay.
     int sigma_group(int j, int c, int nv, bool p64) {
         if (!use_graph) return sigma_launches(j, c, nv, p64);
-        const auto key = std::make_tuple(j, c, nv, p64);
+        SBD_HIP(launch_set_int(rowsel.as<int>(), j, st));
+        const auto key = std::make_tuple(c, nv, p64);
         auto it = graphs.find(key);
         if (it == graphs.end()) {
-            if (seen[key]++ == 0) return sigma_launches(j, c, nv, p64);  // first use: eager
+            if (seen[key]++ == 0) return sigma_launches_indexed(c, nv, p64);  // first use: eager
             SBD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            const int rc = sigma_launches(j, c, nv, p64);
+            const int rc = sigma_launches_indexed(c, nv, p64);
             hipGraph_t g = nullptr;
             const hipError_t e = hipStreamEndCapture(st, &g);
             if (rc) {

@@ -245,12 +245,16 @@ hipError_t launch_argmin_after(const double* v, int64_t N, double vprev, int64_t
                                int64_t* d_part_i, hipStream_t st);
 hipError_t launch_set_unit(double* x, int64_t N, int64_t idx, hipStream_t st);
 // Block sigma staging: out[i*nv + v] = src row v (v < cnt), zero for cnt <= v < nv;
-// dst row v = y[., v] (+ shift * x row v when x is given).
+// dst row v = y[., v] (+ shift * x row v when x is given).  With d_row (device
+// int), src, x and dst are offset by that many rows, read when the kernel runs.
 template <class T>
-hipError_t launch_interleave(const double* src, int cnt, int nv, int64_t N, T* out, hipStream_t st);
+hipError_t launch_interleave(const double* src, const int* d_row, int cnt, int nv, int64_t N, T* out,
+                             hipStream_t st);
 template <class T>
 hipError_t launch_deinterleave(const T* y, int cnt, int nv, int64_t N, const double* x, double shift,
-                               double* dst, hipStream_t st);
+                               double* dst, const int* d_row, hipStream_t st);
+// *d_p = v (a one-thread kernel: usable where memset and memcpy nodes are not wanted)
+hipError_t launch_set_int(int* d_p, int v, hipStream_t st);
 // *d_val = max_i v[i]; d_part holds kRedBlocks partials
 hipError_t launch_max(const double* v, int64_t N, double* d_val, double* d_part, hipStream_t st);
 

@@ -96,19 +96,29 @@ __global__ void k_argmin_final(const double* pv, const int64_t* pi, int nblk, do
 }
 
 // out[i*nv + v] = src[v*N + i] for v < cnt (as T), 0 for cnt <= v < nv: the
-// interleaved layout of a block sigma, k values of one determinant contiguous
+// interleaved layout of a block sigma, k values of one determinant contiguous.
+// With d_row, src is offset by (*d_row) rows read on the device (graph replays).
 template <class T>
-__global__ void __launch_bounds__(kVB) k_interleave(const double* __restrict__ src, int cnt, int nv,
+__global__ void __launch_bounds__(kVB) k_interleave(const double* __restrict__ src,
+                                                    const int* __restrict__ d_row, int cnt, int nv,
                                                     int64_t N, T* __restrict__ out) {
+    if (d_row) src += (size_t)(*d_row) * N;
     for (int64_t i = (int64_t)blockIdx.x * kVB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kVB)
         for (int v = 0; v < nv; ++v) out[i * nv + v] = v < cnt ? (T)src[(size_t)v * N + i] : (T)0;
 }
 
-// dst[v*N + i] = y[i*nv + v] (+ shift * x[v*N + i] when x is given), v < cnt
+// dst[v*N + i] = y[i*nv + v] (+ shift * x[v*N + i] when x is given), v < cnt;
+// with d_row, x and dst are offset by (*d_row) rows read on the device
 template <class T>
 __global__ void __launch_bounds__(kVB) k_deinterleave(const T* __restrict__ y, int cnt, int nv,
                                                       int64_t N, const double* __restrict__ x,
-                                                      double shift, double* __restrict__ dst) {
+                                                      double shift, double* __restrict__ dst,
+                                                      const int* __restrict__ d_row) {
+    if (d_row) {
+        const size_t off = (size_t)(*d_row) * N;
+        if (x) x += off;
+        dst += off;
+    }
     for (int64_t i = (int64_t)blockIdx.x * kVB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kVB)
         for (int v = 0; v < cnt; ++v) {
             const double a = (double)y[i * nv + v];
@@ -197,24 +207,37 @@ hipError_t launch_argmin_after(const double* v, int64_t N, double vprev, int64_t
 }
 
 template <class T>
-hipError_t launch_interleave(const double* src, int cnt, int nv, int64_t N, T* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_interleave<T>, dim3(red_blocks(N)), dim3(kVB), 0, st, src, cnt, nv, N, out);
+hipError_t launch_interleave(const double* src, const int* d_row, int cnt, int nv, int64_t N, T* out,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_interleave<T>, dim3(red_blocks(N)), dim3(kVB), 0, st, src, d_row, cnt, nv,
+                       N, out);
     return hipGetLastError();
 }
-template hipError_t launch_interleave<double>(const double*, int, int, int64_t, double*, hipStream_t);
-template hipError_t launch_interleave<float>(const double*, int, int, int64_t, float*, hipStream_t);
+template hipError_t launch_interleave<double>(const double*, const int*, int, int, int64_t, double*,
+                                              hipStream_t);
+template hipError_t launch_interleave<float>(const double*, const int*, int, int, int64_t, float*,
+                                             hipStream_t);
 
 template <class T>
 hipError_t launch_deinterleave(const T* y, int cnt, int nv, int64_t N, const double* x, double shift,
-                               double* dst, hipStream_t st) {
+                               double* dst, const int* d_row, hipStream_t st) {
     hipLaunchKernelGGL(k_deinterleave<T>, dim3(red_blocks(N)), dim3(kVB), 0, st, y, cnt, nv, N, x,
-                       shift, dst);
+                       shift, dst, d_row);
     return hipGetLastError();
 }
 template hipError_t launch_deinterleave<double>(const double*, int, int, int64_t, const double*, double,
-                                                double*, hipStream_t);
+                                                double*, const int*, hipStream_t);
 template hipError_t launch_deinterleave<float>(const float*, int, int, int64_t, const double*, double,
-                                               double*, hipStream_t);
+                                               double*, const int*, hipStream_t);
+
+__global__ void k_set_int(int* p, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+hipError_t launch_set_int(int* d_p, int v, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, d_p, v);
+    return hipGetLastError();
+}
 
 hipError_t launch_max(const double* v, int64_t N, double* d_val, double* d_part, hipStream_t st) {
     unsigned nb = red_blocks(N);

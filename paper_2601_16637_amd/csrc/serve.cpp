@@ -193,7 +193,7 @@ extern "C" int sbd_serve_estimate(const sbd_request* q, size_t* bytes) {
     const bool mixed = o.sigma_prec == SBD_FP32;
     const double nvmax = k < 2 ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));  // block sigma width
     double total = 2 * ms * N * 8 + std::max<double>(k, keep) * N * 8 + keep * N * 8 +
-                   2 * N * nvmax * 8 + (nvmax > 1 ? 2 * nvmax * N * 8 : 0.0) +
+                   2 * N * nvmax * 8 + ((nvmax > 1 || o.use_graph) ? 2 * nvmax * N * 8 : 0.0) +
                    (mixed ? 2 * std::max(ms, nvmax) * N * 4 : 0.0) + 8.0 * kPassRows * kRedBlocks +
                    65536.0;
     // Hamiltonian: integrals, diagonal, spectator tables and per-string diagonal parts
