@@ -400,6 +400,34 @@ def test_davidson_full_sel26_chosen_form_residual_by_oracle():
     assert e[0] <= S.diag().min()
 
 
+def test_davidson_full_block20_chosen_form_residual_by_oracle():
+    """The block workload at full size (N = 2.5e7, 4 roots solved together with
+    interleaved block sigma, FP32 sigma with FP64 refinement, autotuned, sigma
+    sequences replayed from HIP graphs): for every root the oracle's FP64 sigma
+    on sampled components leaves a residual within the tolerance, the roots are
+    orthonormal, and the energies are ascending and below the lowest diagonal."""
+    W = wl.make_config("block20")
+    _, _, ham = from_workload(W)
+    k = 4
+    vec = torch.empty(k * W.ndet, device=DEV, dtype=torch.float64)
+    e, rep, st = sbd.davidson(ham, k, vectors=vec, tol_residual=1e-6, sigma_prec=sbd.FP32,
+                              max_space=24, use_autotune=1, use_graph=1)
+    assert st == 0 and rep["converged"] and rep["sigma_calls_fp64"] < rep["sigma_calls"]
+    U = vec.cpu().numpy().reshape(k, W.ndet)
+    del vec
+    G = U @ U.T
+    assert np.abs(G - np.eye(k)).max() <= 1e-10
+    assert np.all(np.diff(e[:k]) >= 0)
+    S = oracle.OracleSystem.from_workload(W)
+    assert e[0] <= S.diag().min()
+    rng = np.random.default_rng(43)
+    for r in range(k):
+        idx = np.unique(np.concatenate([np.argsort(-np.abs(U[r]))[:200],
+                                        rng.integers(0, W.ndet, 200)]))
+        res = S.sigma_at(U[r], idx) - e[r] * U[r][idx]
+        assert np.linalg.norm(res) <= 1e-6
+
+
 def test_davidson_single_determinant():
     norb = 6
     A = np.array([0b000111], dtype=np.uint64)
