@@ -250,6 +250,38 @@ def traffic_summary(fetch_csv, write_csv, kernel_json, workload):
     return "\n".join(lines)
 
 
+def block_leg(sbd, wl, stream):
+    """Block workload (block20: 4 roots): chosen form = FP32 sigma with FP64
+    refinement, interleaved block sigma, sigma sequences replayed from HIP
+    graphs; plain = FP64 sigma one vector at a time.  Each form is solved once
+    untimed (autotuning, graph capture) and once timed, from scratch."""
+    W = wl.make_config("block20")
+
+    def solve(prec, block, graph):
+        B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
+        X = sbd.Excitations(B, stream=stream)
+        H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
+        e, rep, st = sbd.davidson(H, W.nroots, stream=stream, tol_residual=1e-6, sigma_prec=prec,
+                                  max_space=20, use_autotune=1, use_graph=graph, block_sigma=block)
+        return e, rep
+
+    out = {}
+    for name, prec, block, graph in (("chosen", sbd.FP32, 1, 1), ("plain_fp64", sbd.FP64, 0, 0)):
+        solve(prec, block, graph)
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e, rep = solve(prec, block, graph)
+        torch.cuda.synchronize()
+        out[name] = dict(ms_solve=1e3 * (time.perf_counter() - t0), iterations=rep["iterations"],
+                         sigma_calls=rep["sigma_calls"], sigma_calls_fp64=rep["sigma_calls_fp64"],
+                         energies=[float(v) for v in e[:W.nroots]])
+    out["energy_max_diff"] = float(max(abs(a - b) for a, b in zip(out["chosen"]["energies"],
+                                                               out["plain_fp64"]["energies"])))
+    out.update(workload="block20", determinants=W.ndet, nroots=W.nroots, tol_residual=1e-6)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +291,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-block", action="store_true")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a few sigma launches and a calibration copy (counter runs)")
     ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
@@ -381,6 +414,9 @@ def main():
     log(f"[bench] sigma fp32 {1e3*t_sig32:.3f} ms ({stages32}), fp64 {1e3*t_sig64:.3f} ms; "
         f"stream {achieved/1e12:.2f} TFLOP/s")
 
+    if not args.no_block:
+        extra["block"] = block_leg(sbd, wl, stream)
+        log(f"[bench] block: {extra['block']}")
     if not args.no_serving:
         extra["serving"] = serving(sbd, wl)
         log(f"[bench] serving: {extra['serving']}")

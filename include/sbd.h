@@ -212,6 +212,8 @@ typedef struct {
     const double* guess;   /* optional device pointer, n_guess x N initial vectors (NULL = none)   */
     int n_guess;
     int verbose;           /* 1: print one line per iteration to stderr                            */
+    int block_sigma;       /* 1 (default): the new vectors of an iteration share one interleaved
+                              sigma (several roots); 0: one sigma launch sequence per vector      */
 } sbd_davidson_opts;
 
 typedef struct {

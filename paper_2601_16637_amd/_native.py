@@ -43,7 +43,8 @@ class DavidsonOpts(ctypes.Structure):
                 ("max_space", ctypes.c_int), ("precond_delta", ctypes.c_double),
                 ("sigma_prec", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("use_autotune", ctypes.c_int), ("guess", ctypes.c_void_p),
-                ("n_guess", ctypes.c_int), ("verbose", ctypes.c_int)]
+                ("n_guess", ctypes.c_int), ("verbose", ctypes.c_int),
+                ("block_sigma", ctypes.c_int)]
 
 
 class DavidsonReport(ctypes.Structure):

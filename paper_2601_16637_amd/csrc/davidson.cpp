@@ -406,6 +406,7 @@ extern "C" void sbd_davidson_default_opts(sbd_davidson_opts* o) {
     o->guess = nullptr;
     o->n_guess = 0;
     o->verbose = 0;
+    o->block_sigma = 1;
 }
 
 extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham* H, int nroots,
@@ -430,10 +431,14 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     ms = std::min(ms, 48);
     hipStream_t st = (hipStream_t)stream;
     if (o.use_autotune) {
-        // launch configuration only: sigma values do not depend on it beyond rounding order
-        int rc = sbd_autotune(b, x, const_cast<sbd_ham*>(H), SBD_FP64, 1, 0, stream, nullptr);
+        // launch configuration only: sigma values do not depend on it beyond rounding
+        // order.  Tuned for the sigma shape the solve issues most: k interleaved
+        // vectors for a block solve, single vectors otherwise.
+        const int nvt = (k < 2 || !o.block_sigma) ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));
+        const int lay = nvt > 1 ? 1 : 0;
+        int rc = sbd_autotune(b, x, const_cast<sbd_ham*>(H), SBD_FP64, nvt, lay, stream, nullptr);
         if (!rc && o.sigma_prec == SBD_FP32)
-            rc = sbd_autotune(b, x, const_cast<sbd_ham*>(H), SBD_FP32, 1, 0, stream, nullptr);
+            rc = sbd_autotune(b, x, const_cast<sbd_ham*>(H), SBD_FP32, nvt, lay, stream, nullptr);
         if (rc) return rc;
     }
 
@@ -456,7 +461,7 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     S.keep = std::max(k, std::min(2 * k, ms - k));
     S.mixed = (o.sigma_prec == SBD_FP32);
     // block solves gather all new vectors of an iteration in one interleaved sigma
-    S.nvmax = k < 2 ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));
+    S.nvmax = (k < 2 || !o.block_sigma) ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));
     S.use_graph = o.use_graph != 0;
     int rc = S.alloc();
     if (rc) return rc;

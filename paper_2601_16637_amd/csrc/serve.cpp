@@ -191,7 +191,7 @@ extern "C" int sbd_serve_estimate(const sbd_request* q, size_t* bytes) {
     ms = std::min(ms, N);
     const double keep = std::max<double>(k, std::min<double>(2 * k, ms - k));
     const bool mixed = o.sigma_prec == SBD_FP32;
-    const double nvmax = k < 2 ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));  // block sigma width
+    const double nvmax = (k < 2 || !o.block_sigma) ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));  // block width
     double total = 2 * ms * N * 8 + std::max<double>(k, keep) * N * 8 + keep * N * 8 +
                    2 * N * nvmax * 8 + ((nvmax > 1 || o.use_graph) ? 2 * nvmax * N * 8 : 0.0) +
                    (mixed ? 2 * std::max(ms, nvmax) * N * 4 : 0.0) + 8.0 * kPassRows * kRedBlocks +
