@@ -406,6 +406,9 @@ def main():
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
                     unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU,
                     traffic=None if traffic is None else traffic,
+                    # the measured bytes at the measured launch time, against the HBM peak
+                    traffic_rate_TBps=None if traffic is None else traffic / (t_stream / 2) / 1e12,
+                    traffic_frac_of_hbm_peak=None if traffic is None else traffic / (t_stream / 2) / PEAK_HBM,
                     kernel=f"{kname} (alpha and beta launches of one FP32 sigma)",
                     launch_ms=1e3 * t_stream / 2, algorithmic_flops_per_launch=(f_alpha + f_beta) / 2,
                     sigma_fp32_stage_ms=stages32, sigma_fp64_stage_ms=stages64,

@@ -151,10 +151,11 @@ static std::vector<int32_t> sell_positions(const std::vector<int64_t>& rp, int W
         std::stable_sort(win.begin(), win.end(), [&](int32_t a, int32_t b) {
             return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
         });
-        const int64_t S = (w1 - w0) / 64;  // whole slices (a short last window is not rotated)
-        const int64_t r = (S > 1 && (w1 - w0) % 64 == 0) ? (q * (W / 128 - 1)) % S : 0;
+        // whole slices rotate; a last window's partial slice keeps its place at the end
+        const int64_t S = (w1 - w0) / 64;
+        const int64_t r = S > 1 ? (q * (W / 128 - 1)) % S : 0;
         for (int64_t j = 0; j < w1 - w0; ++j) {
-            const int64_t sl = j / 64, dst = r ? ((sl + r) % S) * 64 + j % 64 : j;
+            const int64_t sl = j / 64, dst = (r && sl < S) ? ((sl + r) % S) * 64 + j % 64 : j;
             pos[(size_t)(w0 + dst)] = win[(size_t)j];
         }
     }
