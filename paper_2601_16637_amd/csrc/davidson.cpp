@@ -572,16 +572,22 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
             ebnd[r] = std::sqrt(s2);
             certified = certified && ebnd[r] == 0.0;
         }
-        // fused residual / preconditioner for all roots with the first projections V^T t_q
-        std::vector<double> red(2 * k + (size_t)m * k);
+        // fused residual / preconditioner for all roots with the first projections
+        // V^T t_q, and W^T t_q when they fit the same sweep
+        const bool with_w = pass_resid_w_fits(m, k);
+        std::vector<double> red(2 * k + (size_t)(with_w ? 2 : 1) * m * k);
         {
             std::vector<double> Y((size_t)m * k);
             for (int j = 0; j < m; ++j)
                 for (int q = 0; q < k; ++q) Y[j * k + q] = Z[j * m + q];
             SBD_HIP(hipMemcpyAsync(sm + kY, Y.data(), sizeof(double) * m * k, hipMemcpyHostToDevice, st));
             SBD_HIP(hipMemcpyAsync(sm + kTheta, theta.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
-            SBD_HIP(pass_resid(S.V.as<double>(), S.W.as<double>(), m, k, sm + kY, sm + kTheta, diag,
-                               o.precond_delta, tmp, N, true, part, sm + kRed, st));
+            if (with_w)
+                SBD_HIP(pass_resid_w(S.V.as<double>(), S.W.as<double>(), m, k, sm + kY, sm + kTheta, diag,
+                                     o.precond_delta, tmp, N, part, sm + kRed, st));
+            else
+                SBD_HIP(pass_resid(S.V.as<double>(), S.W.as<double>(), m, k, sm + kY, sm + kTheta, diag,
+                                   o.precond_delta, tmp, N, true, part, sm + kRed, st));
             SBD_HIP(hipMemcpyAsync(red.data(), sm + kRed, sizeof(double) * red.size(), hipMemcpyDeviceToHost, st));
             SBD_HIP(hipStreamSynchronize(st));
             for (int q = 0; q < k; ++q) {
@@ -698,8 +704,29 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
             if (h1_valid && m == m_old) {
                 // projection of root r from the residual pass: rows [2k + j*k + r)
                 std::vector<double> h1(m);
-                for (int j = 0; j < m; ++j) h1[j] = red[2 * k + j * k + r];
+                double hh = 0.0;
+                for (int j = 0; j < m; ++j) {
+                    h1[j] = red[2 * k + j * k + r];
+                    hh += h1[j] * h1[j];
+                }
                 SBD_HIP(hipMemcpyAsync(sm + kH1, h1.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+                // One Gram-Schmidt pass suffices when it keeps at least 1/sqrt(2) of
+                // the norm.  With V orthonormal, |t - V h|^2 = |t|^2 - |h|^2 is known
+                // before the pass, and W^T (t - V h) = W^T t - (V^T W)^T h follows from
+                // the residual sweep's sums and T, so the new vector takes a single
+                // subtract-and-scale sweep over V and t.
+                const double n0 = tnorm[r], n1sq = n0 * n0 - hh;
+                if (with_w && n0 > 0.0 && std::isfinite(n1sq) && n1sq >= kReorth * kReorth * n0 * n0) {
+                    const double inv = 1.0 / std::sqrt(n1sq);
+                    SBD_HIP(pass_subs(S.V.as<double>(), m, sm + kH1, t, inv, S.Vr(m), N, st));
+                    for (int j = 0; j < m; ++j) {
+                        double th = red[2 * k + (size_t)m * k + j * k + r];
+                        for (int i = 0; i < m; ++i) th -= h1[i] * T[i * ms + j];
+                        T[j * ms + m] = T[m * ms + j] = th * inv;
+                    }
+                    ++m;
+                    continue;
+                }
             } else {
                 rc = S.first_projection(t, m);
                 if (rc) return rc;
@@ -715,6 +742,7 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
             }
             ++m;
         }
+        SBD_HIP(hipStreamSynchronize(st));  // the update's passes end here, not inside the sigma timer
         t_update += ms_since(tu1);
         if (m == m_old) {
             status = SBD_NOT_CONVERGED;  // stagnation: no new direction

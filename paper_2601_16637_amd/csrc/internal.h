@@ -270,6 +270,15 @@ hipError_t launch_f32_to_f64_axpy(const float* y32, const double* x, double shif
 hipError_t pass_resid(const double* V, const double* W, int m, int k, const double* Y,
                       const double* theta, const double* diag, double delta, double* T, int64_t N,
                       bool proj, double* part, double* out, hipStream_t st);
+// the residual pass that also projects each t_q on W: rows as pass_resid with
+// proj, then [2k + m*k + j*k + q) W_j . t_q; available when pass_resid_w_fits(m, k)
+bool pass_resid_w_fits(int m, int k);
+hipError_t pass_resid_w(const double* V, const double* W, int m, int k, const double* Y,
+                        const double* theta, const double* diag, double delta, double* T, int64_t N,
+                        double* part, double* out, hipStream_t st);
+// dst <- (t - V h) * s; no sums (dst must not alias V)
+hipError_t pass_subs(const double* V, int m, const double* h, const double* t, double s, double* dst,
+                     int64_t N, hipStream_t st);
 // t <- t - V h;  rows [0] |t|^2, [1 + j) V_j . t
 hipError_t pass_sub1(const double* V, int m, const double* h, double* t, int64_t N, double* part,
                      double* out, hipStream_t st);

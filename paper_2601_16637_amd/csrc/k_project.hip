@@ -21,7 +21,10 @@
 //   [0, NR)              norms (mode dependent, see below)
 //   [NR + j*k + q)       G[j][q] = P_j . out_q   for j < mp, q < k
 // When a projection does not fit the register budget of a pass, the pass runs
-// without it and a separate projection pass fills the same rows.
+// without it and a separate projection pass fills the same rows.  RESIDW is
+// RESID that also projects every correction on W (rows [2k + m*k + j*k + q)),
+// so that a Gram-Schmidt step that needs one pass can take the new column of
+// V^T W from these sums; SUBS is the subtraction (t - V h) * s with no sums.
 #include <algorithm>
 
 #include "internal.h"
@@ -32,7 +35,7 @@ namespace {
 constexpr int kTB = 256;       // threads per block
 constexpr int kMaxOut = 8;     // output vectors per pass
 
-enum Mode { RESID = 0, SUB1 = 1, SUB2 = 2, PROJ = 3, SUBW = 4 };
+enum Mode { RESID = 0, SUB1 = 1, SUB2 = 2, PROJ = 3, SUBW = 4, RESIDW = 5, SUBS = 6 };
 
 struct PassArgs {
     int64_t N;
@@ -49,6 +52,7 @@ struct PassArgs {
     const double* theta;  // RESID: k Ritz values
     const double* diag;
     double delta;
+    double scale;     // SUBS: factor applied to t - V h
     double* part;
 };
 
@@ -71,9 +75,13 @@ constexpr int ept_for(int mb) { return mb <= 8 ? 2 : 1; }
 template <int MODE, int MB, int KO, bool PRJ>
 __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
     constexpr int EPT = ept_for(MB);
-    constexpr int NAJ = PRJ ? (MODE == SUBW ? 2 * MB : MB) : 1;  // accumulator rows
-    constexpr int NAQ = (MODE == RESID || MODE == PROJ) ? KO : 1;
-    __shared__ double red[4][MODE == SUBW ? 1 + 2 * MB : 2 * kMaxOut + MB * KO];
+    constexpr bool RES = MODE == RESID || MODE == RESIDW;
+    constexpr int NAJ = PRJ ? ((MODE == SUBW || MODE == RESIDW) ? 2 * MB : MB) : 1;  // accumulator rows
+    constexpr int NAQ = (RES || MODE == PROJ) ? KO : 1;
+    __shared__ double red[4][MODE == SUBW ? 1 + 2 * MB
+                             : MODE == SUBS ? 1
+                             : MODE == RESIDW ? 2 * kMaxOut + 2 * MB * KO
+                                              : 2 * kMaxOut + MB * KO];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = A.m, k = A.k, mp = A.mp;
     const int64_t N = A.N;
@@ -89,7 +97,7 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
     for (int q = 0; q < 2 * KO; ++q) nrm[q] = 0.0;
     double th[KO];
 #pragma unroll
-    for (int q = 0; q < KO; ++q) th[q] = (MODE == RESID && q < k) ? A.theta[q] : 0.0;
+    for (int q = 0; q < KO; ++q) th[q] = (RES && q < k) ? A.theta[q] : 0.0;
 
     const int64_t step = (int64_t)gridDim.x * kTB * EPT;
     for (int64_t base = (int64_t)blockIdx.x * kTB * EPT + tid; base < N; base += step) {
@@ -100,7 +108,7 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
             ix[u] = base + (int64_t)u * kTB;
             in[u] = ix[u] < N;
         }
-        if constexpr (MODE == RESID) {
+        if constexpr (RES) {
             double v[MB][EPT], w[MB][EPT], d[EPT];
 #pragma unroll
             for (int j = 0; j < MB; ++j)
@@ -135,8 +143,31 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
                         for (int j = 0; j < MB; ++j)
                             if (j < mp) acc[j][q] += v[j][u] * t;
                     }
+                    if constexpr (MODE == RESIDW) {
+#pragma unroll
+                        for (int j = 0; j < MB; ++j)
+                            if (j < mp) acc[MB + j][q] += w[j][u] * t;
+                    }
                 }
                 }
+            }
+        } else if constexpr (MODE == SUBS) {
+            double v[MB][EPT], x[EPT];
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) x[u] = in[u] ? A.X[ix[u]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+                if (j < m) {
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) v[j][u] = in[u] ? A.V[(size_t)j * N + ix[u]] : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                double sv = 0.0;
+#pragma unroll
+                for (int j = 0; j < MB; ++j)
+                    if (j < m) sv += v[j][u] * cf[j];
+                if (in[u]) A.out[ix[u]] = (x[u] - sv) * A.scale;
             }
         } else if constexpr (MODE == SUB1 || MODE == SUB2) {
             double v[MB][EPT], x[EPT];
@@ -234,15 +265,16 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
     }
 
     // ---- block reduction: wavefront shuffles, then the four wavefronts in order
-    const int NR = (MODE == RESID) ? 2 * k : ((MODE == PROJ) ? 0 : 1);
-    const int kq = (MODE == RESID || MODE == PROJ) ? k : 1;
+    if constexpr (MODE == SUBS) return;  // no sums
+    const int NR = RES ? 2 * k : ((MODE == PROJ) ? 0 : 1);
+    const int kq = (RES || MODE == PROJ) ? k : 1;
 #pragma unroll
     for (int q = 0; q < 2 * KO; ++q) {
         const double x = wave_sum(nrm[q]);
         if (lane == 0) {
             // RESID: [0,k) |r_q|^2, [k,2k) |t_q|^2;  SUB: [0] |t|^2
-            if (MODE == RESID && q < KO && q < k) red[wv][q] = x;
-            if (MODE == RESID && q >= KO && q - KO < k) red[wv][k + q - KO] = x;
+            if (RES && q < KO && q < k) red[wv][q] = x;
+            if (RES && q >= KO && q - KO < k) red[wv][k + q - KO] = x;
             if ((MODE == SUB1 || MODE == SUB2 || MODE == SUBW) && q == 0) red[wv][0] = x;
         }
     }
@@ -261,11 +293,14 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
 #pragma unroll
             for (int q = 0; q < NAQ; ++q) {
                 const double x = wave_sum(acc[j][q]);
-                if (lane == 0 && j < mp && q < kq) red[wv][NR + j * kq + q] = x;
+                // RESIDW: W rows follow the mp*k V rows
+                const int jj = j < MB ? j : j - MB, off = j < MB ? 0 : mp * kq;
+                if (lane == 0 && jj < mp && q < kq) red[wv][NR + off + jj * kq + q] = x;
             }
     }
     __syncthreads();
-    const int rows = (MODE == SUBW) ? 1 + m + A.mw : NR + (PRJ ? mp * kq : 0);
+    const int rows = (MODE == SUBW) ? 1 + m + A.mw
+                                    : NR + (PRJ ? (MODE == RESIDW ? 2 : 1) * mp * kq : 0);
     for (int r = tid; r < rows; r += kTB)
         A.part[(size_t)r * gridDim.x + blockIdx.x] = ((red[0][r] + red[1][r]) + red[2][r]) + red[3][r];
 }
@@ -301,6 +336,8 @@ int ko_for(int k) { return k <= 1 ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : (k <= 8 ? 8 
 constexpr int held(int mode, int mb, int ko, bool prj) {
     return ept_for(mb) *
            ((mode == RESID)  ? 2 * mb + (prj ? mb * ko : 0)
+            : (mode == RESIDW) ? 2 * mb + 2 * mb * ko
+            : (mode == SUBS)   ? mb + 1
             : (mode == SUB1) ? mb + (prj ? mb : 0)
             : (mode == SUB2) ? mb + (prj ? 2 * mb : 0)
             : (mode == SUBW) ? 4 * mb
@@ -311,6 +348,8 @@ constexpr int held(int mode, int mb, int ko, bool prj) {
 // residual forms where the PRJ form of the same size does not fit.
 constexpr bool exists(int mode, int mb, int ko, bool prj) {
     return mode == SUBW                                 ? ko == 1 && prj && held(mode, mb, 1, true) <= kRegBudget
+           : mode == RESIDW                          ? prj && held(mode, mb, ko, true) <= kRegBudget
+           : mode == SUBS                            ? ko == 1 && !prj
            : (mode == SUB1 || mode == SUB2) && ko != 1 ? false
            : prj                                    ? held(mode, mb, ko, true) <= kRegBudget
            : mode == PROJ                           ? false
@@ -372,7 +411,8 @@ hipError_t by_ko(int ko, int mb, const PassArgs& A, unsigned* nb, hipStream_t st
 bool fits(int mode, int rows, int k, bool prj) {
     const int mb = mb_for(rows), ko = ko_for(k);
     return mb > 0 && ko > 0 &&
-           held(mode, mb, (mode == SUB1 || mode == SUB2 || mode == SUBW) ? 1 : ko, prj) <= kRegBudget;
+           held(mode, mb, (mode == SUB1 || mode == SUB2 || mode == SUBW || mode == SUBS) ? 1 : ko, prj) <=
+               kRegBudget;
 }
 
 // One pass; `rows` results reduced into out.  The caller checked fits().
@@ -380,12 +420,14 @@ hipError_t run_pass(int mode, const PassArgs& A, int rows, double* out, hipStrea
     const bool prj = A.mp > 0;
     const int need = std::max({mode == PROJ ? 0 : A.m, A.mp, mode == SUBW ? A.mw : 0});
     const int mb = mb_for(need < 1 ? 1 : need);
-    const int ko = (mode == RESID || mode == PROJ) ? ko_for(A.k) : 1;
+    const int ko = (mode == RESID || mode == RESIDW || mode == PROJ) ? ko_for(A.k) : 1;
     if (mb < 0 || ko < 0 || rows > kPassRows) return hipErrorInvalidValue;
     if (mode == SUBW && !fits(SUBW, need, 1, true)) return hipErrorInvalidValue;
     unsigned nb = 0;
     hipError_t e = hipErrorInvalidValue;
     if (mode == RESID) e = prj ? by_ko<RESID, true>(ko, mb, A, &nb, st) : by_ko<RESID, false>(ko, mb, A, &nb, st);
+    else if (mode == RESIDW) e = by_ko<RESIDW, true>(ko, mb, A, &nb, st);
+    else if (mode == SUBS) e = by_mb<SUBS, 1, false>(mb, A, &nb, st);
     else if (mode == SUB1) e = prj ? by_mb<SUB1, 1, true>(mb, A, &nb, st) : by_mb<SUB1, 1, false>(mb, A, &nb, st);
     else if (mode == SUB2) e = prj ? by_mb<SUB2, 1, true>(mb, A, &nb, st) : by_mb<SUB2, 1, false>(mb, A, &nb, st);
     else if (mode == SUBW) e = by_mb<SUBW, 1, true>(mb, A, &nb, st);
@@ -431,6 +473,28 @@ hipError_t pass_resid(const double* V, const double* W, int m, int k, const doub
     hipError_t e = run_pass(RESID, A, 2 * k + (proj ? A.mp * k : 0), out, st);
     if (e == hipSuccess && proj && !fused) e = pass_project(V, m, T, k, N, part, out + 2 * k, st);
     return e;
+}
+
+bool pass_resid_w_fits(int m, int k) { return m >= 1 && k >= 1 && k <= kMaxOut && fits(RESIDW, m, k, true); }
+
+hipError_t pass_resid_w(const double* V, const double* W, int m, int k, const double* Y,
+                        const double* theta, const double* diag, double delta, double* T, int64_t N,
+                        double* part, double* out, hipStream_t st) {
+    if (!pass_resid_w_fits(m, k)) return hipErrorInvalidValue;
+    PassArgs A{};
+    A.N = N; A.m = m; A.k = k; A.mp = m;
+    A.V = V; A.W = W; A.P = V; A.out = T; A.coef = Y; A.theta = theta; A.diag = diag;
+    A.delta = delta; A.part = part;
+    return run_pass(RESIDW, A, 2 * k + 2 * m * k, out, st);
+}
+
+hipError_t pass_subs(const double* V, int m, const double* h, const double* t, double s, double* dst,
+                     int64_t N, hipStream_t st) {
+    if (m < 1 || m > 48 || !fits(SUBS, m, 1, false)) return hipErrorInvalidValue;
+    PassArgs A{};
+    A.N = N; A.m = m; A.k = 1; A.mp = 0;
+    A.V = V; A.X = t; A.out = dst; A.coef = h; A.scale = s;
+    return run_pass(SUBS, A, 0, nullptr, st);
 }
 
 hipError_t pass_sub1(const double* V, int m, const double* h, double* t, int64_t N, double* part,
