@@ -88,8 +88,12 @@ def sigma_stages(sbd, H, N, prec, stream, reps=10):
 
 def stream_kernel_name(tune):
     """Instantiation of the FP32 single-vector row stream that a tune selects
-    (columns per lane: 2, or 4 with 16-byte loads; output rows per wavefront)."""
-    return f"k_stream<float,1,{4 if tune['stream_wide'] else 2},{tune['stream_rw']}>"
+    (columns per lane: 2, or 4 with 16-byte loads; output rows per wavefront,
+    or ket entries per load step in the ket-split form)."""
+    vec = 4 if tune['stream_wide'] else 2
+    if tune.get('stream_split', 1) > 1:
+        return f"k_stream_ks<float,1,{vec},{tune['stream_split']}>"
+    return f"k_stream<float,1,{vec},{tune['stream_rw']}>"
 
 
 def kernel_only(sbd, W, stream):

@@ -169,10 +169,14 @@ int sbd_autotune(const sbd_basis* b, const sbd_exc* e, sbd_ham* h, int prec, int
  * (stream_rw in {1, 2}: output rows per wavefront of the stream kernel;
  * ab_lds_bytes in [4096, 1 MiB], capped at the device's LDS per workgroup;
  * stream_wide in {0, 1}: 16-byte instead of 8-byte lane loads in the row
- * streams where the vector width and row alignment allow).  Any output
- * pointer of sbd_get_tune may be NULL. */
-int sbd_get_tune(const sbd_ham* h, int prec, int* stream_rw, int* ab_lds_bytes, int* stream_wide);
-int sbd_set_tune(sbd_ham* h, int prec, int stream_rw, int ab_lds_bytes, int stream_wide);
+ * streams where the vector width and row alignment allow; stream_split in
+ * {1, 2, 4}: ket entries a stream wavefront loads per step, each by 64/split
+ * lanes, which narrows the column tile by that factor (needs stream_rw = 1)).
+ * Any output pointer of sbd_get_tune may be NULL.  Errors: SBD_ERR_ARG. */
+int sbd_get_tune(const sbd_ham* h, int prec, int* stream_rw, int* ab_lds_bytes, int* stream_wide,
+                 int* stream_split);
+int sbd_set_tune(sbd_ham* h, int prec, int stream_rw, int ab_lds_bytes, int stream_wide,
+                 int stream_split);
 
 /*
  * sbd_sigma with HIP events recorded on `stream` around its five launches;

@@ -130,8 +130,9 @@ def load():
     L.sbd_sigma.argtypes = [P, P, P, i32, i32, d, P, P, i32, P]
     L.sbd_sigma_timed.argtypes = [P, P, P, i32, i32, d, P, P, i32, P, P]
     L.sbd_autotune.argtypes = [P, P, P, i32, i32, i32, P, ctypes.POINTER(d)]
-    L.sbd_get_tune.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
-    L.sbd_set_tune.argtypes = [P, i32, i32, i32, i32]
+    L.sbd_get_tune.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                               ctypes.POINTER(i32)]
+    L.sbd_set_tune.argtypes = [P, i32, i32, i32, i32, i32]
     L.sbd_gram.argtypes = [P, i32, P, i32, i64, P, P]
     L.sbd_davidson_default_opts.argtypes = [ctypes.POINTER(DavidsonOpts)]
     L.sbd_davidson_default_opts.restype = None
@@ -271,15 +272,16 @@ class Hamiltonian:
         return ms.value
 
     def get_tune(self, prec: int = FP64):
-        rw, lds, wide = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        rw, lds, wide, split = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         check(load().sbd_get_tune(self._h, int(prec), ctypes.byref(rw), ctypes.byref(lds),
-                                  ctypes.byref(wide)))
-        return dict(stream_rw=rw.value, ab_lds_bytes=lds.value, stream_wide=wide.value)
+                                  ctypes.byref(wide), ctypes.byref(split)))
+        return dict(stream_rw=rw.value, ab_lds_bytes=lds.value, stream_wide=wide.value,
+                    stream_split=split.value)
 
     def set_tune(self, prec: int = FP64, stream_rw: int = 1, ab_lds_bytes: int = 98304,
-                 stream_wide: int = 0):
+                 stream_wide: int = 0, stream_split: int = 1):
         check(load().sbd_set_tune(self._h, int(prec), int(stream_rw), int(ab_lds_bytes),
-                                  int(stream_wide)))
+                                  int(stream_wide), int(stream_split)))
 
     def diag_into(self, out, stream=None):
         check(load().sbd_ham_diag(self._h, _dptr(out), _stream(stream)))

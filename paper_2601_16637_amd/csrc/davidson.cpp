@@ -128,6 +128,7 @@ constexpr int kMisc = 3072;   // argmin value
 constexpr int kOne = 3080;    // the constant 1.0 (Gram-Schmidt coefficient of a difference)
 constexpr int kDiff = 3096;   // |sigma32 - sigma64|^2 rows of a refresh (2 per vector, <= 16 vectors)
 constexpr int kW1 = 3200;     // fused first Gram-Schmidt pass: |t'|^2, V^T t', W^T t' (<= 1 + 48 + 48)
+constexpr int kDot = 3400;    // v . w of a vector restored from an FP32 sigma
 // A second classical pass runs only when the first removed more than this
 // fraction of the norm: ||t'|| < ||t|| / sqrt(2) (Daniel-Gragg-Kaufman-Stewart)
 constexpr double kReorth = 0.70710678118654752;
@@ -164,6 +165,8 @@ struct Solver {
     std::map<std::tuple<int, int, bool>, hipGraphExec_t> graphs;
     std::map<std::tuple<int, int, bool>, int> seen;
     DevBuf rowsel;           // device int: basis row of the sigma being replayed
+    int staged_row = -1;     // basis row whose FP32 copy already sits in x32 (eager path)
+    int dot_row = -1;        // basis row whose v . w the last restore left at sm + kDot
 
     ~Solver() {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
@@ -206,10 +209,19 @@ struct Solver {
         hipError_t e = hipSuccess;
         if (nv == 1) {
             if (p64) return sigma_internal(x, H, c, SBD_FP64, 0.0, Vr(j), Wr(j), 0, sws.p, st);
-            e = launch_f64_to_f32(Vr(j), x32.as<float>(), (int64_t)c * N, st);
+            // the Gram-Schmidt sweep may have written the FP32 copy already
+            if (!(c == 1 && staged_row == j)) e = launch_f64_to_f32(Vr(j), x32.as<float>(), (int64_t)c * N, st);
+            staged_row = -1;
             if (e == hipSuccess) rc = sigma_internal(x, H, c, SBD_FP32, shift, x32.p, y32.p, 0, sws.p, st);
-            if (e == hipSuccess && !rc)
-                e = launch_f32_to_f64_axpy(y32.as<float>(), Vr(j), shift, Wr(j), (int64_t)c * N, st);
+            if (e == hipSuccess && !rc) {
+                if (c == 1) {  // restore with the diagonal entry v . w of T
+                    e = pass_restore(y32.as<float>(), Vr(j), shift, Wr(j), N, nullptr, part.as<double>(),
+                                     sm + kDot, st);
+                    dot_row = j;
+                } else {
+                    e = launch_f32_to_f64_axpy(y32.as<float>(), Vr(j), shift, Wr(j), (int64_t)c * N, st);
+                }
+            }
         } else if (p64) {
             e = launch_interleave<double>(Vr(j), nullptr, c, nv, N, x64.as<double>(), st);
             if (e == hipSuccess) rc = sigma_internal(x, H, nv, SBD_FP64, 0.0, x64.p, y64.p, 1, sws.p, st);
@@ -242,9 +254,14 @@ struct Solver {
         } else {
             e = launch_interleave<float>(V.as<double>(), dj, c, nv, N, x32.as<float>(), st);
             if (e == hipSuccess) rc = sigma_internal(x, H, nv, SBD_FP32, shift, x32.p, y32.p, layout, sws.p, st);
-            if (e == hipSuccess && !rc)
-                e = launch_deinterleave<float>(y32.as<float>(), c, nv, N, V.as<double>(), shift,
-                                               W.as<double>(), dj, st);
+            if (e == hipSuccess && !rc) {
+                if (c == 1 && nv == 1)  // the same restore, with v . w, as the eager path
+                    e = pass_restore(y32.as<float>(), V.as<double>(), shift, W.as<double>(), N, dj,
+                                     part.as<double>(), sm + kDot, st);
+                else
+                    e = launch_deinterleave<float>(y32.as<float>(), c, nv, N, V.as<double>(), shift,
+                                                   W.as<double>(), dj, st);
+            }
         }
         if (e != hipSuccess) return hip_fail(e, "sigma staging");
         return rc;
@@ -256,6 +273,7 @@ struct Solver {
     int sigma_group(int j, int c, int nv, bool p64) {
         if (!use_graph) return sigma_launches(j, c, nv, p64);
         SBD_HIP(launch_set_int(rowsel.as<int>(), j, st));
+        if (!p64 && c == 1 && nv == 1) dot_row = j;  // the sequence's restore leaves v . w
         const auto key = std::make_tuple(c, nv, p64);
         auto it = graphs.find(key);
         if (it == graphs.end()) {
@@ -282,6 +300,7 @@ struct Solver {
     // W[j0 .. j0+cnt) = H V[j0 .. j0+cnt)
     int apply_sigma(int j0, int cnt, bool fp64) {
         auto t0 = clk::now();
+        dot_row = -1;
         const bool p64 = !mixed || fp64;
         for (int d = 0; d < cnt;) {
             int c = std::min(cnt - d, 8);
@@ -291,6 +310,7 @@ struct Solver {
             if (rc) return rc;
             d += c;
         }
+        staged_row = -1;  // a pre-staged copy serves only the sigma that follows it
         if (p64) sigma64 += cnt;
         sigma_calls += cnt;
         hipError_t e = hipStreamSynchronize(st);
@@ -718,7 +738,11 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
                 const double n0 = tnorm[r], n1sq = n0 * n0 - hh;
                 if (with_w && n0 > 0.0 && std::isfinite(n1sq) && n1sq >= kReorth * kReorth * n0 * n0) {
                     const double inv = 1.0 / std::sqrt(n1sq);
-                    SBD_HIP(pass_subs(S.V.as<double>(), m, sm + kH1, t, inv, S.Vr(m), N, st));
+                    // the FP32 copy for the coming sigma, when that sigma takes this row alone
+                    const bool stage = S.mixed && !S.use_graph && S.block_width(nnew) == 1;
+                    SBD_HIP(pass_subs(S.V.as<double>(), m, sm + kH1, t, inv, S.Vr(m),
+                                      stage ? S.x32.as<float>() : nullptr, N, st));
+                    S.staged_row = stage ? m : -1;
                     for (int j = 0; j < m; ++j) {
                         double th = red[2 * k + (size_t)m * k + j * k + r];
                         for (int i = 0; i < m; ++i) th -= h1[i] * T[i * ms + j];
@@ -752,11 +776,18 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         if (rc) return rc;
         for (int j = m_old; j < m; ++j) ebound[j] = S.mixed ? rho : 0.0;
         auto tu2 = clk::now();
-        // T entries among the new vectors: V_new^T W_new (one pass)
+        // T entries among the new vectors: V_new^T W_new (one pass, or the
+        // restore's v . w for a single vector)
         {
             const int nn = m - m_old;
             std::vector<double> g;
-            rc = S.project(S.Vr(m_old), nn, S.Wr(m_old), nn, g);
+            if (nn == 1 && S.dot_row == m_old) {
+                g.assign(1, 0.0);
+                SBD_HIP(hipMemcpyAsync(g.data(), sm + kDot, sizeof(double), hipMemcpyDeviceToHost, st));
+                SBD_HIP(hipStreamSynchronize(st));
+            } else {
+                rc = S.project(S.Vr(m_old), nn, S.Wr(m_old), nn, g);
+            }
             if (rc) return rc;
             for (int i = 0; i < nn; ++i)
                 for (int j = 0; j < nn; ++j) T[(m_old + i) * ms + m_old + j] = g[i * nn + j];

@@ -125,6 +125,7 @@ struct SigmaTune {
     int stream_rows = 4;         // wavefronts per stream workgroup
     int stream_rw = 1;           // output rows per stream wavefront (1 or 2)
     int stream_wide = 0;         // 1: 16-byte lane loads in the row streams where possible
+    int stream_split = 1;        // ket entries per load step of a stream wavefront (1, 2, 4)
 };
 
 struct SpinCoef {
@@ -276,9 +277,14 @@ bool pass_resid_w_fits(int m, int k);
 hipError_t pass_resid_w(const double* V, const double* W, int m, int k, const double* Y,
                         const double* theta, const double* diag, double delta, double* T, int64_t N,
                         double* part, double* out, hipStream_t st);
-// dst <- (t - V h) * s; no sums (dst must not alias V)
+// dst <- (t - V h) * s, and dst32 <- (float)dst when dst32 is not null; no sums
+// (dst must not alias V)
 hipError_t pass_subs(const double* V, int m, const double* h, const double* t, double s, double* dst,
-                     int64_t N, hipStream_t st);
+                     float* dst32, int64_t N, hipStream_t st);
+// y <- (double)y32 + shift * x;  out[0] = x . y.  With row (device int) not
+// null, x and y are the bases of V and W and the row *row of each is used.
+hipError_t pass_restore(const float* y32, const double* x, double shift, double* y, int64_t N,
+                        const int* row, double* part, double* out, hipStream_t st);
 // t <- t - V h;  rows [0] |t|^2, [1 + j) V_j . t
 hipError_t pass_sub1(const double* V, int m, const double* h, double* t, int64_t N, double* part,
                      double* out, hipStream_t st);

@@ -53,6 +53,7 @@ struct PassArgs {
     const double* diag;
     double delta;
     double scale;     // SUBS: factor applied to t - V h
+    float* out32;     // SUBS: optional FP32 copy of the result
     double* part;
 };
 
@@ -167,7 +168,11 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
 #pragma unroll
                 for (int j = 0; j < MB; ++j)
                     if (j < m) sv += v[j][u] * cf[j];
-                if (in[u]) A.out[ix[u]] = (x[u] - sv) * A.scale;
+                if (in[u]) {
+                    const double o = (x[u] - sv) * A.scale;
+                    A.out[ix[u]] = o;
+                    if (A.out32) A.out32[ix[u]] = (float)o;
+                }
             }
         } else if constexpr (MODE == SUB1 || MODE == SUB2) {
             double v[MB][EPT], x[EPT];
@@ -318,6 +323,31 @@ __global__ void k_reduce(const double* __restrict__ part, int nblk, double* __re
         __syncthreads();
     }
     if (threadIdx.x == 0) out[r] = sh[0];
+}
+
+// y = (double)y32 + shift * x with the block partials of x . y in part[block]
+// (the FP32 sigma of a basis vector restored to FP64, and its diagonal entry
+// of V^T W, in one sweep)
+// (row: optional device index; x and y then point at row *row of V and W)
+__global__ void __launch_bounds__(kTB) k_restore(const float* __restrict__ y32, const double* __restrict__ xb,
+                                                 double shift, double* __restrict__ yb, int64_t N,
+                                                 const int* __restrict__ row, double* __restrict__ part) {
+    __shared__ double red[4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t off = row ? (int64_t)row[0] * N : 0;
+    const double* __restrict__ x = xb + off;
+    double* __restrict__ y = yb + off;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kTB + tid; i < N; i += (int64_t)gridDim.x * kTB) {
+        const double xv = x[i];
+        const double w = (double)y32[i] + shift * xv;
+        y[i] = w;
+        acc += xv * w;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    if (tid == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // Register budget (FP64 values held per thread, two VGPRs each): the row
@@ -475,6 +505,24 @@ hipError_t pass_resid(const double* V, const double* W, int m, int k, const doub
     return e;
 }
 
+hipError_t pass_restore(const float* y32, const double* x, double shift, double* y, int64_t N,
+                        const int* row, double* part, double* out, hipStream_t st) {
+    static const int slots = [] {
+        int dev = 0, cus = 0, nbk = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbk, k_restore, kTB, 0) != hipSuccess)
+            return 256;
+        return std::max(1, nbk) * std::max(1, cus);
+    }();
+    int64_t nb = (N + kTB - 1) / kTB;
+    nb = std::min<int64_t>(nb, std::min<int64_t>(slots, kRedBlocks));
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_restore, dim3((unsigned)nb), dim3(kTB), 0, st, y32, x, shift, y, N, row, part);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kTB), 0, st, part, (int)nb, out);
+    return hipGetLastError();
+}
+
 bool pass_resid_w_fits(int m, int k) { return m >= 1 && k >= 1 && k <= kMaxOut && fits(RESIDW, m, k, true); }
 
 hipError_t pass_resid_w(const double* V, const double* W, int m, int k, const double* Y,
@@ -489,11 +537,11 @@ hipError_t pass_resid_w(const double* V, const double* W, int m, int k, const do
 }
 
 hipError_t pass_subs(const double* V, int m, const double* h, const double* t, double s, double* dst,
-                     int64_t N, hipStream_t st) {
+                     float* dst32, int64_t N, hipStream_t st) {
     if (m < 1 || m > 48 || !fits(SUBS, m, 1, false)) return hipErrorInvalidValue;
     PassArgs A{};
     A.N = N; A.m = m; A.k = 1; A.mp = 0;
-    A.V = V; A.X = t; A.out = dst; A.coef = h; A.scale = s;
+    A.V = V; A.X = t; A.out = dst; A.out32 = dst32; A.coef = h; A.scale = s;
     return run_pass(SUBS, A, 0, nullptr, st);
 }
 

@@ -245,6 +245,117 @@ __global__ void __launch_bounds__(256) k_stream(StreamArgs<T> A, const T* __rest
     }
 }
 
+// Ket-split form: one wavefront = one output row and (64/G)*VEC consecutive
+// columns; its lanes form G groups that take G different ket entries of the row
+// per load step (group g takes entries g, g+G, ...; each lane gets its entry by
+// a lane shuffle).  A load instruction still moves 64 lanes' worth of bytes, but
+// the column tile, and so the per-XCD working set in[:, tile], is G times
+// narrower than the one-row form's.  The G partial sums of a column are added
+// across the groups at the end of the row in a fixed order.
+template <class T, int NV, int VEC, int G>
+__global__ void __launch_bounds__(256) k_stream_ks(StreamArgs<T> A, const T* __restrict__ in,
+                                                   T* __restrict__ out) {
+    constexpr int W = NV * VEC;
+    constexpr int GL = 64 / G;  // lanes per group
+    constexpr int UNR = W * (int)sizeof(T) <= 16 ? 8 : 4;  // load steps in flight
+    const int lane = threadIdx.x & 63;
+    const int grp = lane / GL, gl = lane % GL;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t g = blockIdx.x;
+    const int xcd = (int)(g & 7);
+    const int64_t l = g >> 3;
+    const int64_t tl = l / A.row_blocks;
+    const int64_t rb = l - tl * A.row_blocks;
+    const int64_t tile = tl * 8 + xcd;
+    const int64_t r = rb * A.rows_per_wg + wv;
+    if (tile >= A.ntiles || r >= A.nrow || wv >= A.rows_per_wg) return;  // wave-uniform
+    const int64_t ncol = A.ncol;
+    const int64_t col = (tile * GL + gl) * VEC;  // first of VEC columns (ncol % VEC == 0)
+    const bool act = col < ncol;
+    const int64_t cc = act ? col : 0;
+
+    T acc[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) acc[i] = T(0);
+    if (A.diag && grp == 0) {
+        const Vec<T, W> x = vload<T, W>(in + (r * ncol + cc) * NV);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+            const T dg = (T)(A.diag[r * ncol + cc + q] - A.shift);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[q * NV + v] = dg * x.x[q * NV + v];
+        }
+    }
+    // singles: coefficient = base + sign * G[pair][col]
+    {
+        const int64_t a0 = A.p1[r], a1 = A.p1[r + 1];
+        for (int64_t base = a0; base < a1; base += 64) {
+            const int cnt = (int)((a1 - base) < 64 ? (a1 - base) : 64);
+            const int mj = lane < cnt ? A.J1[base + lane] : 0;
+            const int mp = lane < cnt ? A.ps1[base + lane] : 0;
+            const T mc = lane < cnt ? A.c1[base + lane] : T(0);
+            for (int s = 0; s < cnt; s += G) {
+                const int k = s + grp;
+                const int j = __shfl(mj, k & 63, 64), ps = __shfl(mp, k & 63, 64);
+                const T cb = __shfl(mc, k & 63, 64);
+                if (k < cnt) {
+                    const Vec<T, VEC> gv = vload<T, VEC>(A.G + (int64_t)(ps >> 1) * ncol + cc);
+                    const Vec<T, W> x = vload<T, W>(in + ((int64_t)j * ncol + cc) * NV);
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) {
+                        const T coef = cb + ((ps & 1) ? -gv.x[q] : gv.x[q]);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) acc[q * NV + v] += coef * x.x[q * NV + v];
+                    }
+                }
+            }
+        }
+    }
+    // doubles: UNR steps of G entries in flight
+    {
+        const int64_t a0 = A.p2[r], a1 = A.p2[r + 1];
+        for (int64_t base = a0; base < a1; base += 64) {
+            const int cnt = (int)((a1 - base) < 64 ? (a1 - base) : 64);
+            const int mj = lane < cnt ? A.J2[base + lane] : 0;
+            const T mc = lane < cnt ? A.c2[base + lane] : T(0);
+            for (int s = 0; s < cnt; s += G * UNR) {
+                int j[UNR];
+                T f[UNR];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) {
+                    const int k = s + u * G + grp;
+                    const int jv = __shfl(mj, k & 63, 64);
+                    const T fv = __shfl(mc, k & 63, 64);
+                    const bool ok = k < cnt;
+                    j[u] = ok ? jv : (int)r;  // padded entries read a valid row with weight 0
+                    f[u] = ok ? fv : T(0);
+                }
+                Vec<T, W> x[UNR];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+                    if (s + u * G < cnt)  // wave-uniform: skip steps past the row's end
+                        x[u] = vload<T, W>(in + ((int64_t)j[u] * ncol + cc) * NV);
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+                    if (s + u * G < cnt)
+#pragma unroll
+                        for (int i = 0; i < W; ++i) acc[i] += f[u] * x[u].x[i];
+            }
+        }
+    }
+    // sum over the groups: (g0 + g1) + (g2 + g3), the same in every lane
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        if constexpr (G >= 2) acc[i] += __shfl_xor(acc[i], GL, 64);
+        if constexpr (G >= 4) acc[i] += __shfl_xor(acc[i], 2 * GL, 64);
+    }
+    if (act && grp == 0) {
+        T* dst = out + (r * ncol + col) * NV;
+#pragma unroll
+        for (int i = 0; i < W; ++i) dst[i] = acc[i];
+    }
+}
+
 // ------------------------------------------------------------------ alpha-beta
 template <class T>
 struct AbArgs {
@@ -387,6 +498,19 @@ hipError_t transpose(const T* in, T* out, int64_t nrow, int64_t ncol, hipStream_
     return hipGetLastError();
 }
 
+template <class T, int NV, int VEC, int G>
+hipError_t stream_ks(StreamArgs<T> S, const T* in, T* out, int rows_per_wg, hipStream_t st) {
+    S.rows_per_wg = rows_per_wg;
+    S.ntiles = (S.ncol + (64 / G) * VEC - 1) / ((64 / G) * VEC);
+    S.row_blocks = (S.nrow + rows_per_wg - 1) / rows_per_wg;
+    const int64_t tiles8 = (S.ntiles + 7) / 8 * 8;
+    const int64_t nblk = tiles8 * S.row_blocks;
+    if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_stream_ks<T, NV, VEC, G>), dim3((unsigned)nblk), dim3(64 * rows_per_wg), 0,
+                       st, S, in, out);
+    return hipGetLastError();
+}
+
 template <class T, int NV, int VEC, int RW>
 hipError_t stream_vec(StreamArgs<T> S, const T* in, T* out, int rows_per_wg, hipStream_t st) {
     S.rows_per_wg = rows_per_wg;
@@ -403,6 +527,8 @@ hipError_t stream_vec(StreamArgs<T> S, const T* in, T* out, int rows_per_wg, hip
 
 template <class T, int NV, int VEC>
 hipError_t stream_rw(StreamArgs<T> S, const T* in, T* out, const SigmaTune& tune, hipStream_t st) {
+    if (tune.stream_split == 4) return stream_ks<T, NV, VEC, 4>(S, in, out, tune.stream_rows, st);
+    if (tune.stream_split == 2) return stream_ks<T, NV, VEC, 2>(S, in, out, tune.stream_rows, st);
     if (tune.stream_rw == 2) return stream_vec<T, NV, VEC, 2>(S, in, out, tune.stream_rows, st);
     return stream_vec<T, NV, VEC, 1>(S, in, out, tune.stream_rows, st);
 }

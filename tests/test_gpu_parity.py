@@ -468,23 +468,25 @@ def test_error_paths_on_gpu():
 
 
 # ------------------------------------------------------------------ launch configurations
-@pytest.mark.parametrize("rw,lds", [(1, 4096), (2, 4096), (1, 49152), (2, 147456)])
+@pytest.mark.parametrize("rw,lds,split", [(1, 4096, 1), (2, 4096, 1), (1, 49152, 1), (2, 147456, 1),
+                                          (1, 49152, 2), (1, 4096, 4), (1, 147456, 4)])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("wide", [0, 1])
 @pytest.mark.parametrize("na_str,nb_str", [(333, 257), (336, 260)])
-def test_sigma_every_launch_config(rw, lds, prec, wide, na_str, nb_str):
+def test_sigma_every_launch_config(rw, lds, split, prec, wide, na_str, nb_str):
     """Every schedule the autotuner can pick gives the oracle's sigma: windowed
     alpha-beta staging (tiny LDS budget), several ket rows per group, one or
-    two rows per stream wavefront, 8- or 16-byte lane loads (the wide form
-    applies when the row lengths are multiples of the lane width: 336 x 260),
-    odd row counts; single vectors and two interleaved vectors."""
+    two rows per stream wavefront or 2 or 4 ket entries per load step, 8- or
+    16-byte lane loads (the wide form applies when the row lengths are
+    multiples of the lane width: 336 x 260), odd row counts; single vectors and
+    two interleaved vectors."""
     norb = 14
     A = wl.sample_strings(norb, 6, na_str, 51)
     B = wl.sample_strings(norb, 5, nb_str, 52)
     h, eri, ec = wl.make_integrals(norb, 53)
     _, _, ham = gpu_system(norb, 6, 5, A, B, h, eri, ec)
-    ham.set_tune(prec, rw, lds, wide)
-    assert ham.get_tune(prec) == dict(stream_rw=rw, ab_lds_bytes=lds, stream_wide=wide)
+    ham.set_tune(prec, rw, lds, wide, split)
+    assert ham.get_tune(prec) == dict(stream_rw=rw, ab_lds_bytes=lds, stream_wide=wide, stream_split=split)
     S = oracle.OracleSystem(norb, A, B, h, eri, ec)
     X = wl.random_vector(S.N, 54, nvec=2)
     shift = 0.0 if prec == 0 else S.diag().min()
