@@ -65,6 +65,59 @@ __global__ void __launch_bounds__(256) k_transpose(const T* __restrict__ in, T* 
     }
 }
 
+// Single-vector transpose with 16-byte accesses on both sides: a TD x TD tile
+// (64 x 64 floats) is read as rows of 16 vectors of E = 16/sizeof(T)
+// elements, staged in LDS, and written as rows of the transpose.  Needs ncol
+// and nrow to be multiples of E (16-byte aligned rows).
+template <class T, bool ADD>
+__global__ void __launch_bounds__(256) k_transpose_v(const T* __restrict__ in, T* __restrict__ out,
+                                                     int64_t nrow, int64_t ncol, int64_t nby) {
+    constexpr int E = 16 / (int)sizeof(T);
+    constexpr int TD = 16 * E;
+    constexpr int RPT = TD / 16;  // tile rows per thread per phase
+    __shared__ T tile[TD][TD + 1];
+    const int tv = threadIdx.x & 15, tr = threadIdx.x >> 4;  // vector column, row group
+    const int64_t c0 = (int64_t)blockIdx.x * TD;
+    for (int64_t by = blockIdx.y; by < nby; by += gridDim.y) {
+        const int64_t r0 = by * TD;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int j = tr + 16 * k;
+            const int64_t r = r0 + j, c = c0 + tv * E;
+            if (r < nrow && c < ncol) {
+                const float4 q = *reinterpret_cast<const float4*>(in + r * ncol + c);
+                T v[E];
+                __builtin_memcpy(v, &q, 16);
+#pragma unroll
+                for (int e = 0; e < E; ++e) tile[j][tv * E + e] = v[e];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int j = tr + 16 * k;             // output row within the tile (input column)
+            const int64_t c = c0 + j, r = r0 + tv * E;
+            if (c < ncol && r < nrow) {
+                T v[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[e] = tile[tv * E + e][j];
+                float4* dst = reinterpret_cast<float4*>(out + c * nrow + r);
+                if (ADD) {
+                    const float4 o = *dst;
+                    T w[E];
+                    __builtin_memcpy(w, &o, 16);
+#pragma unroll
+                    for (int e = 0; e < E; ++e) v[e] += w[e];
+                }
+                float4 q;
+                __builtin_memcpy(&q, v, 16);
+                *dst = q;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ row stream
 template <class T>
 struct StreamArgs {
@@ -489,8 +542,21 @@ __global__ void __launch_bounds__(1024) k_ab(AbArgs<T> A, const T* __restrict__ 
 }
 
 // ------------------------------------------------------------------ launchers
+// 16-byte aligned (vectors are only guaranteed 8-byte alignment)
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 template <class T, int NV, bool ADD>
 hipError_t transpose(const T* in, T* out, int64_t nrow, int64_t ncol, hipStream_t st) {
+    constexpr int E = 16 / (int)sizeof(T);
+    // FP32 only: for FP64 the 32 x 32 tile's 8-byte accesses are already 256-byte rows and measure faster
+    if (sizeof(T) == 4 && NV == 1 && ncol % E == 0 && nrow % E == 0 && aligned16(in) && aligned16(out)) {
+        constexpr int TD = 16 * E;
+        const int64_t nbx = (ncol + TD - 1) / TD, nby = (nrow + TD - 1) / TD;
+        const unsigned gy = (unsigned)(nby < 65535 ? nby : 65535);
+        hipLaunchKernelGGL((k_transpose_v<T, ADD>), dim3((unsigned)nbx, gy), dim3(256), 0, st, in, out,
+                           nrow, ncol, nby);
+        return hipGetLastError();
+    }
     const int64_t nbx = (ncol + 31) / 32, nby = (nrow + 31) / 32;
     const unsigned gy = (unsigned)(nby < 65535 ? nby : 65535);
     hipLaunchKernelGGL((k_transpose<T, NV, ADD>), dim3((unsigned)nbx, gy), dim3(256), 0, st, in,
@@ -541,7 +607,8 @@ hipError_t stream(StreamArgs<T> S, const T* in, T* out, const SigmaTune& tune, h
     constexpr int B = NV * (int)sizeof(T) >= 8 ? 1 : 8 / (NV * (int)sizeof(T));
     constexpr bool CAN_WIDE = NV * (int)sizeof(T) * B * 2 <= 16;
     if constexpr (CAN_WIDE) {
-        if (tune.stream_wide && S.ncol % (2 * B) == 0) return stream_rw<T, NV, 2 * B>(S, in, out, tune, st);
+        if (tune.stream_wide && S.ncol % (2 * B) == 0 && aligned16(in) && aligned16(out))
+            return stream_rw<T, NV, 2 * B>(S, in, out, tune, st);
     }
     if constexpr (B > 1) {
         if (S.ncol % B != 0) return stream_rw<T, NV, 1>(S, in, out, tune, st);

@@ -467,6 +467,41 @@ def test_error_paths_on_gpu():
         sbd.sigma(ham, x, torch.empty_like(x), nvec=9, layout=1)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sigma_vectors_only_8_byte_aligned(prec):
+    """Vectors the ABI allows at 8-byte alignment (here 8 bytes past a 16-byte
+    boundary) take the paths without 16-byte accesses and give the same sigma
+    as aligned ones; row lengths are multiples of four so that the aligned
+    vectors do take the 16-byte transpose and lane loads."""
+    norb = 14
+    A = wl.sample_strings(norb, 6, 336, 61)
+    B = wl.sample_strings(norb, 5, 260, 62)
+    h, eri, ec = wl.make_integrals(norb, 63)
+    _, _, ham = gpu_system(norb, 6, 5, A, B, h, eri, ec)
+    ham.set_tune(prec, 1, 98304, 1, 1)
+    S = oracle.OracleSystem(norb, A, B, h, eri, ec)
+    x = wl.random_vector(S.N, 64)[0]
+    dt = torch.float64 if prec == 0 else torch.float32
+    if prec == 1:
+        x = x.astype(np.float32).astype(np.float64)
+    shift = 0.0 if prec == 0 else S.diag().min()
+    ref = S.sigma(x) - shift * x
+    off = 8 // (8 if prec == 0 else 4)  # elements in 8 bytes
+    xb = torch.zeros(S.N + 8, device=DEV, dtype=dt)
+    yb = torch.zeros(S.N + 8, device=DEV, dtype=dt)
+    assert xb.data_ptr() % 16 == 0 and yb.data_ptr() % 16 == 0
+    xm, ym = xb[off:off + S.N], yb[off:off + S.N]
+    assert xm.data_ptr() % 16 == 8
+    xm.copy_(torch.from_numpy(x).to(dt))
+    sbd.sigma(ham, xm, ym, prec=prec, shift=shift)
+    torch.cuda.synchronize()
+    got = ym.cpu().numpy().astype(np.float64)
+    aligned = gpu_sigma(ham, x, prec=prec, shift=shift)
+    tol = 1e-12 if prec == 0 else 2e-5
+    assert rel(got, ref) <= tol and rel(aligned, ref) <= tol
+    assert np.all(yb[:off].cpu().numpy() == 0) and np.all(yb[off + S.N:].cpu().numpy() == 0)
+
+
 # ------------------------------------------------------------------ launch configurations
 @pytest.mark.parametrize("rw,lds,split", [(1, 4096, 1), (2, 4096, 1), (1, 49152, 1), (2, 147456, 1),
                                           (1, 49152, 2), (1, 4096, 4), (1, 147456, 4)])
