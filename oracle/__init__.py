@@ -16,6 +16,10 @@ Three tiers, each written from the paper (Sec. II):
 * tier 2 (``davidson``): the Davidson iteration of Sec. II-C with the
   damped diagonal preconditioner of Eqs. 6-7, modified Gram-Schmidt with a
   second pass, and restart; dense ``numpy.linalg.eigh`` for small spaces.
+
+``map_vector`` carries a vector from one determinant basis to another (the
+warm start of a later SQD iteration's solve, Sec. I and the free choice of the
+Davidson start vector, Sec. II-C).
 """
 from __future__ import annotations
 
@@ -392,6 +396,24 @@ def _reorth_pair(V, W):
     L = np.linalg.cholesky(G)
     Li = np.linalg.inv(L)
     return Li @ V, Li @ W
+
+
+def map_vector(alpha_from, beta_from, alpha_to, beta_to, x: np.ndarray) -> np.ndarray:
+    """Coefficients of x (over the determinants alpha_from x beta_from,
+    alpha-major) on the determinants alpha_to x beta_to: the coefficient of the
+    same determinant where it exists in the old basis, else 0.  All string
+    arrays sorted ascending and unique.  x may hold several vectors as rows."""
+    af, bf = np.asarray(alpha_from, np.uint64), np.asarray(beta_from, np.uint64)
+    at, bt = np.asarray(alpha_to, np.uint64), np.asarray(beta_to, np.uint64)
+    X = np.atleast_2d(np.asarray(x, np.float64)).reshape(-1, af.size, bf.size)
+    ia = np.searchsorted(af, at)
+    ib = np.searchsorted(bf, bt)
+    a_ok = (ia < af.size) & (af[np.minimum(ia, max(af.size - 1, 0))] == at) if af.size else np.zeros(at.size, bool)
+    b_ok = (ib < bf.size) & (bf[np.minimum(ib, max(bf.size - 1, 0))] == bt) if bf.size else np.zeros(bt.size, bool)
+    Y = np.zeros((X.shape[0], at.size, bt.size))
+    ra, rb = np.nonzero(a_ok)[0], np.nonzero(b_ok)[0]
+    Y[:, ra[:, None], rb[None, :]] = X[:, ia[ra][:, None], ib[rb][None, :]]
+    return Y.reshape(X.shape[0], -1) if np.ndim(x) > 1 else Y.reshape(-1)
 
 
 def dense_lowest(Hd: np.ndarray, nroots: int = 1):

@@ -327,3 +327,53 @@ def test_damped_inverse_eq7():
     d = np.array([-2.0, -1e-12, 0.0, 1e-12, 3.0])
     out = oracle.damped_inverse(d, 0.0, 1e-8)
     assert np.allclose(out, [-0.5, -1e8, 1e8, 1e8, 1 / 3.0])
+
+
+# ------------------------------------------------------------------ basis transfer (warm starts)
+def _map_brute(af, bf, at, bt, x):
+    """Determinant by determinant: look the (alpha, beta) pair up in the old basis."""
+    pos = {(int(a), int(b)): i * len(bf) + j for i, a in enumerate(af) for j, b in enumerate(bf)}
+    return np.array([x[pos[(int(a), int(b))]] if (int(a), int(b)) in pos else 0.0 for a in at for b in bt])
+
+
+def test_map_vector_brute_force_tiny():
+    """Mapping between overlapping, nested and disjoint string sets equals the
+    determinant-by-determinant lookup."""
+    full = wl.all_strings(7, 3)
+    rng = np.random.default_rng(5)
+    for t in range(6):
+        af = np.sort(rng.choice(full, 9, replace=False))
+        bf = np.sort(rng.choice(full, 7, replace=False))
+        at = np.sort(rng.choice(full, 11, replace=False)) if t % 2 else np.sort(np.union1d(af, full[:4]))
+        bt = np.sort(rng.choice(full, 5, replace=False))
+        x = rng.standard_normal(af.size * bf.size)
+        assert np.array_equal(oracle.map_vector(af, bf, at, bt, x), _map_brute(af, bf, at, bt, x))
+    # several vectors at once, and an empty overlap
+    X = rng.standard_normal((3, af.size * bf.size))
+    Y = oracle.map_vector(af, bf, at, bt, X)
+    for v in range(3):
+        assert np.array_equal(Y[v], _map_brute(af, bf, at, bt, X[v]))
+    lo, hi = full[:10], full[10:20]
+    assert not oracle.map_vector(lo, lo, hi, hi, np.ones(100)).any()
+
+
+def test_map_vector_embedding_keeps_rayleigh_quotient():
+    """Carried into a larger basis, an eigenvector of the smaller one keeps its
+    norm and its energy (the larger H restricted to the old determinants is the
+    old H), and carried back it is unchanged: the transfer respects the
+    alpha-major determinant order the sigma uses."""
+    norb, n = 8, 3
+    h, eri, ec = wl.make_integrals(norb, 91)
+    big_a = wl.sample_strings(norb, n, 40, 92)
+    big_b = wl.sample_strings(norb, n, 36, 93)
+    rng = np.random.default_rng(94)
+    sa = np.sort(rng.choice(big_a, 25, replace=False))
+    sb = np.sort(rng.choice(big_b, 20, replace=False))
+    small = oracle.OracleSystem(norb, sa, sb, h, eri, ec)
+    e, vecs = oracle.dense_lowest(small.dense_h(), 1)
+    x = vecs[0]
+    big = oracle.OracleSystem(norb, big_a, big_b, h, eri, ec)
+    y = oracle.map_vector(sa, sb, big_a, big_b, x)
+    assert abs(np.linalg.norm(y) - 1.0) < 1e-12
+    assert abs(y @ big.sigma(y) - e[0]) < 1e-10 * abs(e[0])
+    assert np.array_equal(oracle.map_vector(big_a, big_b, sa, sb, y), x)
