@@ -286,6 +286,50 @@ def block_leg(sbd, wl, stream):
     return out
 
 
+def sqd_leg(sbd, wl, stream, sizes=(6000, 8000, 10000)):
+    """Successive solves of an SQD run on a growing configuration set: the
+    sel26 string sets with 6000, 8000 and 10000 strings per spin (nested: the
+    same seeds draw the larger sets as supersets).  Cold: each solve starts
+    from unit vectors on the lowest diagonal entries.  Warm: each solve after
+    the first starts from the previous eigenvector carried into the new basis
+    (sbd_map_vectors).  Both in the chosen form (FP32 sigma, FP64
+    refinement); each sequence runs once untimed (autotuning of the three
+    shapes) and once timed, basis, tables and Hamiltonian included."""
+    import torch
+
+    Ws = [wl.make_config("sel26", nstr=n) for n in sizes]
+
+    def run(warm):
+        steps, prev = [], None
+        for W in Ws:
+            t0 = time.perf_counter()
+            B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
+            X = sbd.Excitations(B, stream=stream)
+            H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
+            kw = {}
+            if warm and prev is not None:
+                g = torch.empty(W.ndet, device="cuda", dtype=torch.float64)
+                sbd.map_vectors(prev[0], B, prev[1], g, stream=stream)
+                kw = dict(guess=g.view(1, -1), n_guess=1)
+            v = torch.empty(W.ndet, device="cuda", dtype=torch.float64)
+            e, rep, st = sbd.davidson(H, 1, vectors=v, stream=stream, tol_residual=1e-6, sigma_prec=sbd.FP32,
+                                      max_space=MAX_SPACE, use_autotune=1, **kw)
+            torch.cuda.synchronize()
+            steps.append(dict(strings_per_spin=int(W.alpha.size), determinants=W.ndet,
+                              ms=1e3 * (time.perf_counter() - t0), iterations=rep["iterations"],
+                              sigma_calls=rep["sigma_calls"], energy=float(e[0]), status=int(st)))
+            prev = (B, v)
+        return steps
+
+    run(False)
+    cold = run(False)
+    warm = run(True)
+    return dict(workload="sel26 nested string sets", strings_per_spin=list(sizes), tol_residual=1e-6,
+                cold=cold, warm=warm,
+                cold_ms=sum(x["ms"] for x in cold), warm_ms=sum(x["ms"] for x in warm),
+                energy_max_diff=max(abs(a["energy"] - b["energy"]) for a, b in zip(cold, warm)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,6 +340,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-block", action="store_true")
+    ap.add_argument("--no-sqd", action="store_true")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a few sigma launches and a calibration copy (counter runs)")
     ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
@@ -424,6 +469,11 @@ def main():
     if not args.no_block:
         extra["block"] = block_leg(sbd, wl, stream)
         log(f"[bench] block: {extra['block']}")
+    if not args.no_sqd:
+        extra["sqd_loop"] = sqd_leg(sbd, wl, stream)
+        q = extra["sqd_loop"]
+        log(f"[bench] sqd loop: cold {q['cold_ms']:.0f} ms {[x['iterations'] for x in q['cold']]} it, "
+            f"warm {q['warm_ms']:.0f} ms {[x['iterations'] for x in q['warm']]} it")
     if not args.no_serving:
         extra["serving"] = serving(sbd, wl)
         log(f"[bench] serving: {extra['serving']}")

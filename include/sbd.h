@@ -190,6 +190,24 @@ int sbd_sigma_timed(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h,
                     void* stream, double* stage_ms);
 
 /*
+ * Transfer of vectors between two bases of the same orbital and electron
+ * counts, for warm starts of successive solves: an SQD iteration refines the
+ * configuration set (Sec. I), and the Davidson start vector is free to choose
+ * (Sec. II-C), so the previous eigenvector, carried into the new basis, starts
+ * the next solve.  x_to[v][ia][ib] = x_from[v][ja][jb] where alpha string ia
+ * of `to` is string ja of `from` and beta string ib of `to` is string jb of
+ * `from`; 0 for determinants of `to` absent from `from`.  x_from: nvec device
+ * vectors of (from alphas x from betas) doubles, alpha-major, back to back;
+ * x_to: nvec device vectors of (to alphas x to betas) doubles, caller-owned,
+ * must not overlap x_from.  Values are copied, not rescaled (the copy of a
+ * unit vector has norm <= 1).  Synchronises the stream.
+ * Errors: SBD_ERR_ARG (null pointer, nvec < 1), SBD_ERR_STATE (different
+ * orbital or electron counts), SBD_ERR_NOMEM, SBD_ERR_HIP.
+ */
+int sbd_map_vectors(const sbd_basis* from, const sbd_basis* to, int nvec, const double* x_from,
+                    double* x_to, void* stream);
+
+/*
  * Tall-skinny projection out = A^T X (the Gram-Schmidt / Rayleigh-Ritz
  * projections of the Davidson update, Sec. II-C), one HBM sweep per row group
  * on the FP64 vector units.  A: ma device vectors of N doubles at A + j*N (1 <= ma <= 48);

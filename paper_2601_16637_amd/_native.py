@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "SBD_OK", 1: "SBD_NOT_CONVERGED", -1: "SBD_ERR_ARG", -2: "SBD
 EXPORTED = ["sbd_last_error", "sbd_version", "sbd_source_hash", "sbd_build_basis", "sbd_basis_sizes",
             "sbd_basis_strings", "sbd_free_basis", "sbd_build_excitations", "sbd_exc_count",
             "sbd_exc_export", "sbd_free_exc", "sbd_set_hamiltonian", "sbd_ham_diag",
-            "sbd_free_ham", "sbd_sigma", "sbd_sigma_timed", "sbd_autotune", "sbd_get_tune", "sbd_set_tune", "sbd_gram",
+            "sbd_free_ham", "sbd_sigma", "sbd_sigma_timed", "sbd_autotune", "sbd_get_tune", "sbd_set_tune", "sbd_gram", "sbd_map_vectors",
             "sbd_davidson_default_opts", "sbd_davidson", "sbd_serve_estimate", "sbd_serve_create",
             "sbd_serve_submit", "sbd_serve_wait", "sbd_serve_destroy"]
 
@@ -134,6 +134,7 @@ def load():
                                ctypes.POINTER(i32)]
     L.sbd_set_tune.argtypes = [P, i32, i32, i32, i32, i32]
     L.sbd_gram.argtypes = [P, i32, P, i32, i64, P, P]
+    L.sbd_map_vectors.argtypes = [P, P, i32, P, P, P]
     L.sbd_davidson_default_opts.argtypes = [ctypes.POINTER(DavidsonOpts)]
     L.sbd_davidson_default_opts.restype = None
     L.sbd_davidson.argtypes = [P, P, P, i32, ctypes.POINTER(DavidsonOpts), P, P,
@@ -311,6 +312,13 @@ def sigma_timed(ham: Hamiltonian, c, out, nvec: int = 1, prec: int = FP64, shift
                                  float(shift), _dptr(c), _dptr(out), int(layout),
                                  _stream(stream), _host(ms)))
     return dict(zip(SIGMA_STAGES, ms.tolist()))
+
+
+def map_vectors(basis_from: "Basis", basis_to: "Basis", x_from, x_to, nvec: int = 1, stream=None):
+    """Carry nvec FP64 device vectors from one basis into another (sbd_map_vectors):
+    determinants absent from basis_from get 0."""
+    check(load().sbd_map_vectors(basis_from._h, basis_to._h, int(nvec), _dptr(x_from), _dptr(x_to),
+                                 _stream(stream)))
 
 
 def gram(A, ma: int, X, k: int, N: int, stream=None) -> np.ndarray:

@@ -511,6 +511,27 @@ extern "C" int sbd_sigma_timed(const sbd_basis* b, const sbd_exc* x, const sbd_h
     return SBD_OK;
 }
 
+extern "C" int sbd_map_vectors(const sbd_basis* from, const sbd_basis* to, int nvec, const double* x_from,
+                               double* x_to, void* stream) {
+    if (!from || !to || !x_from || !x_to) return fail(SBD_ERR_ARG, "null argument");
+    if (nvec < 1) return fail(SBD_ERR_ARG, "nvec must be >= 1");
+    if (from->norb != to->norb || from->n_el[0] != to->n_el[0] || from->n_el[1] != to->n_el[1])
+        return fail(SBD_ERR_STATE, "bases differ in orbital or electron counts");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t na = to->s[0].n, nb = to->s[1].n, naf = from->s[0].n, nbf = from->s[1].n;
+    DevBuf amap, bmap;
+    SBD_HIP(amap.alloc(sizeof(int64_t) * (size_t)std::max<int64_t>(na, 1)));
+    SBD_HIP(bmap.alloc(sizeof(int64_t) * (size_t)std::max<int64_t>(nb, 1)));
+    SBD_HIP(launch_string_map(to->s[0].d.as<uint64_t>(), na, from->s[0].d.as<uint64_t>(), naf,
+                              amap.as<int64_t>(), st));
+    SBD_HIP(launch_string_map(to->s[1].d.as<uint64_t>(), nb, from->s[1].d.as<uint64_t>(), nbf,
+                              bmap.as<int64_t>(), st));
+    SBD_HIP(launch_map_vectors(amap.as<int64_t>(), bmap.as<int64_t>(), na, nb, nbf, naf * nbf, nvec, x_from,
+                               x_to, st));
+    SBD_HIP(hipStreamSynchronize(st));
+    return SBD_OK;
+}
+
 extern "C" int sbd_gram(const double* A, int ma, const double* X, int k, int64_t N, double* out,
                         void* stream) {
     if (!A || !X || !out || N < 1) return fail(SBD_ERR_ARG, "null argument or N < 1");

@@ -260,6 +260,13 @@ hipError_t launch_set_int(int* d_p, int v, hipStream_t st);
 hipError_t launch_max(const double* v, int64_t N, double* d_val, double* d_part, hipStream_t st);
 
 hipError_t launch_fill_pattern(void* p, int64_t n, int prec, hipStream_t st);
+// map[i] = position of to[i] in the sorted from[0..nfrom), or -1
+hipError_t launch_string_map(const uint64_t* to, int64_t nto, const uint64_t* from, int64_t nfrom,
+                             int64_t* map, hipStream_t st);
+// y[v][ia][ib] = x[v][amap[ia]][bmap[ib]] (0 where either map is -1); y has nvec x na x nb,
+// x has nvec vectors of n_from = (old alpha count) x nb_from
+hipError_t launch_map_vectors(const int64_t* amap, const int64_t* bmap, int64_t na, int64_t nb, int64_t nb_from,
+                              int64_t n_from, int nvec, const double* x, double* y, hipStream_t st);
 hipError_t launch_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
 hipError_t launch_f32_to_f64_axpy(const float* y32, const double* x, double shift, double* y,
                                   int64_t n, hipStream_t st);

@@ -1,8 +1,11 @@
 // Dense FP64 vector kernels of the Davidson driver (Sec. II-C): linear
 // combinations V Y (collapse and restart), scaling, precision conversions for
-// the FP32 sigma, start-vector selection and small reductions.  Reductions are
+// the FP32 sigma, start-vector selection, the transfer of vectors between two
+// bases (warm starts of successive solves) and small reductions.  Reductions are
 // two-stage with a fixed block count and a fixed combination order, so results
 // do not depend on scheduling.  These kernels are bound by HBM bandwidth.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace sbd {
@@ -165,6 +168,38 @@ __global__ void k_f32_to_f64_axpy(const float* y32, const double* x, double shif
         y[i] = (double)y32[i] + shift * x[i];
 }
 
+// map[i] = index of to[i] in the sorted array from[0..nfrom), or -1
+__global__ void k_string_map(const uint64_t* __restrict__ to, int64_t nto, const uint64_t* __restrict__ from,
+                             int64_t nfrom, int64_t* __restrict__ map) {
+    for (int64_t i = (int64_t)blockIdx.x * kVB + threadIdx.x; i < nto; i += (int64_t)gridDim.x * kVB) {
+        const uint64_t s = to[i];
+        int64_t lo = 0, hi = nfrom;  // first position with from[pos] >= s
+        while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if (from[mid] < s) lo = mid + 1; else hi = mid;
+        }
+        map[i] = (lo < nfrom && from[lo] == s) ? lo : -1;
+    }
+}
+
+// y[v][ia][ib] = x[v][amap[ia]][bmap[ib]] when both strings exist in the old
+// basis, else 0.  Grid: x over beta columns, y over (vector, alpha row).
+__global__ void k_map_vectors(const int64_t* __restrict__ amap, const int64_t* __restrict__ bmap, int64_t na,
+                              int64_t nb, int64_t nb_from, int64_t n_from, int nvec,
+                              const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t nrows = (int64_t)nvec * na;
+    for (int64_t row = blockIdx.y; row < nrows; row += gridDim.y) {
+        const int64_t v = row / na, ia = row - v * na;
+        const int64_t ja = amap[ia];
+        const double* xr = x + v * n_from + (ja >= 0 ? ja : 0) * nb_from;
+        double* yr = y + (v * na + ia) * nb;
+        for (int64_t ib = (int64_t)blockIdx.x * kVB + threadIdx.x; ib < nb; ib += (int64_t)gridDim.x * kVB) {
+            const int64_t jb = bmap[ib];
+            yr[ib] = (ja >= 0 && jb >= 0) ? xr[jb] : 0.0;
+        }
+    }
+}
+
 // Deterministic bounded test pattern: x_i = sin(0.37 i) (FP64 or FP32).
 __global__ void k_fill_pattern(void* p, int64_t n, int prec) {
     for (int64_t i = (int64_t)blockIdx.x * kVB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVB) {
@@ -248,6 +283,23 @@ hipError_t launch_max(const double* v, int64_t N, double* d_val, double* d_part,
 
 hipError_t launch_set_unit(double* x, int64_t N, int64_t idx, hipStream_t st) {
     hipLaunchKernelGGL(k_set_unit, dim3(red_blocks(N)), dim3(kVB), 0, st, x, N, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_string_map(const uint64_t* to, int64_t nto, const uint64_t* from, int64_t nfrom,
+                             int64_t* map, hipStream_t st) {
+    if (nto == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_string_map, dim3(red_blocks(nto)), dim3(kVB), 0, st, to, nto, from, nfrom, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_vectors(const int64_t* amap, const int64_t* bmap, int64_t na, int64_t nb, int64_t nb_from,
+                              int64_t n_from, int nvec, const double* x, double* y, hipStream_t st) {
+    if (na == 0 || nb == 0 || nvec == 0) return hipSuccess;
+    const int64_t gx = std::min<int64_t>((nb + kVB - 1) / kVB, 64);
+    const int64_t gy = std::min<int64_t>((int64_t)nvec * na, 65535);
+    hipLaunchKernelGGL(k_map_vectors, dim3((unsigned)gx, (unsigned)gy), dim3(kVB), 0, st, amap, bmap, na, nb,
+                       nb_from, n_from, nvec, x, y);
     return hipGetLastError();
 }
 

@@ -563,3 +563,76 @@ def test_gram_vs_numpy(ma, k, N):
     assert np.abs(G - ref).max() <= 1e-12 * max(1.0, np.abs(A).sum(axis=1).max() * 4)
     G2 = sbd.gram(Ad, ma, Xd, k, N)
     assert np.array_equal(G, G2)          # fixed reduction order: bitwise repeatable
+
+
+# ------------------------------------------------------------------ f4 warm starts between bases
+@pytest.mark.parametrize("case", ["superset", "subset", "overlap", "disjoint"])
+def test_map_vectors_bitexact(case):
+    """sbd_map_vectors against the oracle's transfer, bit for bit, on two
+    vectors at once (values are copied, never combined)."""
+    norb, n = 12, 5
+    full = wl.all_strings(norb, n)
+    rng = np.random.default_rng({"superset": 1, "subset": 2, "overlap": 3, "disjoint": 4}[case])
+    af = np.sort(rng.choice(full, 300, replace=False))
+    bf = np.sort(rng.choice(full, 170, replace=False))
+    if case == "superset":
+        at, bt = np.union1d(af, full[:50]), np.union1d(bf, full[-40:])
+    elif case == "subset":
+        at, bt = af[::3].copy(), bf[1::2].copy()
+    elif case == "overlap":
+        at = np.sort(rng.choice(full, 257, replace=False))
+        bt = np.sort(rng.choice(full, 333, replace=False))
+    else:
+        rest = np.setdiff1d(full, af)
+        at, bt = rest[:64].copy(), np.setdiff1d(full, bf)[:65].copy()
+    h, eri, ec = wl.make_integrals(norb, 5)
+    bas_f = sbd.Basis(norb, n, n, af, bf)
+    bas_t = sbd.Basis(norb, n, n, at, bt)
+    X = rng.standard_normal((2, af.size * bf.size))
+    xd = dev(X.reshape(-1))
+    yd = torch.full((2 * at.size * bt.size,), 7.0, device=DEV, dtype=torch.float64)
+    sbd.map_vectors(bas_f, bas_t, xd, yd, nvec=2)
+    got = yd.cpu().numpy().reshape(2, -1)
+    ref = oracle.map_vector(af, bf, at, bt, X)
+    assert np.array_equal(got, ref)
+
+
+def test_map_vectors_rejects_other_electron_counts():
+    A = wl.sample_strings(10, 4, 30, 1)
+    B = wl.sample_strings(10, 3, 30, 2)
+    b1 = sbd.Basis(10, 4, 4, A, A)
+    b2 = sbd.Basis(10, 3, 3, B, B)
+    x = torch.zeros(b1.na * b1.nb, device=DEV, dtype=torch.float64)
+    y = torch.zeros(b2.na * b2.nb, device=DEV, dtype=torch.float64)
+    with pytest.raises(sbd.SBDError):
+        sbd.map_vectors(b1, b2, x, y)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_warm_start_from_smaller_basis(prec):
+    """A later SQD iteration's solve on a grown string set, started from the
+    previous eigenvector carried into the new basis, reaches the same energy as
+    a cold start, within the tolerance, in fewer iterations; the oracle checks
+    the warm-started eigenpair's residual on sampled rows."""
+    W = wl.make_config("sel16", nstr=1500)
+    small = wl.make_config("sel16", nstr=900)  # nested: same seeds, fewer strings
+    assert np.isin(small.alpha, W.alpha).all() and np.isin(small.beta, W.beta).all()
+    _, _, hs = from_workload(small)
+    v0 = torch.empty(small.ndet, device=DEV, dtype=torch.float64)
+    _, _, st = sbd.davidson(hs, 1, vectors=v0, tol_residual=1e-7, sigma_prec=prec)
+    assert st == 0
+    bas, _, ham = from_workload(W)
+    guess = torch.empty(W.ndet, device=DEV, dtype=torch.float64)
+    sbd.map_vectors(hs.basis, bas, v0, guess)
+    cold_e, cold, st0 = sbd.davidson(ham, 1, tol_residual=1e-7, sigma_prec=prec)
+    vec = torch.empty(W.ndet, device=DEV, dtype=torch.float64)
+    warm_e, warm, st1 = sbd.davidson(ham, 1, vectors=vec, tol_residual=1e-7, sigma_prec=prec,
+                                     guess=guess.view(1, -1), n_guess=1)
+    assert st0 == 0 and st1 == 0
+    assert abs(warm_e[0] - cold_e[0]) <= 1e-9 * abs(cold_e[0])
+    assert warm["iterations"] < cold["iterations"]
+    S = oracle.OracleSystem.from_workload(W)
+    u = vec.cpu().numpy()
+    idx = np.argsort(-np.abs(u))[:300]
+    r = S.sigma_at(u, idx) - (warm_e[0]) * u[idx]
+    assert np.linalg.norm(r) <= 1e-7 * 1.01
