@@ -286,20 +286,18 @@ def block_leg(sbd, wl, stream):
     return out
 
 
-def sqd_leg(sbd, wl, stream, sizes=(6000, 8000, 10000)):
-    """Successive solves of an SQD run on a growing configuration set: the
-    sel26 string sets with 6000, 8000 and 10000 strings per spin (nested: the
-    same seeds draw the larger sets as supersets).  Cold: each solve starts
-    from unit vectors on the lowest diagonal entries.  Warm: each solve after
-    the first starts from the previous eigenvector carried into the new basis
-    (sbd_map_vectors).  Both in the chosen form (FP32 sigma, FP64
-    refinement); each sequence runs once untimed (autotuning of the three
-    shapes) and once timed, basis, tables and Hamiltonian included."""
+def sqd_leg(sbd, wl, stream, sequences=(("coarse", (6000, 8000, 10000)), ("fine", (9000, 9500, 10000)))):
+    """Successive solves of an SQD run on a growing configuration set: sel26
+    string sets of increasing size per spin (nested: the same seeds draw the
+    larger sets as supersets), in a coarse and a fine growth sequence.  Cold:
+    each solve starts from the unit vector on the lowest diagonal entry.  Warm:
+    each solve after the first starts from the previous eigenvector carried
+    into the new basis (sbd_map_vectors).  Chosen form (FP32 sigma, FP64
+    refinement); each sequence runs once untimed (autotuning of its shapes) and
+    then cold and warm, timed, basis, tables and Hamiltonian included."""
     import torch
 
-    Ws = [wl.make_config("sel26", nstr=n) for n in sizes]
-
-    def run(warm):
+    def run(Ws, warm):
         steps, prev = [], None
         for W in Ws:
             t0 = time.perf_counter()
@@ -316,18 +314,21 @@ def sqd_leg(sbd, wl, stream, sizes=(6000, 8000, 10000)):
                                       max_space=MAX_SPACE, use_autotune=1, **kw)
             torch.cuda.synchronize()
             steps.append(dict(strings_per_spin=int(W.alpha.size), determinants=W.ndet,
-                              ms=1e3 * (time.perf_counter() - t0), iterations=rep["iterations"],
-                              sigma_calls=rep["sigma_calls"], energy=float(e[0]), status=int(st)))
+                              ms=1e3 * (time.perf_counter() - t0), solver_ms=rep["t_total_ms"],
+                              iterations=rep["iterations"], sigma_calls=rep["sigma_calls"],
+                              energy=float(e[0]), status=int(st)))
             prev = (B, v)
         return steps
 
-    run(False)
-    cold = run(False)
-    warm = run(True)
-    return dict(workload="sel26 nested string sets", strings_per_spin=list(sizes), tol_residual=1e-6,
-                cold=cold, warm=warm,
-                cold_ms=sum(x["ms"] for x in cold), warm_ms=sum(x["ms"] for x in warm),
-                energy_max_diff=max(abs(a["energy"] - b["energy"]) for a, b in zip(cold, warm)))
+    out = dict(workload="sel26 nested string sets", tol_residual=1e-6)
+    for name, sizes in sequences:
+        Ws = [wl.make_config("sel26", nstr=n) for n in sizes]
+        run(Ws, False)
+        cold, warm = run(Ws, False), run(Ws, True)
+        out[name] = dict(strings_per_spin=list(sizes), cold=cold, warm=warm,
+                         cold_ms=sum(x["ms"] for x in cold), warm_ms=sum(x["ms"] for x in warm),
+                         energy_max_diff=max(abs(a["energy"] - b["energy"]) for a, b in zip(cold, warm)))
+    return out
 
 
 def main():
@@ -471,9 +472,11 @@ def main():
         log(f"[bench] block: {extra['block']}")
     if not args.no_sqd:
         extra["sqd_loop"] = sqd_leg(sbd, wl, stream)
-        q = extra["sqd_loop"]
-        log(f"[bench] sqd loop: cold {q['cold_ms']:.0f} ms {[x['iterations'] for x in q['cold']]} it, "
-            f"warm {q['warm_ms']:.0f} ms {[x['iterations'] for x in q['warm']]} it")
+        for name in ("coarse", "fine"):
+            q = extra["sqd_loop"][name]
+            log(f"[bench] sqd loop {name} {q['strings_per_spin']}: cold {q['cold_ms']:.0f} ms "
+                f"{[x['iterations'] for x in q['cold']]} it, warm {q['warm_ms']:.0f} ms "
+                f"{[x['iterations'] for x in q['warm']]} it, energies {[round(x['energy'], 6) for x in q['warm']]}")
     if not args.no_serving:
         extra["serving"] = serving(sbd, wl)
         log(f"[bench] serving: {extra['serving']}")
