@@ -559,9 +559,12 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         if (rc) return rc;
     }
     if (m < k) return fail(SBD_ERR_ARG, "could not form nroots independent start vectors");
-    // the start vectors get an exact FP64 sigma, so the first residuals are certified
-    rc = S.apply_sigma(0, m, true);
+    // the start vectors' sigma in the solve's precision: in mixed precision they
+    // carry the FP32 error bound like every later vector (a start vector that is
+    // already an eigenvector is then certified by the first refresh)
+    rc = S.apply_sigma(0, m, false);
     if (rc) return rc;
+    for (int j = 0; j < m; ++j) ebound[j] = S.mixed ? rho : 0.0;
     std::vector<double> T((size_t)ms * ms, 0.0);
     rc = S.rebuild_T(m, T);
     if (rc) return rc;
@@ -571,7 +574,7 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     int it = 0;
     bool converged = false;
     int since_cert = 0;
-    bool certified = true;  // residuals computed from an all-FP64 W
+    bool certified = !S.mixed;  // residuals computed from an all-FP64 W
     std::vector<double> ebnd(k, 0.0);
     int hist_n = 0;
     std::vector<double> hist_theta, hist_time;
