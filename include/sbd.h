@@ -158,7 +158,8 @@ int sbd_sigma(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h,
  * this shape (prec, nvec, layout as in sbd_sigma) and stores the fastest in
  * the Hamiltonian handle for that precision; results are cached per shape for the process, so a
  * second call on the same shape costs nothing.  best_ms (nullable) receives
- * the winner's time per sigma, or -1 when taken from the cache.  Must not run
+ * the winner's time per sigma, or -1 when taken from the cache (or when the
+ * precision is assembled, see sbd_ham_assemble: then nothing is tuned).  Must not run
  * concurrently with other calls on the same handle.  Sigma results do not
  * depend on the choice beyond floating-point summation order.
  * Errors: SBD_ERR_ARG, SBD_ERR_STATE, SBD_ERR_NOMEM, SBD_ERR_HIP.
@@ -188,6 +189,33 @@ int sbd_set_tune(sbd_ham* h, int prec, int stream_rw, int ab_lds_bytes, int stre
 int sbd_sigma_timed(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h,
                     int nvec, int prec, double shift, const void* c, void* sigma, int layout,
                     void* stream, double* stage_ms);
+
+/*
+ * Explicit realization of H (Sec. II-A): assemble every connected pair of the
+ * basis into a CSR matrix owned by the handle (32-bit columns, FP64 values,
+ * and FP32 values when requested), built from the same tables and
+ * coefficients as the matrix-free sigma.  Row I = (ia, ib) stores the
+ * diagonal, the alpha singles and doubles of ia, the beta singles and doubles
+ * of ib, then the alpha-single x beta-single pairs; each nonzero H_IJ once.
+ * precisions: 1 = FP64, 2 = FP32, 3 = both.  max_bytes (0 = no limit) bounds
+ * the device bytes of the matrix; the entry count is known (and written to
+ * nnz_out, nullable) before anything large is allocated.  While a precision
+ * is assembled, sbd_sigma, sbd_sigma_timed (the product is reported as the
+ * alpha-stream stage, the other stages as 0) and sbd_davidson on this handle
+ * apply H through the CSR product y = (H - shift) x for that precision, with
+ * the same layouts; sbd_ham_release_assembled returns to the matrix-free
+ * sigma.  Synchronises the stream.  Not to be called while other calls use
+ * the handle.  Errors: SBD_ERR_ARG (null, precisions outside 1..3, 2^31 or
+ * more determinants), SBD_ERR_STATE (tables of another basis), SBD_ERR_NOMEM
+ * (allocation failed, or larger than max_bytes: the handle is unchanged),
+ * SBD_ERR_HIP.
+ */
+int sbd_ham_assemble(sbd_ham* h, const sbd_exc* e, int precisions, size_t max_bytes, void* stream,
+                     int64_t* nnz_out);
+int sbd_ham_release_assembled(sbd_ham* h);
+/* Stored entries of the assembled matrix (0 if none) and the assembled
+ * precisions (bit 0 FP64, bit 1 FP32); either pointer may be NULL. */
+int sbd_ham_assembled(const sbd_ham* h, int64_t* nnz, int* precisions);
 
 /*
  * Transfer of vectors between two bases of the same orbital and electron

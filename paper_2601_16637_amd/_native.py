@@ -28,6 +28,7 @@ EXPORTED = ["sbd_last_error", "sbd_version", "sbd_source_hash", "sbd_build_basis
             "sbd_basis_strings", "sbd_free_basis", "sbd_build_excitations", "sbd_exc_count",
             "sbd_exc_export", "sbd_free_exc", "sbd_set_hamiltonian", "sbd_ham_diag",
             "sbd_free_ham", "sbd_sigma", "sbd_sigma_timed", "sbd_autotune", "sbd_get_tune", "sbd_set_tune", "sbd_gram", "sbd_map_vectors",
+            "sbd_ham_assemble", "sbd_ham_release_assembled", "sbd_ham_assembled",
             "sbd_davidson_default_opts", "sbd_davidson", "sbd_serve_estimate", "sbd_serve_create",
             "sbd_serve_submit", "sbd_serve_wait", "sbd_serve_destroy"]
 
@@ -135,6 +136,9 @@ def load():
     L.sbd_set_tune.argtypes = [P, i32, i32, i32, i32, i32]
     L.sbd_gram.argtypes = [P, i32, P, i32, i64, P, P]
     L.sbd_map_vectors.argtypes = [P, P, i32, P, P, P]
+    L.sbd_ham_assemble.argtypes = [P, P, i32, ctypes.c_size_t, P, ctypes.POINTER(i64)]
+    L.sbd_ham_release_assembled.argtypes = [P]
+    L.sbd_ham_assembled.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]
     L.sbd_davidson_default_opts.argtypes = [ctypes.POINTER(DavidsonOpts)]
     L.sbd_davidson_default_opts.restype = None
     L.sbd_davidson.argtypes = [P, P, P, i32, ctypes.POINTER(DavidsonOpts), P, P,
@@ -271,6 +275,23 @@ class Hamiltonian:
         check(load().sbd_autotune(self.basis._h, self.exc._h, self._h, int(prec), int(nvec),
                                   int(layout), _stream(stream), ctypes.byref(ms)))
         return ms.value
+
+    def assemble(self, precisions: int = 3, max_bytes: int = 0, stream=None) -> int:
+        """Explicit CSR realization of H (sbd_ham_assemble); returns the stored
+        entries.  precisions: 1 FP64, 2 FP32, 3 both."""
+        nnz = ctypes.c_int64()
+        check(load().sbd_ham_assemble(self._h, self.exc._h, int(precisions), int(max_bytes), _stream(stream),
+                                      ctypes.byref(nnz)))
+        return nnz.value
+
+    def release_assembled(self):
+        check(load().sbd_ham_release_assembled(self._h))
+
+    def assembled(self):
+        """(stored entries, precision bits) of the assembled matrix (sbd_ham_assembled)."""
+        nnz, pr = ctypes.c_int64(), ctypes.c_int()
+        check(load().sbd_ham_assembled(self._h, ctypes.byref(nnz), ctypes.byref(pr)))
+        return nnz.value, pr.value
 
     def get_tune(self, prec: int = FP64):
         rw, lds, wide, split = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -433,8 +433,33 @@ SigmaArgs<float> make_args<float>(const sbd_exc* x, const sbd_ham* H, double shi
     return A;
 }
 
+// y = (H - shift) c through the assembled CSR (nvec vectors, either layout);
+// ev (nullable): the six stage events, all but the first two after the product
+static int spmv_internal(const sbd_ham* H, int nvec, int prec, double shift, const void* c, void* y,
+                         int layout, hipStream_t st, hipEvent_t* ev) {
+    const int64_t N = H->na * H->nb;
+    const int64_t* rp = H->csr_rp.as<int64_t>();
+    const int32_t* col = H->csr_col.as<int32_t>();
+    hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
+    const int nv = layout == 1 ? nvec : 1;
+    const int reps = layout == 1 ? 1 : nvec;
+    for (int v = 0; v < reps && e == hipSuccess; ++v) {
+        if (prec == SBD_FP64)
+            e = launch_spmv<double>(rp, col, H->csr_v64.as<double>(), N, nv, shift,
+                                    (const double*)c + (size_t)v * N, (double*)y + (size_t)v * N, st);
+        else
+            e = launch_spmv<float>(rp, col, H->csr_v32.as<float>(), N, nv, shift,
+                                   (const float*)c + (size_t)v * N, (float*)y + (size_t)v * N, st);
+    }
+    for (int i = 2; i < 6 && e == hipSuccess && ev; ++i) e = hipEventRecord(ev[i], st);
+    if (e != hipSuccess) return hip_fail(e, "sbd_sigma (assembled) launch");
+    return SBD_OK;
+}
+
 int sigma_internal(const sbd_exc* x, const sbd_ham* H, int nvec, int prec, double shift,
                    const void* c, void* y, int layout, void* ws, hipStream_t st, hipEvent_t* ev) {
+    if (H->csr_has[prec == SBD_FP64 ? 0 : 1]) return spmv_internal(H, nvec, prec, shift, c, y, layout, st, ev);
     hipError_t e;
     const SigmaTune tune = H->tune[prec == SBD_FP64 ? 0 : 1];
     if (prec == SBD_FP64)
@@ -508,6 +533,75 @@ extern "C" int sbd_sigma_timed(const sbd_basis* b, const sbd_exc* x, const sbd_h
     for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
     if (rc) return rc;
     if (e != hipSuccess) return hip_fail(e, "sbd_sigma_timed");
+    return SBD_OK;
+}
+
+extern "C" int sbd_ham_assemble(sbd_ham* H, const sbd_exc* x, int precisions, size_t max_bytes, void* stream,
+                                int64_t* nnz_out) {
+    if (!H || !x) return fail(SBD_ERR_ARG, "null argument");
+    if (H->exc_id != x->id) return fail(SBD_ERR_STATE, "tables do not belong to this Hamiltonian");
+    if (precisions < 1 || precisions > 3) return fail(SBD_ERR_ARG, "precisions must be 1 (FP64), 2 (FP32) or 3");
+    const int64_t N = H->na * H->nb;
+    if (N >= ((int64_t)1 << 31)) return fail(SBD_ERR_ARG, "assembly needs fewer than 2^31 determinants");
+    hipStream_t st = (hipStream_t)stream;
+    CsrTables t{};
+    t.na = H->na; t.nb = H->nb; t.norb = H->norb;
+    const Table *a1 = &x->t[0][0], *a2 = &x->t[0][1], *b1 = &x->t[1][0], *b2 = &x->t[1][1];
+    t.a1p = a1->row_ptr.as<int64_t>(); t.a2p = a2->row_ptr.as<int64_t>();
+    t.b1p = b1->row_ptr.as<int64_t>(); t.b2p = b2->row_ptr.as<int64_t>();
+    t.a1J = a1->J.as<int32_t>(); t.a2J = a2->J.as<int32_t>(); t.b1J = b1->J.as<int32_t>(); t.b2J = b2->J.as<int32_t>();
+    t.a1c = H->sc[0].c1_64.as<double>(); t.a2c = H->sc[0].c2_64.as<double>();
+    t.b1c = H->sc[1].c1_64.as<double>(); t.b2c = H->sc[1].c2_64.as<double>();
+    t.a1ps = H->sc[0].ps1.as<int32_t>(); t.b1ps = H->sc[1].ps1.as<int32_t>();
+    t.a1pack = a1->pack.as<uint64_t>(); t.b1pack = b1->pack.as<uint64_t>();
+    t.Ga = H->sc[0].G64.as<double>(); t.Gb = H->sc[1].G64.as<double>();
+    t.eri = H->eri64.as<double>(); t.diag = H->diag.as<double>();
+    // row lengths, their scan, then the size check before the large allocations
+    DevBuf cnt, rp;
+    SBD_HIP(cnt.alloc(sizeof(int64_t) * (size_t)std::max<int64_t>(N, 1)));
+    SBD_HIP(rp.alloc(sizeof(int64_t) * (size_t)(N + 1)));
+    SBD_HIP(launch_csr_count(t, cnt.as<int64_t>(), st));
+    SBD_HIP(launch_exclusive_scan(cnt.as<int64_t>(), N, rp.as<int64_t>(), st));
+    int64_t nnz = 0;
+    SBD_HIP(hipMemcpyAsync(&nnz, rp.as<int64_t>() + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SBD_HIP(hipStreamSynchronize(st));
+    const bool f32 = (precisions & 2) != 0;
+    const size_t need = (size_t)nnz * (sizeof(int32_t) + sizeof(double) + (f32 ? sizeof(float) : 0)) +
+                        sizeof(int64_t) * (size_t)(N + 1);
+    if (nnz_out) *nnz_out = nnz;
+    if (max_bytes && need > max_bytes) return fail(SBD_ERR_NOMEM, "assembled Hamiltonian exceeds max_bytes");
+    DevBuf col, v64, v32;
+    SBD_HIP(col.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1)));
+    SBD_HIP(v64.alloc(sizeof(double) * (size_t)std::max<int64_t>(nnz, 1)));
+    if (f32) SBD_HIP(v32.alloc(sizeof(float) * (size_t)std::max<int64_t>(nnz, 1)));
+    SBD_HIP(launch_csr_fill(t, rp.as<int64_t>(), col.as<int32_t>(), v64.as<double>(), f32 ? v32.as<float>() : nullptr,
+                            st));
+    SBD_HIP(hipStreamSynchronize(st));
+    H->csr_rp = std::move(rp);
+    H->csr_col = std::move(col);
+    H->csr_v64 = std::move(v64);
+    H->csr_v32 = std::move(v32);
+    H->csr_nnz = nnz;
+    H->csr_has[0] = (precisions & 1) != 0;
+    H->csr_has[1] = f32;
+    return SBD_OK;
+}
+
+extern "C" int sbd_ham_release_assembled(sbd_ham* H) {
+    if (!H) return fail(SBD_ERR_ARG, "null argument");
+    H->csr_has[0] = H->csr_has[1] = false;
+    H->csr_nnz = 0;
+    H->csr_rp = DevBuf();
+    H->csr_col = DevBuf();
+    H->csr_v64 = DevBuf();
+    H->csr_v32 = DevBuf();
+    return SBD_OK;
+}
+
+extern "C" int sbd_ham_assembled(const sbd_ham* H, int64_t* nnz, int* precisions) {
+    if (!H) return fail(SBD_ERR_ARG, "null argument");
+    if (nnz) *nnz = H->csr_nnz;
+    if (precisions) *precisions = (H->csr_has[0] ? 1 : 0) | (H->csr_has[1] ? 2 : 0);
     return SBD_OK;
 }
 

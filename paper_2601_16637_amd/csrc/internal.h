@@ -48,6 +48,23 @@ struct DevBuf {
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), regional(o.regional) {
+        o.p = nullptr;
+        o.bytes = 0;
+        o.regional = false;
+    }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            bytes = o.bytes;
+            regional = o.regional;
+            o.p = nullptr;
+            o.bytes = 0;
+            o.regional = false;
+        }
+        return *this;
+    }
     ~DevBuf() { release(); }
     hipError_t alloc(size_t n) {
         release();
@@ -147,6 +164,10 @@ struct sbd_ham {
     sbd::DevBuf h64, eri64, eri32;  // integrals on device
     sbd::SpinCoef sc[2];
     sbd::DevBuf diag;               // double[N]
+    // explicit realization (sbd_ham_assemble): H in CSR, FP64 values and optionally FP32
+    sbd::DevBuf csr_rp, csr_col, csr_v64, csr_v32;
+    int64_t csr_nnz = 0;
+    bool csr_has[2] = {false, false};  // per precision (0 FP64, 1 FP32)
     std::mutex ws_mu;               // per-stream sigma workspaces of sbd_sigma
     std::map<hipStream_t, std::unique_ptr<sbd::DevBuf>> ws;
 };
@@ -224,6 +245,29 @@ struct SigmaArgs {
     const double* diag;
     double shift;
 };
+
+// Inputs of the explicit assembly (k_csr.hip): the FP64 tables and coefficients.
+struct CsrTables {
+    int64_t na, nb;
+    int norb;
+    const int64_t *a1p, *a2p, *b1p, *b2p;
+    const int32_t *a1J, *a2J, *b1J, *b2J;
+    const double *a1c, *a2c, *b1c, *b2c;
+    const int32_t *a1ps, *b1ps;
+    const uint64_t *a1pack, *b1pack;
+    const double *Ga, *Gb;
+    const double* eri;
+    const double* diag;
+};
+// cnt[I] = stored entries of row I (diagonal included)
+hipError_t launch_csr_count(const CsrTables& t, int64_t* cnt, hipStream_t st);
+// columns and values of every row at rp[I] (v32 nullable)
+hipError_t launch_csr_fill(const CsrTables& t, const int64_t* rp, int32_t* col, double* v64, float* v32,
+                           hipStream_t st);
+// y = (H - shift) x over the CSR; nv interleaved vectors per determinant (1, 2, 4, 8)
+template <class T>
+hipError_t launch_spmv(const int64_t* rp, const int32_t* col, const T* val, int64_t N, int nv, double shift,
+                       const T* x, T* y, hipStream_t st);
 
 // Workspace bytes needed by launch_sigma for nvec vectors of type T.
 size_t sigma_workspace_bytes(int64_t N, int nvec, int layout, size_t elem);

@@ -57,6 +57,10 @@ extern "C" int sbd_autotune(const sbd_basis* b, const sbd_exc* x, sbd_ham* H, in
     if (nvec < 1 || (layout == 1 && nvec != 1 && nvec != 2 && nvec != 4 && nvec != 8) ||
         (layout != 0 && layout != 1))
         return fail(SBD_ERR_ARG, "bad nvec/layout");
+    if (H->csr_has[prec == SBD_FP64 ? 0 : 1]) {  // assembled: the CSR product has nothing to tune
+        if (best_ms) *best_ms = -1.0;
+        return SBD_OK;
+    }
     const Key key{H->na, H->nb, H->norb, prec, nvec, layout};
     {
         std::lock_guard<std::mutex> g(g_mu);

@@ -636,3 +636,94 @@ def test_warm_start_from_smaller_basis(prec):
     idx = np.argsort(-np.abs(u))[:300]
     r = S.sigma_at(u, idx) - (warm_e[0]) * u[idx]
     assert np.linalg.norm(r) <= 1e-7 * 1.01
+
+
+# ------------------------------------------------------------------ f1 explicit (assembled) H
+@pytest.mark.parametrize("name,nstr", CASES)
+def test_assembled_sigma_fp64(name, nstr):
+    """The CSR realization stores exactly the connected pairs the oracle counts
+    and its product is the oracle's sigma; releasing it returns the
+    matrix-free sigma."""
+    W = wl.make_config(name, nstr=nstr)
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    nnz = ham.assemble(3)
+    assert nnz == S.nnz() and ham.assembled() == (nnz, 3)
+    x = wl.random_vector(S.N, 31)[0]
+    ref = S.sigma(x)
+    assert rel(gpu_sigma(ham, x), ref) <= 1e-12
+    shift = float(S.diag().min())
+    assert rel(gpu_sigma(ham, x, shift=shift), ref - shift * x) <= 1e-12
+    ham.release_assembled()
+    assert ham.assembled() == (0, 0)
+    assert rel(gpu_sigma(ham, x), ref) <= 1e-12
+
+
+def test_assembled_matrix_equals_dense_h():
+    """fci8: the assembled product on eight vectors equals the oracle's dense
+    H times them (every stored value and column checked through the product)."""
+    W = wl.make_config("fci8")
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    ham.assemble(1)
+    X = np.random.default_rng(32).standard_normal((8, S.N))
+    Y = gpu_sigma(ham, X.reshape(-1), nvec=8, layout=0).reshape(8, S.N)
+    ref = X @ S.dense_h().T
+    assert np.abs(Y - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_assembled_multivector(layout):
+    W = wl.make_config("sel16", nstr=200)
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    ham.assemble(1)
+    X = wl.random_vector(S.N, 33, nvec=4)
+    Yo = S.sigma(X)
+    if layout == 0:
+        Y = gpu_sigma(ham, X.reshape(-1), nvec=4, layout=0).reshape(4, S.N)
+    else:
+        Y = gpu_sigma(ham, X.T.reshape(-1), nvec=4, layout=1).reshape(S.N, 4).T
+    for v in range(4):
+        assert rel(Y[v], Yo[v]) <= 1e-12
+
+
+def test_assembled_fp32_within_rounding_bound():
+    """FP32 values and accumulation: |y32 - y|_I <= 2 (z_I + 2) u32 (|H - shift| |x|)_I."""
+    W = wl.make_config("fci8")
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    ham.assemble(2)
+    Hs = S.dense_h() - S.diag().min() * np.eye(S.N)
+    x = wl.random_vector(S.N, 34)[0].astype(np.float32).astype(np.float64)
+    y32 = gpu_sigma(ham, x, prec=1, shift=S.diag().min())
+    z = (np.abs(Hs) > 0).sum(axis=1)
+    bound = 2 * (z + 2) * 2.0 ** -24 * (np.abs(Hs) @ np.abs(x))
+    assert np.all(np.abs(y32 - Hs @ x) <= bound)
+
+
+def test_assembled_size_limit_leaves_handle_unchanged():
+    W = wl.make_config("sel16", nstr=150)
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    with pytest.raises(sbd.SBDError):
+        ham.assemble(3, max_bytes=1024)
+    assert ham.assembled() == (0, 0)
+    x = wl.random_vector(S.N, 35)[0]
+    assert rel(gpu_sigma(ham, x), S.sigma(x)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_assembled_davidson_matches_matrix_free(prec):
+    """Davidson through the assembled matrix reaches the matrix-free solve's
+    energies (two roots), and the oracle's dense lowest eigenvalues."""
+    W = wl.make_config("sel16", nstr=60)
+    _, _, ham = from_workload(W)
+    e_free, _, st0 = sbd.davidson(ham, 2, tol_residual=1e-8, sigma_prec=prec)
+    ham.assemble(3)
+    e_asm, rep, st1 = sbd.davidson(ham, 2, tol_residual=1e-8, sigma_prec=prec, use_autotune=1)
+    assert st0 == 0 and st1 == 0
+    assert np.abs(e_asm - e_free).max() <= 1e-9 * np.abs(e_free).max()
+    S = oracle.OracleSystem.from_workload(W)
+    ref, _ = oracle.dense_lowest(S.dense_h(), 2)
+    assert np.abs(e_asm - ref).max() <= 1e-8
