@@ -331,6 +331,67 @@ def sqd_leg(sbd, wl, stream, sequences=(("coarse", (6000, 8000, 10000)), ("fine"
     return out
 
 
+def assembled_leg(sbd, wl, stream, cases=(("sel16", 300), ("sel16", 1000), ("sel16", None))):
+    """Explicit (assembled CSR) against matrix-free realization of H on sel16
+    bases of 9e4, 1e6 and 4e6 determinants: assembly time and size, sigma time
+    per precision with each realization, the CSR product's algorithmic HBM rate
+    (stored entries x (value + 4-byte column) + row pointers + x and y once),
+    and a chosen-form solve with each."""
+    import torch
+
+    out = []
+    for name, nstr in cases:
+        W = wl.make_config(name, nstr=nstr)
+        B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
+        X = sbd.Excitations(B, stream=stream)
+        H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
+        N = W.ndet
+        row = dict(workload=f"{name} ({W.alpha.size} strings per spin)", determinants=N)
+
+        def sig_ms(prec):
+            dt = torch.float64 if prec == sbd.FP64 else torch.float32
+            x = torch.randn(N, device="cuda", dtype=dt)
+            y = torch.empty_like(x)
+            sbd.sigma(H, x, y, prec=prec, shift=-200.0, stream=stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(torch.cuda.current_stream())
+            for _ in range(10):
+                sbd.sigma(H, x, y, prec=prec, shift=-200.0, stream=stream)
+            e1.record(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / 10
+
+        def solve_ms():
+            sbd.davidson(H, 1, stream=stream, tol_residual=1e-6, sigma_prec=sbd.FP32, use_autotune=1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, rep, st = sbd.davidson(H, 1, stream=stream, tol_residual=1e-6, sigma_prec=sbd.FP32, use_autotune=1)
+            torch.cuda.synchronize()
+            return 1e3 * (time.perf_counter() - t0), float(e[0]), rep["iterations"]
+
+        H.autotune(sbd.FP64, stream=stream)
+        H.autotune(sbd.FP32, stream=stream)
+        row["free_sigma_ms"] = {"f64": sig_ms(sbd.FP64), "f32": sig_ms(sbd.FP32)}
+        row["free_solve_ms"], e_free, row["free_iterations"] = solve_ms()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nnz = H.assemble(3, stream=stream)
+        torch.cuda.synchronize()
+        row["assemble_ms"] = 1e3 * (time.perf_counter() - t0)
+        row["stored_entries"] = nnz
+        row["csr_bytes"] = nnz * (4 + 8 + 4) + 8 * (N + 1)
+        row["csr_sigma_ms"] = {"f64": sig_ms(sbd.FP64), "f32": sig_ms(sbd.FP32)}
+        for key, vb in (("f64", 8), ("f32", 4)):
+            bytes_ = nnz * (vb + 4) + 8 * (N + 1) + 2 * vb * N
+            row.setdefault("csr_hbm_TBps", {})[key] = bytes_ / (row["csr_sigma_ms"][key] * 1e-3) / 1e12
+        row["csr_solve_ms"], e_csr, row["csr_iterations"] = solve_ms()
+        row["energy_diff"] = abs(e_csr - e_free)
+        H.release_assembled()
+        out.append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,6 +403,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-block", action="store_true")
     ap.add_argument("--no-sqd", action="store_true")
+    ap.add_argument("--no-assembled", action="store_true")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a few sigma launches and a calibration copy (counter runs)")
     ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
@@ -477,6 +539,12 @@ def main():
             log(f"[bench] sqd loop {name} {q['strings_per_spin']}: cold {q['cold_ms']:.0f} ms "
                 f"{[x['iterations'] for x in q['cold']]} it, warm {q['warm_ms']:.0f} ms "
                 f"{[x['iterations'] for x in q['warm']]} it, energies {[round(x['energy'], 6) for x in q['warm']]}")
+    if not args.no_assembled:
+        extra["assembled"] = assembled_leg(sbd, wl, stream)
+        for r in extra["assembled"]:
+            log(f"[bench] assembled {r['workload']}: N={r['determinants']} entries={r['stored_entries']} "
+                f"assemble {r['assemble_ms']:.1f} ms; sigma free {r['free_sigma_ms']} csr {r['csr_sigma_ms']} "
+                f"({r['csr_hbm_TBps']} TB/s); solve free {r['free_solve_ms']:.1f} csr {r['csr_solve_ms']:.1f} ms")
     if not args.no_serving:
         extra["serving"] = serving(sbd, wl)
         log(f"[bench] serving: {extra['serving']}")
