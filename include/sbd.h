@@ -173,6 +173,8 @@ int sbd_autotune(const sbd_basis* b, const sbd_exc* e, sbd_ham* h, int prec, int
  * streams where the vector width and row alignment allow; stream_split in
  * {1, 2, 4}: ket entries a stream wavefront loads per step, each by 64/split
  * lanes, which narrows the column tile by that factor (needs stream_rw = 1)).
+ * A new handle starts at stream_rw 1, ab_lds_bytes 147456, stream_wide 1,
+ * stream_split 1 (the autotuner's usual pick).
  * Any output pointer of sbd_get_tune may be NULL.  Errors: SBD_ERR_ARG. */
 int sbd_get_tune(const sbd_ham* h, int prec, int* stream_rw, int* ab_lds_bytes, int* stream_wide,
                  int* stream_split);

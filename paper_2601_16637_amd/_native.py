@@ -300,8 +300,8 @@ class Hamiltonian:
         return dict(stream_rw=rw.value, ab_lds_bytes=lds.value, stream_wide=wide.value,
                     stream_split=split.value)
 
-    def set_tune(self, prec: int = FP64, stream_rw: int = 1, ab_lds_bytes: int = 98304,
-                 stream_wide: int = 0, stream_split: int = 1):
+    def set_tune(self, prec: int = FP64, stream_rw: int = 1, ab_lds_bytes: int = 147456,
+                 stream_wide: int = 1, stream_split: int = 1):
         check(load().sbd_set_tune(self._h, int(prec), int(stream_rw), int(ab_lds_bytes),
                                   int(stream_wide), int(stream_split)))
 

@@ -138,10 +138,11 @@ namespace sbd {
 // Launch parameters of the sigma kernels (picked per shape by the autotuner).
 struct SigmaTune {
     int ab_threads = 1024;       // threads per alpha-beta workgroup
-    int ab_lds_bytes = 98304;    // LDS budget for the staged row of the alpha-beta kernel
+    // defaults: the configuration the autotuner picks at most measured shapes
+    int ab_lds_bytes = 147456;   // LDS budget for the staged row of the alpha-beta kernel
     int stream_rows = 4;         // wavefronts per stream workgroup
     int stream_rw = 1;           // output rows per stream wavefront (1 or 2)
-    int stream_wide = 0;         // 1: 16-byte lane loads in the row streams where possible
+    int stream_wide = 1;         // 1: 16-byte lane loads in the row streams where possible
     int stream_split = 1;        // ket entries per load step of a stream wavefront (1, 2, 4)
 };
 
