@@ -653,12 +653,12 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
             refine = inner_conv || err_dominated || overdue;
         }
         if (S.mixed && refine) {
-            // collapse onto the Ritz vectors and recompute their sigma in FP64;
-            // the collapsed mixed sigma (kept in tmp) calibrates rho.  A refresh
-            // that certifies (inner residuals already at the target) keeps only the
-            // k roots: the solve most likely ends with it.
+            // collapse onto the k Ritz vectors of the roots and recompute their
+            // sigma in FP64; the collapsed mixed sigma (kept in tmp) calibrates rho.
+            // Only the roots are kept: further kept vectors would carry FP32 error
+            // bounds as large as those that forced the refresh and force the next.
             auto tr0 = clk::now();
-            const int kk = std::min(inner_conv ? k : S.keep, m);
+            const int kk = std::min(k, m);
             std::vector<double> pred(kk, 0.0);
             for (int c = 0; c < kk; ++c) {
                 double s2 = 0.0;
