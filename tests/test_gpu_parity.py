@@ -727,3 +727,29 @@ def test_assembled_davidson_matches_matrix_free(prec):
     S = oracle.OracleSystem.from_workload(W)
     ref, _ = oracle.dense_lowest(S.dense_h(), 2)
     assert np.abs(e_asm - ref).max() <= 1e-8
+
+
+# ------------------------------------------------------------------ degenerate systems
+@pytest.mark.parametrize("norb,na,nb", [(4, 0, 0), (4, 4, 4), (3, 1, 0), (5, 1, 1), (4, 2, 0), (6, 5, 1)])
+def test_degenerate_tiny_systems(norb, na, nb):
+    """Bases of one determinant or a handful (no electrons, full shells, a
+    single electron, one spin empty): sigma in both precisions and both
+    realizations, and Davidson, against the oracle's dense H."""
+    h, eri, ec = wl.make_integrals(norb, 70 + norb + na + nb)
+    A, B = wl.all_strings(norb, na), wl.all_strings(norb, nb)
+    _, _, ham = gpu_system(norb, na, nb, A, B, h, eri, ec)
+    S = oracle.OracleSystem(norb, A, B, h, eri, ec)
+    Hd = S.dense_h()
+    x = wl.random_vector(S.N, 71)[0]
+    assert rel(gpu_sigma(ham, x), Hd @ x) <= 1e-12
+    x32 = x.astype(np.float32).astype(np.float64)
+    assert rel(gpu_sigma(ham, x32, prec=1, shift=0.0), Hd @ x32) <= 1e-5
+    nroots = min(2, S.N)
+    ref, _ = oracle.dense_lowest(Hd, nroots)
+    for prec in (0, 1):
+        e, rep, st = sbd.davidson(ham, nroots, tol_residual=1e-8, sigma_prec=prec)
+        assert st == 0 and np.abs(e - ref).max() <= 1e-8, (prec, e, ref)
+    ham.assemble(3)
+    assert rel(gpu_sigma(ham, x), Hd @ x) <= 1e-12
+    e, rep, st = sbd.davidson(ham, nroots, tol_residual=1e-8)
+    assert st == 0 and np.abs(e - ref).max() <= 1e-8
