@@ -721,7 +721,84 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
             h1_valid = false;
         }
         const int m_old = m;
-        for (int r = 0; r < k; ++r) {
+        // Block Gram-Schmidt (the block variant of Sec. II-C) when every root adds a
+        // correction: one sweep subtracts V H from all k corrections and sums their
+        // Gram matrix G (a second sweep when a column kept less than 1/sqrt(2) of
+        // its norm), G = R^T R by Cholesky, the new basis vectors are T' R^-1 (one
+        // combination), and T's new columns come from one projection of T' on W.
+        // A nearly dependent block (a Cholesky pivot below 1 % of its column's
+        // norm) falls back to the one-root-at-a-time path below.
+        bool block_done = false;
+        if (k >= 2 && nnew == k && m >= 1 && pass_subb_fits(m, k)) {
+            std::vector<double> Hm((size_t)m * k);
+            if (h1_valid) {
+                for (int j = 0; j < m; ++j)
+                    for (int q = 0; q < k; ++q) Hm[j * k + q] = red[2 * k + j * k + q];
+            } else {
+                rc = S.project(S.V.as<double>(), m, tmp, k, Hm);
+                if (rc) return rc;
+            }
+            std::vector<double> G((size_t)k * k);
+            for (int pass = 0; pass < 2; ++pass) {
+                SBD_HIP(hipMemcpyAsync(sm + kY, Hm.data(), sizeof(double) * m * k, hipMemcpyHostToDevice, st));
+                SBD_HIP(pass_subb(S.V.as<double>(), m, sm + kY, tmp, k, N, part, sm + kProj, st));
+                SBD_HIP(hipMemcpyAsync(G.data(), sm + kProj, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
+                SBD_HIP(hipStreamSynchronize(st));
+                if (pass == 1) break;
+                bool again = false;  // a column kept less than 1/sqrt(2) of its norm
+                for (int q = 0; q < k; ++q)
+                    if (!(G[q * k + q] >= kReorth * kReorth * tnorm[q] * tnorm[q])) again = true;
+                if (!again) break;
+                ++S.reorth;  // second sweep with H = V^T T'
+                rc = S.project(S.V.as<double>(), m, tmp, k, Hm);
+                if (rc) return rc;
+            }
+            // Cholesky G = R^T R (R upper), with relative pivots of at least 1e-4
+            std::vector<double> R((size_t)k * k, 0.0);
+            bool ok = true;
+            for (int i = 0; i < k && ok; ++i) {
+                double d = G[i * k + i];
+                for (int p = 0; p < i; ++p) d -= R[p * k + i] * R[p * k + i];
+                if (!std::isfinite(d) || !(d > 1e-4 * G[i * k + i]) || !(G[i * k + i] > 0.0)) {
+                    ok = false;
+                    break;
+                }
+                R[i * k + i] = std::sqrt(d);
+                for (int j = i + 1; j < k; ++j) {
+                    double e = G[i * k + j];
+                    for (int p = 0; p < i; ++p) e -= R[p * k + i] * R[p * k + j];
+                    R[i * k + j] = e / R[i * k + i];
+                }
+            }
+            if (ok) {
+                // Rinv = R^-1 (upper triangular), by back substitution column by column
+                std::vector<double> Ri((size_t)k * k, 0.0);
+                for (int c = 0; c < k; ++c) {
+                    Ri[c * k + c] = 1.0 / R[c * k + c];
+                    for (int i = c - 1; i >= 0; --i) {
+                        double e = 0.0;
+                        for (int p = i + 1; p <= c; ++p) e += R[i * k + p] * Ri[p * k + c];
+                        Ri[i * k + c] = -e / R[i * k + i];
+                    }
+                }
+                SBD_HIP(hipMemcpyAsync(sm + kYc, Ri.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, st));
+                SBD_HIP(launch_combination(tmp, k, sm + kYc, k, k, S.Vr(m), N, st));
+                std::vector<double> P;
+                rc = S.project(S.W.as<double>(), m, tmp, k, P);  // W^T T'
+                if (rc) return rc;
+                for (int j = 0; j < m; ++j)
+                    for (int q = 0; q < k; ++q) {
+                        double u = 0.0;
+                        for (int p = 0; p <= q; ++p) u += P[j * k + p] * Ri[p * k + q];
+                        T[j * ms + m + q] = T[(m + q) * ms + j] = u;
+                    }
+                m += k;
+                block_done = true;
+            } else {
+                h1_valid = false;  // the corrections in tmp are now T': project them afresh
+            }
+        }
+        for (int r = 0; r < k && !block_done; ++r) {
             if (rnorm[r] <= o.tol_residual) continue;
             double* t = tmp + (size_t)r * N;
             if (h1_valid && m == m_old) {

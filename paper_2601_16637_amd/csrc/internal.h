@@ -329,6 +329,11 @@ bool pass_resid_w_fits(int m, int k);
 hipError_t pass_resid_w(const double* V, const double* W, int m, int k, const double* Y,
                         const double* theta, const double* diag, double delta, double* T, int64_t N,
                         double* part, double* out, hipStream_t st);
+// T_q <- T_q - sum_j V_j H[j*k + q] for q < k (in place), rows [q1*k + q2) = T_q1 . T_q2;
+// available when pass_subb_fits(m, k)
+bool pass_subb_fits(int m, int k);
+hipError_t pass_subb(const double* V, int m, const double* H, double* T, int k, int64_t N, double* part,
+                     double* out, hipStream_t st);
 // dst <- (t - V h) * s, and dst32 <- (float)dst when dst32 is not null; no sums
 // (dst must not alias V)
 hipError_t pass_subs(const double* V, int m, const double* h, const double* t, double s, double* dst,

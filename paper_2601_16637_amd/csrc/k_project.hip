@@ -24,7 +24,9 @@
 // without it and a separate projection pass fills the same rows.  RESIDW is
 // RESID that also projects every correction on W (rows [2k + m*k + j*k + q)),
 // so that a Gram-Schmidt step that needs one pass can take the new column of
-// V^T W from these sums; SUBS is the subtraction (t - V h) * s with no sums.
+// V^T W from these sums; SUBS is the subtraction (t - V h) * s with no sums;
+// SUBB subtracts V H from k vectors at once and sums their k x k Gram matrix
+// (rows [q1*k + q2)), the first step of a block Gram-Schmidt.
 #include <algorithm>
 
 #include "internal.h"
@@ -35,7 +37,7 @@ namespace {
 constexpr int kTB = 256;       // threads per block
 constexpr int kMaxOut = 8;     // output vectors per pass
 
-enum Mode { RESID = 0, SUB1 = 1, SUB2 = 2, PROJ = 3, SUBW = 4, RESIDW = 5, SUBS = 6 };
+enum Mode { RESID = 0, SUB1 = 1, SUB2 = 2, PROJ = 3, SUBW = 4, RESIDW = 5, SUBS = 6, SUBB = 7 };
 
 struct PassArgs {
     int64_t N;
@@ -77,16 +79,29 @@ template <int MODE, int MB, int KO, bool PRJ>
 __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
     constexpr int EPT = ept_for(MB);
     constexpr bool RES = MODE == RESID || MODE == RESIDW;
-    constexpr int NAJ = PRJ ? ((MODE == SUBW || MODE == RESIDW) ? 2 * MB : MB) : 1;  // accumulator rows
-    constexpr int NAQ = (RES || MODE == PROJ) ? KO : 1;
+    constexpr int NAJ = MODE == SUBB ? KO : (PRJ ? ((MODE == SUBW || MODE == RESIDW) ? 2 * MB : MB) : 1);
+    constexpr int NAQ = (RES || MODE == PROJ || MODE == SUBB) ? KO : 1;  // accumulator columns
     __shared__ double red[4][MODE == SUBW ? 1 + 2 * MB
                              : MODE == SUBS ? 1
                              : MODE == RESIDW ? 2 * kMaxOut + 2 * MB * KO
+                             : MODE == SUBB ? KO * KO
                                               : 2 * kMaxOut + MB * KO];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = A.m, k = A.k, mp = A.mp;
     const int64_t N = A.N;
     const double* __restrict__ cf = A.coef;
+    // multi-root residual passes read their m x k coefficients from LDS (broadcast
+    // reads), which keeps them out of the scalar registers, and load every row
+    // without a branch (rows past m load row m-1, a cache hit; their terms are
+    // dropped by selects, never multiplied in): with k > 1 the scalar registers
+    // cannot hold the coefficients and branch-guarded loads serialise.  With one
+    // root the guarded form measures faster.
+    constexpr bool STAGED = RES && KO > 1;
+    __shared__ double ys[STAGED ? MB * KO : 1];
+    if constexpr (STAGED) {
+        for (int i = threadIdx.x; i < m * k; i += kTB) ys[i] = cf[i];
+        __syncthreads();
+    }
 
     double acc[NAJ][NAQ];
 #pragma unroll
@@ -112,14 +127,22 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
         if constexpr (RES) {
             double v[MB][EPT], w[MB][EPT], d[EPT];
 #pragma unroll
-            for (int j = 0; j < MB; ++j)
-                if (j < m) {
+            for (int j = 0; j < MB; ++j) {
+                if constexpr (STAGED) {
+                    const size_t jr = (size_t)(j < m ? j : m - 1);
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) {
+                        v[j][u] = in[u] ? A.V[jr * N + ix[u]] : 0.0;
+                        w[j][u] = in[u] ? A.W[jr * N + ix[u]] : 0.0;
+                    }
+                } else if (j < m) {
 #pragma unroll
                     for (int u = 0; u < EPT; ++u) {
                         v[j][u] = in[u] ? A.V[(size_t)j * N + ix[u]] : 0.0;
                         w[j][u] = in[u] ? A.W[(size_t)j * N + ix[u]] : 0.0;
                     }
                 }
+            }
 #pragma unroll
             for (int u = 0; u < EPT; ++u) d[u] = in[u] ? A.diag[ix[u]] : 0.0;
 #pragma unroll
@@ -129,11 +152,16 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
                 for (int u = 0; u < EPT; ++u) {
                     double vy = 0.0, wy = 0.0;
 #pragma unroll
-                    for (int j = 0; j < MB; ++j)
-                        if (j < m) {
+                    for (int j = 0; j < MB; ++j) {
+                        if constexpr (STAGED) {
+                            const double c = ys[(j < m ? j : 0) * k + q];
+                            vy += j < m ? v[j][u] * c : 0.0;
+                            wy += j < m ? w[j][u] * c : 0.0;
+                        } else if (j < m) {
                             vy += v[j][u] * cf[j * k + q];
                             wy += w[j][u] * cf[j * k + q];
                         }
+                    }
                     const double r = wy - th[q] * vy;
                     const double t = in[u] ? r * damped_inv(d[u] - th[q], A.delta) : 0.0;
                     if (in[u]) A.out[(size_t)q * N + ix[u]] = t;
@@ -151,6 +179,42 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
                     }
                 }
                 }
+            }
+        } else if constexpr (MODE == SUBB) {
+            // t'_q = t_q - sum_j V_j H[j][q] for q < k (in place allowed), Gram t'^T t'
+            double v[MB][EPT], x[KO][EPT];
+#pragma unroll
+            for (int q = 0; q < KO; ++q)
+                if (q < k) {
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) x[q][u] = in[u] ? A.X[(size_t)q * N + ix[u]] : 0.0;
+                }
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+                if (j < m) {
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) v[j][u] = in[u] ? A.V[(size_t)j * N + ix[u]] : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                double o[KO];
+#pragma unroll
+                for (int q = 0; q < KO; ++q) {
+                    o[q] = 0.0;
+                    if (q < k) {
+                        double sv = 0.0;
+#pragma unroll
+                        for (int j = 0; j < MB; ++j)
+                            if (j < m) sv += v[j][u] * cf[j * k + q];
+                        o[q] = in[u] ? x[q][u] - sv : 0.0;
+                        if (in[u]) A.out[(size_t)q * N + ix[u]] = o[q];
+                    }
+                }
+#pragma unroll
+                for (int q1 = 0; q1 < KO; ++q1)
+#pragma unroll
+                    for (int q2 = 0; q2 < KO; ++q2)
+                        if (q1 < k && q2 < k) acc[q1][q2] += o[q1] * o[q2];
             }
         } else if constexpr (MODE == SUBS) {
             double v[MB][EPT], x[EPT];
@@ -271,8 +335,8 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
 
     // ---- block reduction: wavefront shuffles, then the four wavefronts in order
     if constexpr (MODE == SUBS) return;  // no sums
-    const int NR = RES ? 2 * k : ((MODE == PROJ) ? 0 : 1);
-    const int kq = (RES || MODE == PROJ) ? k : 1;
+    const int NR = RES ? 2 * k : ((MODE == PROJ || MODE == SUBB) ? 0 : 1);
+    const int kq = (RES || MODE == PROJ || MODE == SUBB) ? k : 1;
 #pragma unroll
     for (int q = 0; q < 2 * KO; ++q) {
         const double x = wave_sum(nrm[q]);
@@ -283,7 +347,15 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
             if ((MODE == SUB1 || MODE == SUB2 || MODE == SUBW) && q == 0) red[wv][0] = x;
         }
     }
-    if constexpr (MODE == SUBW) {
+    if constexpr (MODE == SUBB) {
+#pragma unroll
+        for (int q1 = 0; q1 < KO; ++q1)
+#pragma unroll
+            for (int q2 = 0; q2 < KO; ++q2) {
+                const double x = wave_sum(acc[q1][q2]);
+                if (lane == 0 && q1 < k && q2 < k) red[wv][q1 * k + q2] = x;
+            }
+    } else if constexpr (MODE == SUBW) {
         // rows [1 + j) V_j . t' (j < m), then [1 + m + j) W_j . t' (j < mw)
 #pragma unroll
         for (int j = 0; j < MB; ++j) {
@@ -304,8 +376,9 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
             }
     }
     __syncthreads();
-    const int rows = (MODE == SUBW) ? 1 + m + A.mw
-                                    : NR + (PRJ ? (MODE == RESIDW ? 2 : 1) * mp * kq : 0);
+    const int rows = (MODE == SUBW)   ? 1 + m + A.mw
+                     : (MODE == SUBB) ? k * k
+                                      : NR + (PRJ ? (MODE == RESIDW ? 2 : 1) * mp * kq : 0);
     for (int r = tid; r < rows; r += kTB)
         A.part[(size_t)r * gridDim.x + blockIdx.x] = ((red[0][r] + red[1][r]) + red[2][r]) + red[3][r];
 }
@@ -368,6 +441,7 @@ constexpr int held(int mode, int mb, int ko, bool prj) {
            ((mode == RESID)  ? 2 * mb + (prj ? mb * ko : 0)
             : (mode == RESIDW) ? 2 * mb + 2 * mb * ko
             : (mode == SUBS)   ? mb + 1
+            : (mode == SUBB)   ? mb + ko + ko * ko
             : (mode == SUB1) ? mb + (prj ? mb : 0)
             : (mode == SUB2) ? mb + (prj ? 2 * mb : 0)
             : (mode == SUBW) ? 4 * mb
@@ -380,6 +454,7 @@ constexpr bool exists(int mode, int mb, int ko, bool prj) {
     return mode == SUBW                                 ? ko == 1 && prj && held(mode, mb, 1, true) <= kRegBudget
            : mode == RESIDW                          ? prj && held(mode, mb, ko, true) <= kRegBudget
            : mode == SUBS                            ? ko == 1 && !prj
+           : mode == SUBB                            ? prj && held(mode, mb, ko, true) <= kRegBudget
            : (mode == SUB1 || mode == SUB2) && ko != 1 ? false
            : prj                                    ? held(mode, mb, ko, true) <= kRegBudget
            : mode == PROJ                           ? false
@@ -450,7 +525,7 @@ hipError_t run_pass(int mode, const PassArgs& A, int rows, double* out, hipStrea
     const bool prj = A.mp > 0;
     const int need = std::max({mode == PROJ ? 0 : A.m, A.mp, mode == SUBW ? A.mw : 0});
     const int mb = mb_for(need < 1 ? 1 : need);
-    const int ko = (mode == RESID || mode == RESIDW || mode == PROJ) ? ko_for(A.k) : 1;
+    const int ko = (mode == RESID || mode == RESIDW || mode == PROJ || mode == SUBB) ? ko_for(A.k) : 1;
     if (mb < 0 || ko < 0 || rows > kPassRows) return hipErrorInvalidValue;
     if (mode == SUBW && !fits(SUBW, need, 1, true)) return hipErrorInvalidValue;
     unsigned nb = 0;
@@ -458,6 +533,7 @@ hipError_t run_pass(int mode, const PassArgs& A, int rows, double* out, hipStrea
     if (mode == RESID) e = prj ? by_ko<RESID, true>(ko, mb, A, &nb, st) : by_ko<RESID, false>(ko, mb, A, &nb, st);
     else if (mode == RESIDW) e = by_ko<RESIDW, true>(ko, mb, A, &nb, st);
     else if (mode == SUBS) e = by_mb<SUBS, 1, false>(mb, A, &nb, st);
+    else if (mode == SUBB) e = by_ko<SUBB, true>(ko, mb, A, &nb, st);
     else if (mode == SUB1) e = prj ? by_mb<SUB1, 1, true>(mb, A, &nb, st) : by_mb<SUB1, 1, false>(mb, A, &nb, st);
     else if (mode == SUB2) e = prj ? by_mb<SUB2, 1, true>(mb, A, &nb, st) : by_mb<SUB2, 1, false>(mb, A, &nb, st);
     else if (mode == SUBW) e = by_mb<SUBW, 1, true>(mb, A, &nb, st);
@@ -534,6 +610,17 @@ hipError_t pass_resid_w(const double* V, const double* W, int m, int k, const do
     A.V = V; A.W = W; A.P = V; A.out = T; A.coef = Y; A.theta = theta; A.diag = diag;
     A.delta = delta; A.part = part;
     return run_pass(RESIDW, A, 2 * k + 2 * m * k, out, st);
+}
+
+bool pass_subb_fits(int m, int k) { return m >= 1 && k >= 1 && k <= kMaxOut && fits(SUBB, m, k, true); }
+
+hipError_t pass_subb(const double* V, int m, const double* H, double* T, int k, int64_t N, double* part,
+                     double* out, hipStream_t st) {
+    if (!pass_subb_fits(m, k)) return hipErrorInvalidValue;
+    PassArgs A{};
+    A.N = N; A.m = m; A.k = k; A.mp = m;
+    A.V = V; A.X = T; A.out = T; A.coef = H; A.part = part;
+    return run_pass(SUBB, A, k * k, out, st);
 }
 
 hipError_t pass_subs(const double* V, int m, const double* h, const double* t, double s, double* dst,
