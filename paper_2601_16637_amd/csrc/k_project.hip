@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
     // dropped by selects, never multiplied in): with k > 1 the scalar registers
     // cannot hold the coefficients and branch-guarded loads serialise.  With one
     // root the guarded form measures faster.
-    constexpr bool STAGED = RES && KO > 1;
+    constexpr bool STAGED = (RES || MODE == SUBB) && KO > 1;
     __shared__ double ys[STAGED ? MB * KO : 1];
     if constexpr (STAGED) {
         for (int i = threadIdx.x; i < m * k; i += kTB) ys[i] = cf[i];
@@ -181,20 +181,21 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
                 }
             }
         } else if constexpr (MODE == SUBB) {
-            // t'_q = t_q - sum_j V_j H[j][q] for q < k (in place allowed), Gram t'^T t'
+            // t'_q = t_q - sum_j V_j H[j][q] for q < k (in place allowed), Gram t'^T t';
+            // rows loaded without branches as in the staged residual pass
             double v[MB][EPT], x[KO][EPT];
 #pragma unroll
-            for (int q = 0; q < KO; ++q)
-                if (q < k) {
+            for (int q = 0; q < KO; ++q) {
+                const size_t qr = (size_t)(q < k ? q : k - 1);
 #pragma unroll
-                    for (int u = 0; u < EPT; ++u) x[q][u] = in[u] ? A.X[(size_t)q * N + ix[u]] : 0.0;
-                }
+                for (int u = 0; u < EPT; ++u) x[q][u] = in[u] ? A.X[qr * N + ix[u]] : 0.0;
+            }
 #pragma unroll
-            for (int j = 0; j < MB; ++j)
-                if (j < m) {
+            for (int j = 0; j < MB; ++j) {
+                const size_t jr = (size_t)(j < m ? j : m - 1);
 #pragma unroll
-                    for (int u = 0; u < EPT; ++u) v[j][u] = in[u] ? A.V[(size_t)j * N + ix[u]] : 0.0;
-                }
+                for (int u = 0; u < EPT; ++u) v[j][u] = in[u] ? A.V[jr * N + ix[u]] : 0.0;
+            }
 #pragma unroll
             for (int u = 0; u < EPT; ++u) {
                 double o[KO];
@@ -204,8 +205,10 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
                     if (q < k) {
                         double sv = 0.0;
 #pragma unroll
-                        for (int j = 0; j < MB; ++j)
-                            if (j < m) sv += v[j][u] * cf[j * k + q];
+                        for (int j = 0; j < MB; ++j) {
+                            const double c = STAGED ? ys[(j < m ? j : 0) * k + q] : cf[(j < m ? j : 0) * k + q];
+                            sv += j < m ? v[j][u] * c : 0.0;
+                        }
                         o[q] = in[u] ? x[q][u] - sv : 0.0;
                         if (in[u]) A.out[(size_t)q * N + ix[u]] = o[q];
                     }
@@ -307,19 +310,31 @@ __global__ void __launch_bounds__(kTB) k_pass(PassArgs A) {
                 }
             }
         } else {  // PROJ
+            // with several vectors, rows loaded without branches (past the end: the
+            // last row again, a cache hit; those sums are never stored)
             double p[MB][EPT], x[KO][EPT];
 #pragma unroll
-            for (int q = 0; q < KO; ++q)
-                if (q < k) {
+            for (int q = 0; q < KO; ++q) {
+                if constexpr (KO > 1) {
+                    const size_t qr = (size_t)(q < k ? q : k - 1);
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) x[q][u] = in[u] ? A.X[qr * N + ix[u]] : 0.0;
+                } else if (q < k) {
 #pragma unroll
                     for (int u = 0; u < EPT; ++u) x[q][u] = in[u] ? A.X[(size_t)q * N + ix[u]] : 0.0;
                 }
+            }
 #pragma unroll
-            for (int j = 0; j < MB; ++j)
-                if (j < mp) {
+            for (int j = 0; j < MB; ++j) {
+                if constexpr (KO > 1) {
+                    const size_t jr = (size_t)(j < mp ? j : mp - 1);
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) p[j][u] = in[u] ? A.P[jr * N + ix[u]] : 0.0;
+                } else if (j < mp) {
 #pragma unroll
                     for (int u = 0; u < EPT; ++u) p[j][u] = in[u] ? A.P[(size_t)j * N + ix[u]] : 0.0;
                 }
+            }
 #pragma unroll
             for (int j = 0; j < MB; ++j)
                 if (j < mp) {
