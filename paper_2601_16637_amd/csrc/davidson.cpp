@@ -167,6 +167,7 @@ struct Solver {
     DevBuf rowsel;           // device int: basis row of the sigma being replayed
     int staged_row = -1;     // basis row whose FP32 copy already sits in x32 (eager path)
     int dot_row = -1;        // basis row whose v . w the last restore left at sm + kDot
+    double dot_value = 0.0;  // that v . w, read back by apply_sigma
 
     ~Solver() {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
@@ -313,7 +314,11 @@ struct Solver {
         staged_row = -1;  // a pre-staged copy serves only the sigma that follows it
         if (p64) sigma64 += cnt;
         sigma_calls += cnt;
-        hipError_t e = hipStreamSynchronize(st);
+        // a single vector's restore left v . w on the device: bring it back with
+        // the same synchronisation
+        hipError_t e = hipSuccess;
+        if (cnt == 1 && dot_row == j0) e = hipMemcpyAsync(&dot_value, sm + kDot, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "sigma");
         t_sigma += ms_since(t0);
         return SBD_OK;
@@ -862,9 +867,7 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
             const int nn = m - m_old;
             std::vector<double> g;
             if (nn == 1 && S.dot_row == m_old) {
-                g.assign(1, 0.0);
-                SBD_HIP(hipMemcpyAsync(g.data(), sm + kDot, sizeof(double), hipMemcpyDeviceToHost, st));
-                SBD_HIP(hipStreamSynchronize(st));
+                g.assign(1, S.dot_value);
             } else {
                 rc = S.project(S.Vr(m_old), nn, S.Wr(m_old), nn, g);
             }
