@@ -753,3 +753,20 @@ def test_degenerate_tiny_systems(norb, na, nb):
     assert rel(gpu_sigma(ham, x), Hd @ x) <= 1e-12
     e, rep, st = sbd.davidson(ham, nroots, tol_residual=1e-8)
     assert st == 0 and np.abs(e - ref).max() <= 1e-8
+
+
+def test_assembled_sigma_timed_reports_the_product():
+    """sbd_sigma_timed on an assembled handle: the CSR product is reported as
+    the alpha-stream stage and the other stages are empty; the result is the
+    oracle's sigma."""
+    W = wl.make_config("sel16", nstr=150)
+    _, _, ham = from_workload(W)
+    S = oracle.OracleSystem.from_workload(W)
+    ham.assemble(1)
+    x = wl.random_vector(S.N, 36)[0]
+    xd = dev(x)
+    yd = torch.empty_like(xd)
+    st = sbd.sigma_timed(ham, xd, yd)
+    assert rel(yd.cpu().numpy(), S.sigma(x)) <= 1e-12
+    assert st["alpha_stream"] > 0.0
+    assert all(v <= 0.05 for k, v in st.items() if k != "alpha_stream"), st
