@@ -758,13 +758,16 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
                 rc = S.project(S.V.as<double>(), m, tmp, k, Hm);
                 if (rc) return rc;
             }
-            // Cholesky G = R^T R (R upper), with relative pivots of at least 1e-4
+            // Cholesky G = R^T R (R upper), with relative pivots of at least 1e-4; a
+            // column left with less than 1e-12 of its norm before the sweeps is noise
+            // (the one-root path drops such a vector)
             std::vector<double> R((size_t)k * k, 0.0);
             bool ok = true;
             for (int i = 0; i < k && ok; ++i) {
                 double d = G[i * k + i];
                 for (int p = 0; p < i; ++p) d -= R[p * k + i] * R[p * k + i];
-                if (!std::isfinite(d) || !(d > 1e-4 * G[i * k + i]) || !(G[i * k + i] > 0.0)) {
+                if (!std::isfinite(d) || !(d > 1e-4 * G[i * k + i]) ||
+                    !(G[i * k + i] > 1e-24 * tnorm[i] * tnorm[i])) {
                     ok = false;
                     break;
                 }
