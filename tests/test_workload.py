@@ -45,3 +45,18 @@ def test_sampling_prefers_low_levels():
     lv = wl._level(s, n)
     frac = [np.mean(lv == k) / (math.comb(n, k) * math.comb(norb - n, k)) for k in (1, 3)]
     assert frac[0] > 2 * frac[1]
+
+
+def test_string_sets_nested_across_sizes():
+    """Where all C(norb, n) strings can be enumerated (weighted sampling keys),
+    the same seed draws smaller string sets as subsets of larger ones: the
+    successive-solve benchmark grows a sel26 basis this way.  (The rejection
+    regime for larger spaces draws in batches sized by the count, so it makes
+    no such promise.)"""
+    for norb, n, sizes in ((26, 7, (600, 900, 1500)), (16, 8, (300, 700, 2000))):
+        sets = [wl.sample_strings(norb, n, k, 3001) for k in sizes]
+        for small, big in zip(sets, sets[1:]):
+            assert np.isin(small, big).all()
+    a = wl.make_config("sel26", nstr=6000).alpha
+    b = wl.make_config("sel26", nstr=8000).alpha
+    assert np.isin(a, b).all()
