@@ -1,14 +1,17 @@
-"""Benchmark: selected-basis Davidson solve on one MI355X.
+"""Benchmark: the sigma = H c product and the Davidson solve on one MI355X.
 
-One step = one whole solve of the hot path on a synthetic workload: basis
-build (sort/dedupe), excitation tables, Hamiltonian set-up (diagonal and
-coefficients), and the Davidson iteration to ||r|| <= 1e-6 in the chosen form
-(FP32 sigma with FP64 Gram-Schmidt / Rayleigh-Ritz / residuals and FP64
-refinement).  ``value`` is whole-job throughput: determinants solved per
-second (N x steps / wall time).  Also reported: sigma determinants/s per
-precision, the plain-FP64 solve of the same workload, time to 1e-6 Ha for
-both, the dominant kernel's roofline, the CPU oracle's sigma rate, and the
-serving stream (continuous batching of 256 solves, p50/p99 latency).
+One step = one sigma = H c in FP64 (the paper's `mult`: all five launches,
+alpha-alpha, beta-beta and alpha-beta terms with the diagonal) on one vector of
+the sel26 workload (N = 1e8 determinants), with the tables, Hamiltonian and
+vector resident in device memory.  ``value`` = N x steps / wall time of the
+timed steps (determinants/s, FP64).  Alongside, on the same workload: the FP32
+sigma, per-stage times and the roofline report of each precision; the whole
+Davidson solve to ||r|| <= 1e-6 in plain FP64 and in the chosen form (FP32
+sigma with FP64 Gram-Schmidt / Rayleigh-Ritz / residuals and refinement),
+repeated the same number of times, with per-solve phase splits and the time
+to 1e-6 Ha of a tight FP64 reference energy; sigma rows of the sel16 and
+block20 workloads; the block, successive-solve, explicit-realization and
+serving legs; and the CPU oracle's sigma rate.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sel26]
 """
@@ -71,50 +74,28 @@ def time_to(hist_theta, hist_time, e_ref, tol=1e-6):
     return None
 
 
-def sigma_stages(sbd, H, N, prec, stream, reps=10):
-    """Mean per-stage milliseconds of sigma over reps launches (HIP events)."""
-    import torch
-    dt = torch.float64 if prec == sbd.FP64 else torch.float32
-    x = torch.randn(N, device="cuda", dtype=dt)
-    y = torch.empty_like(x)
-    for _ in range(2):
-        sbd.sigma(H, x, y, prec=prec, shift=-200.0, stream=stream)
-    acc = None
-    for _ in range(reps):
-        st = sbd.sigma_timed(H, x, y, prec=prec, shift=-200.0, stream=stream)
-        acc = st if acc is None else {k: acc[k] + st[k] for k in st}
-    return {k: v / reps for k, v in acc.items()}
-
-
-def stream_kernel_name(tune):
-    """Instantiation of the FP32 single-vector row stream that a tune selects
-    (columns per lane: 2, or 4 with 16-byte loads; output rows per wavefront,
-    or ket entries per load step in the ket-split form)."""
-    vec = 4 if tune['stream_wide'] else 2
-    if tune.get('stream_split', 1) > 1:
-        return f"k_stream_ks<float,1,{vec},{tune['stream_split']}>"
-    return f"k_stream<float,1,{vec},{tune['stream_rw']}>"
-
-
-def kernel_only(sbd, W, stream):
-    """Short run for hardware-counter passes: five FP32 sigma launches and one
-    device copy of known size (2 * N * 4 bytes) used to calibrate the counters."""
+def kernel_only(sbd, W, stream, prec):
+    """Short run for hardware-counter passes: five sigma launches in precision
+    `prec` after autotuning, then one device copy of known size (N elements of
+    that precision read and written) that calibrates the counters."""
     import torch
     B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
     X = sbd.Excitations(B, stream=stream)
     H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
-    H.autotune(sbd.FP32, stream=stream)
-    x = torch.randn(W.ndet, device="cuda", dtype=torch.float32)
+    H.autotune(prec, stream=stream)
+    dt = torch.float64 if prec == sbd.FP64 else torch.float32
+    w = 8 if prec == sbd.FP64 else 4
+    x = torch.randn(W.ndet, device="cuda", dtype=dt)
     y = torch.empty_like(x)
     for _ in range(5):
-        sbd.sigma(H, x, y, prec=sbd.FP32, shift=-200.0, stream=stream)
+        sbd.sigma(H, x, y, prec=prec, shift=-200.0, stream=stream)
     z = torch.empty_like(x)
     z.copy_(x)
     torch.cuda.synchronize()
-    tune = H.get_tune(sbd.FP32)
-    print(json.dumps(dict(kernel_only=True, workload=W.name, ndet=W.ndet,
-                          copy_bytes_read=4 * W.ndet, copy_bytes_written=4 * W.ndet,
-                          tune=tune, stream_kernel=stream_kernel_name(tune))))
+    tune = H.get_tune(prec)
+    print(json.dumps(dict(kernel_only=True, workload=W.name, ndet=W.ndet, precision=prec,
+                          copy_bytes_read=w * W.ndet, copy_bytes_written=w * W.ndet,
+                          tune=tune, stream_kernel=stream_kernel(tune, prec))))
 
 
 def cpu_baseline(W, target_s=15.0):
@@ -140,9 +121,13 @@ def cpu_baseline(W, target_s=15.0):
 def serving(sbd, wl, nreq=256, budget=96 << 30, inflight=16):
     """Serving stream: Poisson arrivals at 20/s of solves with 1e4-2e7
     determinants (norb 12-32, 1-2 roots, FP32 sigma + FP64 refinement);
-    each request is generated at its arrival time and submitted then."""
+    each request is generated at its arrival time and submitted then.
+    Latency percentiles are also reported per size class, and the largest
+    request is solved again alone on the idle server to split its latency
+    into its own run time and the cost of sharing the device."""
     descs = wl.serving_stream(nreq=nreq)
     srv = sbd.Server(budget, inflight)
+    kw = dict(sigma_prec=sbd.FP32, tol_residual=1e-6, max_space=20)
     t0 = time.perf_counter()
     tickets = []
     for d in descs:
@@ -151,18 +136,32 @@ def serving(sbd, wl, nreq=256, budget=96 << 30, inflight=16):
         if delay > 0:
             time.sleep(delay)
         tickets.append((W, srv.submit(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, W.h, W.eri,
-                                      W.e_core, W.nroots, sigma_prec=sbd.FP32, tol_residual=1e-6,
-                                      max_space=20)))
+                                      W.e_core, W.nroots, **kw)))
         if len(tickets) % 64 == 0:
             log(f"[bench] serving: {len(tickets)} requests submitted")
     res = [(W, srv.wait(t)) for W, t in tickets]
     wall = time.perf_counter() - t0
-    srv.close()
     bad = [r for _, r in res if r["status"] < 0]
     lat = np.array([r["latency_ms"] for _, r in res])
     dets = sum(r["ndet"] for _, r in res)
     apps = sum(r["ndet"] * r["report"]["sigma_calls"] for _, r in res)
     conv = sum(1 for _, r in res if r["report"]["converged"])
+    classes = {}
+    for cname, lo, hi in (("small_lt_1e5", 0, 1e5), ("medium_1e5_to_2e6", 1e5, 2e6), ("large_ge_2e6", 2e6, 1e30)):
+        sel = [r for _, r in res if lo <= r["ndet"] < hi]
+        if not sel:
+            continue
+        l = np.array([r["latency_ms"] for r in sel])
+        q = np.array([r["queue_ms"] for r in sel])
+        u = np.array([r["run_ms"] for r in sel])
+        classes[cname] = dict(requests=len(sel), latency_p50_ms=float(np.percentile(l, 50)),
+                              latency_p99_ms=float(np.percentile(l, 99)),
+                              queue_p99_ms=float(np.percentile(q, 99)), run_p50_ms=float(np.percentile(u, 50)))
+    # the largest request again, alone on the idle server
+    Wl, rl = max(res, key=lambda p: p[1]["ndet"])
+    alone = srv.wait(srv.submit(Wl.norb, Wl.n_alpha, Wl.n_beta, Wl.alpha, Wl.beta, Wl.h, Wl.eri,
+                                Wl.e_core, Wl.nroots, **kw))
+    srv.close()
     return dict(requests=nreq, rate_per_s=20.0, budget_bytes=budget, max_inflight=inflight,
                 hw_queues=int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
                 failed=len(bad), converged=conv, wall_s=wall,
@@ -170,7 +169,12 @@ def serving(sbd, wl, nreq=256, budget=96 << 30, inflight=16):
                 latency_p99_ms=float(np.percentile(lat, 99)),
                 queue_p99_ms=float(np.percentile([r["queue_ms"] for _, r in res], 99)),
                 determinants_per_s=dets / wall, sigma_determinants_per_s=apps / wall,
-                max_request_ndet=int(max(r["ndet"] for _, r in res)))
+                max_request_ndet=int(rl["ndet"]), classes=classes,
+                largest_request=dict(ndet=int(rl["ndet"]), nroots=int(Wl.nroots), norb=int(Wl.norb),
+                                     latency_in_mix_ms=rl["latency_ms"], run_in_mix_ms=rl["run_ms"],
+                                     queue_in_mix_ms=rl["queue_ms"], run_alone_ms=alone["run_ms"],
+                                     iterations=rl["report"]["iterations"],
+                                     energies_equal=bool(np.array_equal(alone["energies"], rl["energies"]))))
 
 
 def _csv_rows(path):
@@ -392,20 +396,119 @@ def assembled_leg(sbd, wl, stream, cases=(("sel16", 300), ("sel16", 1000), ("sel
     return out
 
 
+def stream_kernel(tune, prec):
+    """Row-stream instantiation a tune selects for single-vector sigma: columns
+    per lane (FP32: 2, or 4 with 16-byte loads; FP64: 1, or 2), output rows per
+    wavefront, or ket entries per load step in the ket-split form."""
+    t = "float" if prec == 1 else "double"
+    vec = (4 if tune["stream_wide"] else 2) if prec == 1 else (2 if tune["stream_wide"] else 1)
+    if tune.get("stream_split", 1) > 1:
+        return f"k_stream_ks<{t},1,{vec},{tune['stream_split']}>"
+    return f"k_stream<{t},1,{vec},{tune['stream_rw']}>"
+
+
+def table_counts(B, X):
+    p1a, p2a, p1b, p2b = X.count(0, 1), X.count(0, 2), X.count(1, 1), X.count(1, 2)
+    N = B.na * B.nb
+    nnz = N + B.nb * (p1a + p2a) + B.na * (p1b + p2b) + p1a * p1b
+    return dict(p1a=p1a, p2a=p2a, p1b=p1b, p2b=p2b, nnz=nnz)
+
+
+def sigma_report(sbd, W, B, X, H, prec, stream, nvec=1, reps=10):
+    """Per-stage times and the measurement items of one sigma shape: det/s;
+    fraction of the binding roof max(B/BW, F/P)/t with F = 2 k NNZ and B the
+    compulsory bytes (k N (w_in + w_out) + 8 N diagonal + tables, coefficients
+    and integrals); the HBM fraction (B/t)/BW beside its cap t_HBM/t_ALU; and
+    the gather volume k w (NNZ - N)/t as an effective cache bandwidth."""
+    import torch
+    layout = 1 if nvec > 1 else 0
+    H.autotune(prec, nvec=nvec, layout=layout, stream=stream)
+    dt = torch.float64 if prec == sbd.FP64 else torch.float32
+    N = W.ndet
+    x = torch.randn(N * nvec, device="cuda", dtype=dt)
+    y = torch.empty_like(x)
+    for _ in range(2):
+        sbd.sigma(H, x, y, nvec=nvec, prec=prec, shift=-200.0, layout=layout, stream=stream)
+    acc = None
+    for _ in range(reps):
+        st = sbd.sigma_timed(H, x, y, nvec=nvec, prec=prec, shift=-200.0, layout=layout, stream=stream)
+        acc = st if acc is None else {k: acc[k] + st[k] for k in st}
+    stages = {k: v / reps for k, v in acc.items()}
+    t = sum(stages.values()) * 1e-3
+    c = table_counts(B, X)
+    w = 8 if prec == sbd.FP64 else 4
+    F = 2.0 * nvec * c["nnz"]
+    tables = (c["p1a"] + c["p1b"]) * (8 + 8 + 4 + w) + (c["p2a"] + c["p2b"]) * (8 + 4 + w)
+    Bytes = nvec * N * 2 * w + 8 * N + tables + W.norb ** 4 * w
+    peak = PEAK_FP64_VALU if prec == sbd.FP64 else PEAK_FP32_VALU
+    t_hbm, t_alu = Bytes / PEAK_HBM, F / peak
+    return dict(workload=W.name, precision="f64" if prec == sbd.FP64 else "f32", vectors=nvec,
+                determinants=N, stage_ms=stages, sigma_ms=1e3 * t, det_per_s=nvec * N / t,
+                nnz_pairs=c["nnz"], flops=F, compulsory_bytes=Bytes,
+                binding_roof="alu" if t_alu >= t_hbm else "hbm",
+                binding_roof_frac=max(t_hbm, t_alu) / t, alu_frac=t_alu / t,
+                hbm_frac=t_hbm / t, hbm_frac_cap=min(1.0, t_hbm / t_alu),
+                gather_TBps=nvec * w * (c["nnz"] - N) / t / 1e12,
+                tune=H.get_tune(prec))
+
+
+def solve_runs(sbd, H, W, stream, reps, e_ref, tol):
+    """Plain FP64 and chosen-form solves, alternating, `reps` of each; per
+    solve: host wall time, the report's phases (workspace, autotune, sigma,
+    update, the rest = host decisions and synchronisation), iterations and the
+    time to |theta - e_ref| <= 1e-6 Ha."""
+    import torch
+    forms = (("plain_fp64", sbd.FP64), ("chosen", sbd.FP32))
+    runs = {name: [] for name, _ in forms}
+    for r in range(reps):
+        for name, prec in forms:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, rep, st = sbd.davidson(H, W.nroots, stream=stream, tol_residual=tol, sigma_prec=prec,
+                                      max_space=MAX_SPACE, use_autotune=1)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            other = rep["t_total_ms"] - rep["t_sigma_ms"] - rep["t_update_ms"] - rep["t_workspace_ms"] \
+                - rep["t_autotune_ms"]
+            runs[name].append(dict(ms=ms, solver_ms=rep["t_total_ms"], workspace_ms=rep["t_workspace_ms"],
+                                   autotune_ms=rep["t_autotune_ms"], sigma_ms=rep["t_sigma_ms"],
+                                   update_ms=rep["t_update_ms"], host_other_ms=other,
+                                   iterations=rep["iterations"], sigma_calls=rep["sigma_calls"],
+                                   sigma_calls_fp64=rep["sigma_calls_fp64"], energy=float(e[0]),
+                                   energy_error=float(abs(e[0] - e_ref)), status=int(st),
+                                   time_to_1e6_ms=time_to(rep["theta_history"], rep["time_history_ms"], e_ref)))
+            log(f"[bench] solve {name} #{r}: {ms:.1f} ms, {rep['iterations']} it, "
+                f"sigma {rep['t_sigma_ms']:.1f} update {rep['t_update_ms']:.1f} "
+                f"workspace {rep['t_workspace_ms']:.1f} ms, E={e[0]:.10f}")
+    out = {}
+    for name, rs in runs.items():
+        ms = np.array([x["ms"] for x in rs])
+        tt = [x["time_to_1e6_ms"] for x in rs if x["time_to_1e6_ms"] is not None]
+        out[name] = dict(runs=rs, median_ms=float(np.median(ms)), max_ms=float(ms.max()),
+                         min_ms=float(ms.min()), max_over_median=float(ms.max() / np.median(ms)),
+                         time_to_1e6_median_ms=float(np.median(tt)) if tt else None,
+                         energy_error_max=float(max(x["energy_error"] for x in rs)))
+    out["speedup_median"] = out["plain_fp64"]["median_ms"] / out["chosen"]["median_ms"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sel26")
+    ap.add_argument("--solve-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-solves", action="store_true")
+    ap.add_argument("--no-rows", action="store_true", help="skip the sel16 / block20 sigma rows")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-block", action="store_true")
     ap.add_argument("--no-sqd", action="store_true")
     ap.add_argument("--no-assembled", action="store_true")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a few sigma launches and a calibration copy (counter runs)")
+    ap.add_argument("--prec", type=int, default=0, help="precision of --kernel-only (0 FP64, 1 FP32)")
     ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
                     help="print a markdown summary of a rocprofv3 --stats run and exit")
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_ONLY_LOG"),
@@ -434,104 +537,119 @@ def main():
     log(f"[bench] workload {W.name}: norb={W.norb} n={W.n_alpha} strings={W.alpha.size}x"
         f"{W.beta.size} N={N} roots={W.nroots}")
     if args.kernel_only:
-        kernel_only(sbd, W, stream)
+        kernel_only(sbd, W, stream, args.prec)
         return
 
-    def solve(prec, tol_r):
-        B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
-        X = sbd.Excitations(B, stream=stream)
-        H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
-        e, rep, st = sbd.davidson(H, W.nroots, stream=stream, tol_residual=tol_r,
-                                  sigma_prec=prec, max_space=MAX_SPACE, use_autotune=1)
-        return e, rep, st, (B, X, H)
-
-    for i in range(args.warmup):
-        e, rep, st, _ = solve(sbd.FP32, tol)
-        log(f"[bench] warmup {i}: E={e[0]:.10f} it={rep['iterations']} "
-            f"t={rep['t_total_ms']:.1f} ms")
-
+    # set-up, once: basis, tables, Hamiltonian (strings and integrals uploaded from the host)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    reps = []
+    B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
+    t1 = time.perf_counter()
+    X = sbd.Excitations(B, stream=stream)
+    t2 = time.perf_counter()
+    H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    setup = dict(basis_ms=1e3 * (t1 - t0), tables_ms=1e3 * (t2 - t1), hamiltonian_ms=1e3 * (t3 - t2))
+    best64 = H.autotune(sbd.FP64, stream=stream)
+    best32 = H.autotune(sbd.FP32, stream=stream)
+    setup.update(autotune_best_ms_fp64=best64, autotune_best_ms_fp32=best32)
+    log(f"[bench] set-up {setup}")
+
+    # ---- the timed steps: FP64 sigma = H c on one resident vector
+    x = torch.randn(N, device="cuda", dtype=torch.float64)
+    x /= torch.linalg.vector_norm(x)
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        sbd.sigma(H, x, y, prec=sbd.FP64, stream=stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
     for i in range(args.steps):
-        e, rep, st, _ = solve(sbd.FP32, tol)
-        reps.append((e, rep))
+        sbd.sigma(H, x, y, prec=sbd.FP64, stream=stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
     ms_per_step = 1e3 * dt / args.steps
-    applications = sum(r["sigma_calls"] for _, r in reps)
     value = N * args.steps / dt
-    e_mixed = reps[-1][0]
-    rep_m = reps[-1][1]
-    log(f"[bench] timed: {args.steps} steps {ms_per_step:.1f} ms/step, sigma apps "
-        f"{applications}, E={e_mixed[0]:.10f}")
+    log(f"[bench] timed: {args.steps} FP64 sigma steps {ms_per_step:.3f} ms/step "
+        f"(events: median {np.median(step_ms):.3f}, max {step_ms.max():.3f} ms), {value:.3e} det/s")
 
-    extra = {}
-    if not args.no_plain:
-        tp = time.perf_counter()
-        e64, rep64, st64, keep = solve(sbd.FP64, tol)
-        torch.cuda.synchronize()
-        t_plain = 1e3 * (time.perf_counter() - tp)
-        # tight FP64 reference energy for time-to-1e-6 Ha
-        eref, repref, _ = sbd.davidson(keep[2], W.nroots, stream=stream, tol_residual=1e-8,
-                                       sigma_prec=sbd.FP64, max_space=20, use_autotune=1)
-        ttp = time_to(rep64["theta_history"], rep64["time_history_ms"], eref[0])
-        ttm = time_to(rep_m["theta_history"], rep_m["time_history_ms"], eref[0])
-        extra = dict(
-            plain_fp64=dict(ms_solve=t_plain, iterations=rep64["iterations"],
-                            sigma_calls=rep64["sigma_calls"], energy=float(e64[0]),
-                            time_to_1e6_ms=ttp, sigma_ms=rep64["t_sigma_ms"],
-                            update_ms=rep64["t_update_ms"]),
-            chosen_fp32_sigma=dict(ms_solve=ms_per_step, iterations=rep_m["iterations"],
-                                   sigma_calls=rep_m["sigma_calls"],
-                                   sigma_calls_fp64=rep_m["sigma_calls_fp64"],
-                                   energy=float(e_mixed[0]), time_to_1e6_ms=ttm,
-                                   sigma_ms=rep_m["t_sigma_ms"], update_ms=rep_m["t_update_ms"]),
-            reference_energy=float(eref[0]),
-            energy_error_chosen_vs_fp64=float(abs(e_mixed[0] - eref[0])),
-            energy_error_plain_vs_fp64=float(abs(e64[0] - eref[0])),
-        )
-        log(f"[bench] plain FP64: {t_plain:.1f} ms, E={e64[0]:.10f}; ref {eref[0]:.10f}")
-
-    # dominant kernel: the FP32 same-spin row stream (two launches per sigma),
-    # timed live with HIP events recorded on the launch stream
-    B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
-    X = sbd.Excitations(B, stream=stream)
-    H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
-    H.autotune(sbd.FP32, stream=stream)
-    kname = stream_kernel_name(H.get_tune(sbd.FP32))
-    stages32 = sigma_stages(sbd, H, N, sbd.FP32, stream)
+    # ---- roofline of the dominant kernel of the FP64 sigma, and the measurement items
+    rows = {}
+    rows["sel26_f64"] = sigma_report(sbd, W, B, X, H, sbd.FP64, stream)
+    rows["sel26_f32"] = sigma_report(sbd, W, B, X, H, sbd.FP32, stream)
     H.autotune(sbd.FP64, stream=stream)
-    stages64 = sigma_stages(sbd, H, N, sbd.FP64, stream)
-    p1a, p2a = X.count(0, 1), X.count(0, 2)
-    p1b, p2b = X.count(1, 1), X.count(1, 2)
-    nnz = N + B.nb * (p1a + p2a) + B.na * (p1b + p2b) + p1a * p1b
-    # algorithmic flops of the two stream launches: one multiply-add per
-    # connected same-spin pair (+ the diagonal term and the spectator add of singles)
-    f_alpha = 2.0 * (B.nb * (p1a + p2a) + N) + 1.0 * B.nb * p1a
-    f_beta = 2.0 * B.na * (p1b + p2b) + 1.0 * B.na * p1b
-    t_stream = (stages32["alpha_stream"] + stages32["beta_stream"]) * 1e-3
-    achieved = (f_alpha + f_beta) / t_stream
-    t_sig32 = sum(stages32.values()) * 1e-3
-    t_sig64 = sum(stages64.values()) * 1e-3
+    s64 = rows["sel26_f64"]["stage_ms"]
+    c = table_counts(B, X)
+    tune64 = H.get_tune(sbd.FP64)
+    kname = stream_kernel(tune64, sbd.FP64)
+    f_alpha = 2.0 * (B.nb * (c["p1a"] + c["p2a"]) + N) + 1.0 * B.nb * c["p1a"]
+    f_beta = 2.0 * B.na * (c["p1b"] + c["p2b"]) + 1.0 * B.na * c["p1b"]
+    b_alpha = 8.0 * 3 * N   # read c, read the diagonal, write sigma
+    b_beta = 8.0 * 2 * N    # read c^T, write the partial sigma^T
+    t_stream = (s64["alpha_stream"] + s64["beta_stream"]) * 1e-3
+    flops_rate = (f_alpha + f_beta) / t_stream
+    bytes_rate = (b_alpha + b_beta) / t_stream
+    alu_frac, hbm_frac = flops_rate / PEAK_FP64_VALU, bytes_rate / PEAK_HBM
     traffic = traffic_for(kname, W.name)
-    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
-                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU,
-                    traffic=None if traffic is None else traffic,
-                    # the measured bytes at the measured launch time, against the HBM peak
-                    traffic_rate_TBps=None if traffic is None else traffic / (t_stream / 2) / 1e12,
-                    traffic_frac_of_hbm_peak=None if traffic is None else traffic / (t_stream / 2) / PEAK_HBM,
-                    kernel=f"{kname} (alpha and beta launches of one FP32 sigma)",
-                    launch_ms=1e3 * t_stream / 2, algorithmic_flops_per_launch=(f_alpha + f_beta) / 2,
-                    sigma_fp32_stage_ms=stages32, sigma_fp64_stage_ms=stages64,
-                    sigma_fp32_det_per_s=N / t_sig32, sigma_fp64_det_per_s=N / t_sig64,
-                    nnz_pairs=nnz, sigma_fp32_pair_flops_per_s=2.0 * nnz / t_sig32)
-    log(f"[bench] sigma fp32 {1e3*t_sig32:.3f} ms ({stages32}), fp64 {1e3*t_sig64:.3f} ms; "
-        f"stream {achieved/1e12:.2f} TFLOP/s")
+    share = {k: v / sum(s64.values()) for k, v in s64.items()}
+    if hbm_frac >= alu_frac:
+        roofline = dict(bound="hbm", achieved=bytes_rate / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                        frac=hbm_frac)
+    else:
+        roofline = dict(bound="alu", achieved=flops_rate / 1e12, peak=PEAK_FP64_VALU / 1e12,
+                        unit="TFLOP/s", frac=alu_frac)
+    roofline.update(
+        traffic=traffic,
+        kernel=f"{kname} (alpha and beta row-stream launches of one FP64 sigma)",
+        launch_ms=1e3 * t_stream / 2,
+        algorithmic_bytes_per_launch=(b_alpha + b_beta) / 2,
+        algorithmic_flops_per_launch=(f_alpha + f_beta) / 2,
+        alu_frac_fp64=alu_frac, hbm_frac=hbm_frac,
+        traffic_rate_TBps=None if traffic is None else traffic / (t_stream / 2) / 1e12,
+        traffic_over_algorithmic=None if traffic is None else traffic / ((b_alpha + b_beta) / 2),
+        stage_share_of_sigma=share)
+    log(f"[bench] sigma f64 {rows['sel26_f64']['sigma_ms']:.3f} ms {s64}; "
+        f"f32 {rows['sel26_f32']['sigma_ms']:.3f} ms; roofline {roofline['bound']} {roofline['frac']:.3f}")
 
+    extra = dict(setup=setup, step_event_ms=dict(median=float(np.median(step_ms)), max=float(step_ms.max()),
+                                                 min=float(step_ms.min())))
+    if not args.no_solves:
+        # tight FP64 reference energy for the time to 1e-6 Ha
+        eref, repref, _ = sbd.davidson(H, W.nroots, stream=stream, tol_residual=1e-8,
+                                       sigma_prec=sbd.FP64, max_space=20, use_autotune=1)
+        extra["reference_energy"] = float(eref[0])
+        extra["reference_iterations"] = repref["iterations"]
+        extra["solves"] = solve_runs(sbd, H, W, stream, args.solve_reps, float(eref[0]), tol)
+        sv = extra["solves"]
+        log(f"[bench] solves: plain median {sv['plain_fp64']['median_ms']:.1f} (max/median "
+            f"{sv['plain_fp64']['max_over_median']:.3f}), chosen median {sv['chosen']['median_ms']:.1f} "
+            f"(max/median {sv['chosen']['max_over_median']:.3f}) ms; time to 1e-6 Ha "
+            f"{sv['plain_fp64']['time_to_1e6_median_ms']} vs {sv['chosen']['time_to_1e6_median_ms']} ms")
+    del x, y
+    if not args.no_rows:
+        for name, nv in (("sel16", 1), ("block20", 4)):
+            Wr = wl.make_config(name)
+            Br = sbd.Basis(Wr.norb, Wr.n_alpha, Wr.n_beta, Wr.alpha, Wr.beta, stream=stream)
+            Xr = sbd.Excitations(Br, stream=stream)
+            Hr = sbd.Hamiltonian(Br, Xr, Wr.h, Wr.eri, Wr.e_core, stream=stream)
+            for prec, tag in ((sbd.FP64, "f64"), (sbd.FP32, "f32")):
+                rows[f"{name}_{tag}"] = sigma_report(sbd, Wr, Br, Xr, Hr, prec, stream, nvec=nv)
+                r = rows[f"{name}_{tag}"]
+                log(f"[bench] sigma row {name} {tag} k={nv}: {r['sigma_ms']:.3f} ms, {r['det_per_s']:.3e} det/s, "
+                    f"binding {r['binding_roof']} {r['binding_roof_frac']:.3f}")
+            del Hr, Xr, Br
+    extra["sigma_rows"] = rows
+    del H, X, B
+    torch.cuda.synchronize()
+    sbd.release_cached_memory()
     if not args.no_block:
         extra["block"] = block_leg(sbd, wl, stream)
         log(f"[bench] block: {extra['block']}")
+        sbd.release_cached_memory()
     if not args.no_sqd:
         extra["sqd_loop"] = sqd_leg(sbd, wl, stream)
         for name in ("coarse", "fine"):
@@ -539,26 +657,26 @@ def main():
             log(f"[bench] sqd loop {name} {q['strings_per_spin']}: cold {q['cold_ms']:.0f} ms "
                 f"{[x['iterations'] for x in q['cold']]} it, warm {q['warm_ms']:.0f} ms "
                 f"{[x['iterations'] for x in q['warm']]} it, energies {[round(x['energy'], 6) for x in q['warm']]}")
+        sbd.release_cached_memory()
     if not args.no_assembled:
         extra["assembled"] = assembled_leg(sbd, wl, stream)
         for r in extra["assembled"]:
             log(f"[bench] assembled {r['workload']}: N={r['determinants']} entries={r['stored_entries']} "
                 f"assemble {r['assemble_ms']:.1f} ms; sigma free {r['free_sigma_ms']} csr {r['csr_sigma_ms']} "
                 f"({r['csr_hbm_TBps']} TB/s); solve free {r['free_solve_ms']:.1f} csr {r['csr_solve_ms']:.1f} ms")
+        sbd.release_cached_memory()
     if not args.no_serving:
         extra["serving"] = serving(sbd, wl)
-        log(f"[bench] serving: {extra['serving']}")
+        log(f"[bench] serving: { {k: v for k, v in extra['serving'].items() if k != 'classes'} }")
     cpu = None if args.no_cpu_baseline else cpu_baseline(W)
-    out = dict(metric="determinants/s of whole Davidson solves to 1e-6 (chosen form: FP32 sigma "
-                      "+ FP64 refinement); sigma determinants/s and time-to-1e-6 Ha, plain FP64 "
-                      "vs chosen, alongside",
+    out = dict(metric="sigma=H.c determinants/s (FP64, one vector, sel26); Davidson time-to-1e-6 Ha, "
+                      "plain FP64 vs chosen form, alongside",
                value=value, unit="det/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=ms_per_step, higher_is_better=True, scaling="weak",
-               vs_baseline=None, dtype="f32", data="synthetic",
+               vs_baseline=None, dtype="f64", data="synthetic",
                config=dict(workload=W.name, norb=W.norb, n_alpha=W.n_alpha, n_beta=W.n_beta,
-                           strings_per_spin=int(W.alpha.size), determinants=N,
-                           nroots=W.nroots, tol_residual=tol, max_space=MAX_SPACE),
-               sigma_applications_per_step=applications / args.steps,
+                           strings_per_spin=int(W.alpha.size), determinants=N, vectors_per_step=1,
+                           solve_tol_residual=tol, solve_max_space=MAX_SPACE),
                roofline=roofline, cpu_baseline=cpu, **extra)
     print(json.dumps(out))
 

@@ -69,6 +69,22 @@ int sbd_version(void);
  * compare it with their own sources to refuse a stale build. */
 const char* sbd_source_hash(void);
 
+/*
+ * Device memory of the library.  Every device buffer the library owns
+ * (handles, sigma workspaces, Davidson subspaces) comes from a per-device
+ * cache: a released buffer is kept, after the device has synchronised, and
+ * handed out again to a later request of about the same size, so successive
+ * solves of one workload do not map and unmap tens of gigabytes each time.
+ * Buffers carved from a serving slab are not part of it.
+ * sbd_release_cached_memory returns every cached (unused) block of every
+ * device to the driver; it synchronises the devices that have cached blocks.
+ * sbd_memory_stats reports, for the current device, the bytes held in the
+ * cache unused and the bytes handed out to live buffers.
+ * Errors: sbd_memory_stats returns SBD_ERR_ARG for a NULL pointer.
+ */
+int sbd_release_cached_memory(void);
+int sbd_memory_stats(size_t* cached_bytes, size_t* in_use_bytes);
+
 typedef struct sbd_basis sbd_basis;
 typedef struct sbd_exc sbd_exc;
 typedef struct sbd_ham sbd_ham;
@@ -117,7 +133,7 @@ void sbd_free_exc(sbd_exc* e);
 
 /*
  * Hamiltonian on a basis (Eq. 3).  Uploads h and (pq|rs), builds the
- * diagonal H_ii (cached, Sec. II-D) and per-table-entry matrix-element
+ * diagonal H_ii (cached, Sec. II-E) and per-table-entry matrix-element
  * coefficients in FP64 and FP32.  h1: norb*norb host array; eri: norb^4
  * host array; e_core is added to every diagonal element.
  * Errors: SBD_ERR_INTEGRALS (asymmetric input), SBD_ERR_STATE (exc not built
@@ -280,6 +296,8 @@ typedef struct {
     double residual[64];   /* final ||r||_2 per root                                                */
     double ortho_loss;     /* ||V^T V - I||_F at exit                                               */
     double t_sigma_ms, t_update_ms, t_total_ms;
+    double t_workspace_ms; /* acquiring the device workspace (block cache or driver)                */
+    double t_autotune_ms;  /* opts.use_autotune: timing the sigma candidates (0 when cached)        */
     int n_history;         /* entries filled in theta_history                                       */
     double theta_history[512]; /* lowest Ritz value per iteration (first 512 iterations)            */
     double time_history_ms[512]; /* wall time since the call started, per iteration                 */
@@ -302,7 +320,8 @@ void sbd_davidson_default_opts(sbd_davidson_opts* o);
  * Returns SBD_OK, SBD_NOT_CONVERGED (outputs valid), or an error
  * (SBD_ERR_ARG, SBD_ERR_STATE, SBD_ERR_NOMEM, SBD_ERR_NUMERIC, SBD_ERR_HIP).
  * Workspace (2*max_space + 2*nroots vectors of N doubles, plus FP32 copies
- * in SBD_FP32 mode) is allocated for the call and freed before returning.
+ * in SBD_FP32 mode) is taken from the library's device block cache for the
+ * call and returned to it before returning (see sbd_release_cached_memory).
  */
 int sbd_davidson(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h, int nroots,
                  const sbd_davidson_opts* opts, double* energies, double* vectors,
@@ -315,7 +334,8 @@ int sbd_davidson(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h, int nro
  * threads, each with its own HIP stream (default priority).  A submitted
  * request is copied, queued in arrival order, and admitted when a worker is
  * free and a contiguous region of its estimated size (sbd_serve_estimate) is
- * free in the slab; every device buffer of the request (basis, tables,
+ * free in the slab (a later request that fits may pass a head that does not,
+ * at most 64 times per head); every device buffer of the request (basis, tables,
  * Hamiltonian, Davidson vectors) is carved from that region, so requests run
  * concurrently on the device with their vectors resident, and no device
  * allocation or free happens on the serving path.  The region returns to the
@@ -365,8 +385,11 @@ int sbd_serve_submit(sbd_server* s, const sbd_request* req, uint64_t* ticket);
 /* Blocks until the request has finished and moves its result to *out (each
  * ticket can be waited once).  Returns SBD_OK or SBD_ERR_ARG (unknown ticket). */
 int sbd_serve_wait(sbd_server* s, uint64_t ticket, sbd_result* out);
-/* Finishes the running requests, fails the queued ones, joins the workers and
- * frees the slab.  Results not yet waited for are discarded. */
+/* Finishes the running requests, fails the queued ones (a thread waiting on one
+ * receives status SBD_ERR_STATE), joins the workers, waits until every thread
+ * inside sbd_serve_wait on this server has returned, and frees the slab.
+ * Results not yet waited for are discarded.  No call on the server may start
+ * after sbd_serve_destroy has been entered. */
 void sbd_serve_destroy(sbd_server* s);
 
 #ifdef __cplusplus

@@ -54,6 +54,8 @@ def lib():
         L.orc_sigma.restype = i32
         L.orc_sigma_at.argtypes = [i32, P, P, d, P, i64, P, i64] + tab + [P, P, i64, P]
         L.orc_sigma_at.restype = i32
+        L.orc_sigma_abs_at.argtypes = [i32, P, P, d, P, i64, P, i64] + tab + [P, d, P, i64, P]
+        L.orc_sigma_abs_at.restype = i32
         L.orc_diag.argtypes = [i32, P, P, d, P, i64, P, i64, P]
         L.orc_diag.restype = i32
         L.orc_dense_h.argtypes = [i32, P, P, d, P, i64, P, i64, P]
@@ -161,6 +163,24 @@ class OracleSystem:
         y = np.empty(idx.size, dtype=np.float64)
         lib().orc_sigma_at(*self._common(), _p(x), _p(idx), idx.size, _p(y))
         return y
+
+    def sigma_abs_at(self, x: np.ndarray, idx, shift: float = 0.0) -> np.ndarray:
+        """(|H - shift I| |x|)_I for the determinant indices in idx (one vector):
+        the magnitude sum that bounds the rounding error of (H - shift) x."""
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        y = np.empty(idx.size, dtype=np.float64)
+        lib().orc_sigma_abs_at(*self._common(), _p(x), float(shift), _p(idx), idx.size, _p(y))
+        return y
+
+    def row_terms(self, idx) -> np.ndarray:
+        """z_I, the number of stored terms of row I of H (the determinant itself
+        and its Slater-Condon neighbours in the basis), for I in idx."""
+        idx = np.asarray(idx, dtype=np.int64)
+        ia, ib = idx // self.nb, idx % self.nb
+        la = lambda t, i: t.row_ptr[i + 1] - t.row_ptr[i]
+        s1a, s2a, s1b, s2b = la(self.a1, ia), la(self.a2, ia), la(self.b1, ib), la(self.b2, ib)
+        return 1 + s1a + s2a + s1b + s2b + s1a * s1b
 
     def diag(self) -> np.ndarray:
         if self._diag is None:

@@ -360,6 +360,50 @@ int orc_sigma_at(int norb, const double* h, const double* eri, double e_core,
     return ORC_OK;
 }
 
+/*
+ * Componentwise magnitude bound at selected determinants:
+ * y[k] = sum_J |H_IJ - shift delta_IJ| |x_J| for I = idx[k] (one vector).  The
+ * same neighbourhood walk as sigma, with every element and vector entry taken
+ * in absolute value; it bounds the rounding error of any summation order of
+ * (H - shift) x (u * z_I * y[k] to first order, z_I terms in row I).
+ */
+int orc_sigma_abs_at(int norb, const double* h, const double* eri, double e_core,
+                     const uint64_t* a, int64_t na, const uint64_t* b, int64_t nb,
+                     const int64_t* a1p, const int32_t* a1J, const int64_t* a2p, const int32_t* a2J,
+                     const int64_t* b1p, const int32_t* b1J, const int64_t* b2p, const int32_t* b2J,
+                     const double* x, double shift, const int64_t* idx, int64_t nidx, double* y) {
+    ham_t H = {norb, h, eri, e_core};
+    basis_t B;
+    fill_basis(&B, a, na, b, nb, a1p, a1J, a2p, a2J, b1p, b1J, b2p, b2J);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < nidx; ++k) {
+        const int64_t ia = idx[k] / nb, ib = idx[k] % nb;
+        det_t I = mkdet(&B, ia, ib);
+        double acc = fabs(hij(&H, &I, &I) - shift) * fabs(x[idx[k]]);
+        const int64_t* ap[2] = {B.a1p, B.a2p};
+        const int32_t* aJ[2] = {B.a1J, B.a2J};
+        const int64_t* bp[2] = {B.b1p, B.b2p};
+        const int32_t* bJ[2] = {B.b1J, B.b2J};
+        for (int t = 0; t < 2; ++t) {
+            for (int64_t e = ap[t][ia]; e < ap[t][ia + 1]; ++e) {
+                det_t J = mkdet(&B, aJ[t][e], ib);
+                acc += fabs(hij(&H, &I, &J)) * fabs(x[aJ[t][e] * nb + ib]);
+            }
+            for (int64_t e = bp[t][ib]; e < bp[t][ib + 1]; ++e) {
+                det_t J = mkdet(&B, ia, bJ[t][e]);
+                acc += fabs(hij(&H, &I, &J)) * fabs(x[ia * nb + bJ[t][e]]);
+            }
+        }
+        for (int64_t ea = B.a1p[ia]; ea < B.a1p[ia + 1]; ++ea)
+            for (int64_t eb = B.b1p[ib]; eb < B.b1p[ib + 1]; ++eb) {
+                det_t J = mkdet(&B, B.a1J[ea], B.b1J[eb]);
+                acc += fabs(hij(&H, &I, &J)) * fabs(x[(int64_t)B.a1J[ea] * nb + B.b1J[eb]]);
+            }
+        y[k] = acc;
+    }
+    return ORC_OK;
+}
+
 /* Diagonal H_II for every determinant. */
 int orc_diag(int norb, const double* h, const double* eri, double e_core,
              const uint64_t* a, int64_t na, const uint64_t* b, int64_t nb, double* d) {

@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "SBD_OK", 1: "SBD_NOT_CONVERGED", -1: "SBD_ERR_ARG", -2: "SBD
                 -6: "SBD_ERR_HIP", -7: "SBD_ERR_NUMERIC", -8: "SBD_ERR_STATE"}
 
 # Every symbol include/sbd.h declares.
-EXPORTED = ["sbd_last_error", "sbd_version", "sbd_source_hash", "sbd_build_basis", "sbd_basis_sizes",
+EXPORTED = ["sbd_last_error", "sbd_version", "sbd_source_hash", "sbd_release_cached_memory",
+            "sbd_memory_stats", "sbd_build_basis", "sbd_basis_sizes",
             "sbd_basis_strings", "sbd_free_basis", "sbd_build_excitations", "sbd_exc_count",
             "sbd_exc_export", "sbd_free_exc", "sbd_set_hamiltonian", "sbd_ham_diag",
             "sbd_free_ham", "sbd_sigma", "sbd_sigma_timed", "sbd_autotune", "sbd_get_tune", "sbd_set_tune", "sbd_gram", "sbd_map_vectors",
@@ -56,6 +57,7 @@ class DavidsonReport(ctypes.Structure):
                 ("fp32_error_scale", ctypes.c_double), ("residual", ctypes.c_double * 64),
                 ("ortho_loss", ctypes.c_double), ("t_sigma_ms", ctypes.c_double),
                 ("t_update_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
+                ("t_workspace_ms", ctypes.c_double), ("t_autotune_ms", ctypes.c_double),
                 ("n_history", ctypes.c_int), ("theta_history", ctypes.c_double * 512),
                 ("time_history_ms", ctypes.c_double * 512)]
 
@@ -69,6 +71,7 @@ class DavidsonReport(ctypes.Structure):
                     residual=list(self.residual[:nroots]),
                     ortho_loss=self.ortho_loss, t_sigma_ms=self.t_sigma_ms,
                     t_update_ms=self.t_update_ms, t_total_ms=self.t_total_ms,
+                    t_workspace_ms=self.t_workspace_ms, t_autotune_ms=self.t_autotune_ms,
                     theta_history=list(self.theta_history[:n]),
                     time_history_ms=list(self.time_history_ms[:n]))
 
@@ -114,6 +117,8 @@ def load():
     L.sbd_last_error.restype = ctypes.c_char_p
     L.sbd_last_error.argtypes = []
     L.sbd_version.restype = i32
+    L.sbd_release_cached_memory.argtypes = []
+    L.sbd_memory_stats.argtypes = [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
     L.sbd_build_basis.argtypes = [i32, i32, i32, P, i64, P, i64, P, PP]
     L.sbd_basis_sizes.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.sbd_basis_strings.argtypes = [P, P, P]
@@ -166,6 +171,18 @@ def check(status: int) -> int:
     if status < 0:
         raise SBDError(status, last_error())
     return status
+
+
+def release_cached_memory() -> None:
+    """Return the library's cached device blocks to the driver."""
+    check(load().sbd_release_cached_memory())
+
+
+def memory_stats() -> dict:
+    """Bytes of the current device held by the library's block cache."""
+    c, u = ctypes.c_size_t(), ctypes.c_size_t()
+    check(load().sbd_memory_stats(ctypes.byref(c), ctypes.byref(u)))
+    return dict(cached_bytes=c.value, in_use_bytes=u.value)
 
 
 def _stream(stream):

@@ -341,6 +341,7 @@ struct Solver {
     // W[0..mw)^T v_new / |v_new| and accept tells whether the vector survived
     // (|v_new| > 1e-12 |t|).
     int orthonormalise(double* t, int m, int mw, double n0, std::vector<double>& u, bool& accept) {
+        if (m >= ms) return fail(SBD_ERR_STATE, "internal: no free subspace row for a new vector");
         double* p = part.as<double>();
         u.assign(mw, 0.0);
         const double* h2 = sm + kH2 + 1;
@@ -455,7 +456,9 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     ms = (int)std::min<int64_t>(ms, std::max<int64_t>(N, 1));
     ms = std::min(ms, 48);
     hipStream_t st = (hipStream_t)stream;
+    double t_autotune = 0.0, t_workspace = 0.0;
     if (o.use_autotune) {
+        const auto ta = clk::now();
         // launch configuration only: sigma values do not depend on it beyond rounding
         // order.  Tuned for the sigma shape the solve issues most: k interleaved
         // vectors for a block solve, single vectors otherwise.
@@ -465,6 +468,7 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         if (!rc && o.sigma_prec == SBD_FP32)
             rc = sbd_autotune(b, x, const_cast<sbd_ham*>(H), SBD_FP32, nvt, lay, stream, nullptr);
         if (rc) return rc;
+        t_autotune = ms_since(ta);
     }
 
     // graph capture needs a stream of its own (the legacy default stream cannot
@@ -488,8 +492,10 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     // block solves gather all new vectors of an iteration in one interleaved sigma
     S.nvmax = (k < 2 || !o.block_sigma) ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));
     S.use_graph = o.use_graph != 0;
+    const auto tw = clk::now();
     int rc = S.alloc();
     if (rc) return rc;
+    t_workspace = ms_since(tw);
     double* sm = S.sm;
     double* part = S.part.as<double>();
     double* tmp = S.tmp.as<double>();
@@ -734,7 +740,7 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         // A nearly dependent block (a Cholesky pivot below 1 % of its column's
         // norm) falls back to the one-root-at-a-time path below.
         bool block_done = false;
-        if (k >= 2 && nnew == k && m >= 1 && pass_subb_fits(m, k)) {
+        if (k >= 2 && nnew == k && m >= 1 && m + k <= ms && pass_subb_fits(m, k)) {
             std::vector<double> Hm((size_t)m * k);
             if (h1_valid) {
                 for (int j = 0; j < m; ++j)
@@ -808,6 +814,9 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         }
         for (int r = 0; r < k && !block_done; ++r) {
             if (rnorm[r] <= o.tol_residual) continue;
+            // no room left: a basis of N < 2 nroots determinants restarts onto
+            // more vectors than leave space for one correction per root
+            if (m >= ms) break;
             double* t = tmp + (size_t)r * N;
             if (h1_valid && m == m_old) {
                 // projection of root r from the residual pass: rows [2k + j*k + r)
@@ -917,6 +926,8 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         report->t_sigma_ms = S.t_sigma;
         report->t_update_ms = t_update;
         report->t_total_ms = ms_since(t_start);
+        report->t_workspace_ms = t_workspace;
+        report->t_autotune_ms = t_autotune;
         report->n_history = hist_n;
         for (int i = 0; i < hist_n; ++i) {
             report->theta_history[i] = hist_theta[i];

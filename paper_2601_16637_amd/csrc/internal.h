@@ -40,6 +40,14 @@ struct Region {
 };
 Region* current_region();
 
+// Caching device allocator (pool.cpp): blocks released by DevBuf are kept per
+// device, after a device synchronisation, and reused for requests of about the
+// same size; sbd_release_cached_memory() hands them back to the driver.
+hipError_t pool_alloc(size_t n, void** out);
+void pool_free(void* p);
+void pool_stats(size_t* cached, size_t* in_use);
+void pool_release_cached();
+
 // Device buffer owned by a handle.
 struct DevBuf {
     void* p = nullptr;
@@ -82,10 +90,10 @@ struct DevBuf {
             regional = true;
             return hipSuccess;
         }
-        return hipMalloc(&p, n);
+        return pool_alloc(n, &p);
     }
     void release() {
-        if (p && !regional) (void)hipFree(p);
+        if (p && !regional) pool_free(p);
         p = nullptr;
         bytes = 0;
         regional = false;

@@ -1,4 +1,4 @@
-// Hamiltonian set-up kernels: the cached diagonal (Sec. II-D) and the
+// Hamiltonian set-up kernels: the cached diagonal (Sec. II-E) and the
 // matrix-element coefficients of every excitation-table entry (Eq. 4 with the
 // Slater-Condon forms of the half-bitstring split).
 //

@@ -5,7 +5,9 @@
 // (the HBM budget) and a pool of worker threads, each driving its own HIP
 // stream.  Requests queue in arrival order; the head is admitted as soon as a
 // worker is idle and a contiguous region of its estimated size is free in the
-// slab.  The worker installs the region as the thread's allocation arena, so
+// slab.  When the head does not fit the free slab space, a later request that
+// fits may pass it, but the head is passed at most kMaxBypass times, so a
+// large request cannot be starved by a stream of small ones.  The worker installs the region as the thread's allocation arena, so
 // every device buffer of the request is carved from it (no hipMalloc/hipFree
 // on the serving path: hipFree would synchronise the whole device and stall
 // the other requests), runs the solve on its stream, synchronises that stream,
@@ -34,6 +36,7 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 constexpr size_t kRegionAlign = size_t(2) << 20;  // 2 MiB: keeps the slab's free list short
+constexpr int kMaxBypass = 64;  // later requests that may be admitted past a head that does not fit
 
 double ms_between(clk::time_point a, clk::time_point b) {
     return std::chrono::duration<double, std::milli>(b - a).count();
@@ -52,6 +55,7 @@ struct Job {
     std::vector<uint64_t> A, B;
     std::vector<double> h, eri;
     size_t est = 0;
+    int bypassed = 0;  // later requests admitted while this one waited at the head
     clk::time_point t_submit;
 };
 
@@ -69,6 +73,7 @@ struct sbd_server {
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
     bool stop = false;
+    int waiters = 0;  // threads inside sbd_serve_wait
     uint64_t next = 1;
     int device = 0;
     clk::time_point t0 = clk::now();
@@ -127,19 +132,40 @@ void run_job(const Job& j, hipStream_t st, sbd_result& r) {
     sbd_free_basis(b);
 }
 
+// Next job to admit, with its slab offset; caller holds the lock.  The head
+// if it fits; otherwise the first later job that fits, while the head has
+// been passed fewer than kMaxBypass times.
+bool admit(sbd_server* s, Job** out, size_t* off) {
+    if (s->queue.empty()) return false;
+    Job* head = s->queue.front();
+    if (slab_take(s, head->est, off)) {
+        s->queue.pop_front();
+        *out = head;
+        return true;
+    }
+    if (head->bypassed >= kMaxBypass) return false;
+    for (auto it = std::next(s->queue.begin()); it != s->queue.end(); ++it) {
+        if ((*it)->est > head->est || !slab_take(s, (*it)->est, off)) continue;
+        *out = *it;
+        s->queue.erase(it);
+        ++head->bypassed;
+        return true;
+    }
+    return false;
+}
+
 void worker(sbd_server* s, int w) {
     (void)hipSetDevice(s->device);
     hipStream_t st = s->streams[w];
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
         size_t off = 0;
+        Job* j = nullptr;
         s->cv_work.wait(lk, [&] {
             if (s->stop) return true;
-            return !s->queue.empty() && slab_take(s, s->queue.front()->est, &off);
+            return admit(s, &j, &off);
         });
         if (s->stop) break;
-        Job* j = s->queue.front();
-        s->queue.pop_front();
         lk.unlock();
 
         sbd_result r;
@@ -288,10 +314,13 @@ extern "C" int sbd_serve_wait(sbd_server* s, uint64_t ticket, sbd_result* out) {
     if (!s || !out) return fail(SBD_ERR_ARG, "null argument");
     std::unique_lock<std::mutex> lk(s->mu);
     if (!s->known.count(ticket)) return fail(SBD_ERR_ARG, "unknown ticket");
+    ++s->waiters;
     s->cv_done.wait(lk, [&] { return s->done.count(ticket) > 0; });
     *out = s->done[ticket];
     s->done.erase(ticket);
     s->known.erase(ticket);
+    --s->waiters;
+    s->cv_done.notify_all();  // sbd_serve_destroy may be waiting for the last waiter to leave
     return SBD_OK;
 }
 
@@ -300,11 +329,27 @@ extern "C" void sbd_serve_destroy(sbd_server* s) {
     {
         std::lock_guard<std::mutex> g(s->mu);
         s->stop = true;
-        for (Job* j : s->queue) delete j;
+        // queued requests fail: their waiters (if any) get SBD_ERR_STATE
+        for (Job* j : s->queue) {
+            sbd_result r;
+            std::memset(&r, 0, sizeof(r));
+            r.status = SBD_ERR_STATE;
+            std::strncpy(r.message, "server destroyed before the request was admitted",
+                         sizeof(r.message) - 1);
+            r.queue_ms = r.latency_ms = ms_between(j->t_submit, clk::now());
+            s->done[j->ticket] = r;
+            delete j;
+        }
         s->queue.clear();
     }
     s->cv_work.notify_all();
-    for (auto& t : s->workers) t.join();
+    s->cv_done.notify_all();
+    for (auto& t : s->workers) t.join();  // running requests finish and post their results
+    {
+        // threads blocked in sbd_serve_wait hold the server: let them take their results first
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_done.wait(lk, [&] { return s->waiters == 0; });
+    }
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     (void)hipFree(s->slab);
     delete s;

@@ -90,7 +90,7 @@ def _check_tables(bas, exc, norb):
 
 
 @pytest.mark.parametrize("name,nstr", [("fci8", None), ("sel16", 2000), ("block20", 700),
-                                       ("sel26", 10000)])
+                                       ("block20", 5000), ("sel26", 10000)])
 def test_tables_bitexact(name, nstr):
     W = wl.make_config(name, nstr=nstr)
     bas = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta)
@@ -265,7 +265,79 @@ def test_sigma_full_size_sampled(name, prec):
         assert rel(y[idx], yo) <= 2e-5
 
 
+@pytest.mark.parametrize("name,nvec", [("sel26", 1), ("block20", 4)])
+def test_sigma_fp32_componentwise_bound_full_size(name, nvec):
+    """FP32 sigma at full size in the benchmark's launch configuration (sel26
+    one vector; block20 four interleaved vectors): on sampled rows every
+    component is within |s32 - s64|_I <= 2 (z_I + 2) u32 (|H - shift| |x32|)_I
+    of the exact product of the FP32-rounded input, u32 = 2^-24, z_I the terms
+    of row I, with the magnitude sum from the oracle."""
+    W = wl.make_config(name)
+    _, _, ham = from_workload(W)
+    layout = 1 if nvec > 1 else 0
+    ham.autotune(1, nvec=nvec, layout=layout)
+    N = W.ndet
+    S = oracle.OracleSystem.from_workload(W)
+    shift = float(S.diag().min())
+    rng = np.random.default_rng(51)
+    X = rng.standard_normal((nvec, N)).astype(np.float32)
+    X /= np.linalg.norm(X, axis=1, keepdims=True).astype(np.float32)
+    xd = torch.tensor(X.T.copy() if nvec > 1 else X[0], device=DEV)
+    yd = torch.empty_like(xd)
+    sbd.sigma(ham, xd, yd, nvec=nvec, prec=1, shift=shift, layout=layout)
+    torch.cuda.synchronize()
+    Y = yd.cpu().numpy().astype(np.float64).reshape(N, nvec).T if nvec > 1 else \
+        yd.cpu().numpy().astype(np.float64)[None, :]
+    del xd, yd
+    idx = np.unique(np.concatenate([rng.integers(0, N, 1500), [0, N - 1, W.beta.size, N // 2]]))
+    z = S.row_terms(idx)
+    for v in range(nvec):
+        x = X[v].astype(np.float64)
+        exact = S.sigma_at(x, idx) - shift * x[idx]
+        bound = 2 * (z + 2) * 2.0 ** -24 * S.sigma_abs_at(x, idx, shift)
+        err = np.abs(Y[v][idx] - exact)
+        assert np.all(err <= bound), (v, np.max(err / bound))
+
+
 # ------------------------------------------------------------------ a6 Davidson
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_davidson_full_sel16_energy_vs_oracle_golden(prec):
+    """Full sel16 (N = 4e6): the lowest energy in plain FP64 within 1e-8 Ha and
+    in the chosen form within 1e-6 Ha of the oracle's Davidson on the oracle's
+    sigma (tests/golden/energies_sel16.json, written by make_energies.py)."""
+    g = _golden("energies_sel16.json")
+    W = wl.make_config("sel16")
+    assert g["determinants"] == W.ndet and g["seeds"] == list(W.meta["seeds"])
+    _, _, ham = from_workload(W)
+    e, rep, st = sbd.davidson(ham, 1, tol_residual=1e-7, sigma_prec=prec, use_autotune=1)
+    assert st == 0
+    assert abs(e[0] - g["energies"][0]) <= (1e-8 if prec == 0 else 1e-6), (e[0], g["energies"][0])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_davidson_block20_energies_vs_oracle_golden(prec):
+    """block20 at 2,500 strings per spin (N = 6.25e6), four roots solved as a
+    block: every energy within 1e-8 Ha (plain FP64) and 1e-6 Ha (chosen form:
+    FP32 interleaved block sigma, FP64 refinement, graph replay) of the
+    oracle's (tests/golden/energies_block20_2500.json)."""
+    g = _golden("energies_block20_2500.json")
+    W = wl.make_config("block20", nstr=2500)
+    assert g["determinants"] == W.ndet and g["seeds"] == list(W.meta["seeds"])
+    _, _, ham = from_workload(W)
+    kw = dict(sigma_prec=1, use_graph=1, block_sigma=1) if prec else dict(sigma_prec=0, block_sigma=0)
+    e, rep, st = sbd.davidson(ham, 4, tol_residual=1e-7, max_space=24, use_autotune=1, **kw)
+    assert st == 0
+    err = np.abs(e[:4] - np.array(g["energies"]))
+    assert err.max() <= (1e-8 if prec == 0 else 1e-6), err
+
+
 def test_davidson_fci8_vs_dense():
     W = wl.make_config("fci8")
     _, _, ham = from_workload(W)

@@ -377,3 +377,84 @@ def test_map_vector_embedding_keeps_rayleigh_quotient():
     assert abs(np.linalg.norm(y) - 1.0) < 1e-12
     assert abs(y @ big.sigma(y) - e[0]) < 1e-10 * abs(e[0])
     assert np.array_equal(oracle.map_vector(big_a, big_b, sa, sb, y), x)
+
+
+# ---------------------------------------------------------------- connected-pair count
+def _count_connected_brute(S):
+    """Pairs (I, J) of determinants differing by at most two electrons, counted
+    over every pair of the basis (no tables): the stored terms of H including
+    the diagonal."""
+    A = S.alpha.astype(np.uint64)
+    B = S.beta.astype(np.uint64)
+
+    def popc(v):
+        v = v.copy()
+        c = np.zeros(v.shape, dtype=np.int64)
+        while np.any(v):
+            c += (v & np.uint64(1)).astype(np.int64)
+            v >>= np.uint64(1)
+        return c
+
+    da = popc(A[:, None] ^ A[None, :]) // 2   # electrons moved within alpha
+    db = popc(B[:, None] ^ B[None, :]) // 2
+    # a determinant pair (ia,ib)-(ja,jb) is connected iff da + db <= 2
+    hist_a = np.bincount(da.ravel(), minlength=3)[:3]
+    hist_b = np.bincount(db.ravel(), minlength=3)[:3]
+    return int(sum(hist_a[i] * hist_b[j] for i in range(3) for j in range(3) if i + j <= 2))
+
+
+@pytest.mark.parametrize("norb,na,nb,sa,sb", [
+    (6, 3, 3, None, None), (7, 3, 2, None, None), (6, 0, 2, None, None), (5, 5, 2, None, None),
+    (8, 4, 4, 30, 25), (10, 3, 5, 40, 60), (6, 6, 0, None, None), (9, 1, 4, None, 50),
+])
+def test_nnz_equals_brute_force_pair_count(norb, na, nb, sa, sb):
+    """OracleSystem.nnz (N + nb (P1a + P2a) + na (P1b + P2b) + P1a P1b from the
+    tables) equals a count over all determinant pairs of those differing by at
+    most two electrons, with unequal electron counts, empty and full shells."""
+    S = _system(norb, na, nb, 5, sa, sb)
+    assert S.nnz() == _count_connected_brute(S)
+
+
+def test_nnz_equals_dense_structure_and_row_terms():
+    """On a small basis the count equals the number of structurally connected
+    entries of the dense H (pairs within two electrons, whatever their value),
+    and row_terms gives the per-row counts."""
+    S = _system(6, 3, 2, 9, 14, 12)
+    A, B = S.alpha, S.beta
+    z = np.zeros(S.N, dtype=np.int64)
+    for I in range(S.N):
+        ia, ib = divmod(I, S.nb)
+        for J in range(S.N):
+            ja, jb = divmod(J, S.nb)
+            d = (bin(int(A[ia]) ^ int(A[ja])).count("1") + bin(int(B[ib]) ^ int(B[jb])).count("1")) // 2
+            z[I] += d <= 2
+    assert z.sum() == S.nnz()
+    assert np.array_equal(S.row_terms(np.arange(S.N)), z)
+
+
+# ---------------------------------------------------------------- componentwise bound
+@pytest.mark.parametrize("norb,na,nb,sa,sb,shift", [
+    (6, 3, 3, None, None, 0.0), (7, 3, 2, 20, None, -3.5), (6, 2, 2, 10, 11, 12.0),
+])
+def test_sigma_abs_equals_dense_magnitudes(norb, na, nb, sa, sb, shift):
+    """(|H - shift I| |x|)_I from the table walk equals the same product formed
+    with the brute-force dense H (all pairs, no tables), at every row."""
+    S = _system(norb, na, nb, 17, sa, sb)
+    x = np.random.default_rng(3).standard_normal(S.N)
+    Hd = S.dense_h()
+    ref = np.abs(Hd - shift * np.eye(S.N)) @ np.abs(x)
+    got = S.sigma_abs_at(x, np.arange(S.N), shift)
+    assert np.allclose(got, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+def test_sigma_abs_bounds_rounding_of_float32_product():
+    """The bound holds for a plain FP32 evaluation of (H - shift) x32 (numpy,
+    rows summed in FP32): |y32 - y64|_I <= 2 (z_I + 2) u32 (|H - shift||x32|)_I."""
+    S = _system(7, 3, 3, 21)
+    shift = float(S.diag().min())
+    x = np.random.default_rng(4).standard_normal(S.N).astype(np.float32).astype(np.float64)
+    Hs = S.dense_h() - shift * np.eye(S.N)
+    y64 = Hs @ x
+    y32 = (Hs.astype(np.float32) @ x.astype(np.float32)).astype(np.float64)
+    bound = 2 * (S.row_terms(np.arange(S.N)) + 2) * 2.0 ** -24 * S.sigma_abs_at(x, np.arange(S.N), shift)
+    assert np.all(np.abs(y32 - y64) <= bound)

@@ -1,6 +1,8 @@
 """Serving loop (continuous batching of whole solves): admission by HBM
 budget, concurrent requests on their own streams, and results that do not
 depend on the mix."""
+import time
+
 import numpy as np
 import pytest
 
@@ -80,6 +82,15 @@ def test_serve_alone_vs_mix_identical():
         assert a["report"]["iterations"] == m["report"]["iterations"]
         assert m["ndet"] == W.alpha.size * W.beta.size
         assert 0 < m["peak_bytes"] <= m["region_bytes"]
+    # the mix really ran concurrently: some requests' [admission, completion)
+    # intervals overlap, and some request was admitted while another was running
+    iv = sorted((m["admit_at_ms"], m["done_at_ms"]) for m in mix)
+    overlaps = sum(1 for i in range(len(iv)) for j in range(i + 1, len(iv)) if iv[j][0] < iv[i][1])
+    assert overlaps >= 1, iv
+    assert any(a0 < b0 < a1 for (a0, a1) in iv for (b0, _) in iv), iv
+    # alone, one worker: no two requests overlap
+    iv1 = sorted((a["admit_at_ms"], a["done_at_ms"]) for a in alone)
+    assert all(iv1[i + 1][0] >= iv1[i][1] for i in range(len(iv1) - 1))
 
 
 @pytest.mark.gpu
@@ -127,3 +138,45 @@ def test_serve_rejects_request_larger_than_budget():
         submit(s, W)
     assert ei.value.status == -5
     s.close()
+
+
+@pytest.mark.gpu
+def test_serve_small_request_passes_a_head_that_does_not_fit():
+    """With the slab taken by a running request, a queued request too large for
+    the remaining space does not hold back a smaller one that fits."""
+    reqs = small_stream(12, seed=7600)
+    by = sorted(reqs, key=lambda W: W.alpha.size * W.beta.size)
+    small, big = by[0], by[-1]
+    e_small, e_big = estimate(small), estimate(big)
+    budget = e_big + e_small  # the big one running leaves room for one small one only
+    s = sbd.Server(budget, 3)
+    t_run = submit(s, big)
+    t_head = submit(s, big)      # cannot fit while the first one runs
+    t_small = submit(s, small)   # fits beside the running one
+    r_small, r_run, r_head = s.wait(t_small), s.wait(t_run), s.wait(t_head)
+    s.close()
+    assert r_small["status"] == r_run["status"] == r_head["status"] == 0
+    assert r_small["admit_at_ms"] < r_head["admit_at_ms"]
+
+
+@pytest.mark.gpu
+def test_serve_destroy_fails_queued_waiters():
+    """Destroying a server while a thread waits on a queued request hands that
+    thread an SBD_ERR_STATE result instead of leaving it blocked."""
+    import threading
+    reqs = small_stream(4, seed=7700)
+    big = max(reqs, key=lambda W: W.alpha.size * W.beta.size)
+    s = sbd.Server(estimate(big), 1)
+    tickets = [submit(s, big) for _ in range(3)]
+    got = {}
+
+    def wait_last():
+        got["r"] = s.wait(tickets[-1])
+
+    th = threading.Thread(target=wait_last)
+    th.start()
+    time.sleep(0.2)  # the waiter is inside sbd_serve_wait by now
+    s.close()
+    th.join(timeout=60)
+    assert not th.is_alive()
+    assert got["r"]["status"] in (0, -8)
