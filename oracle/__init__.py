@@ -63,6 +63,16 @@ def lib():
         L.orc_hij.argtypes = [i32, P, P, d, ctypes.c_uint64, ctypes.c_uint64,
                               ctypes.c_uint64, ctypes.c_uint64]
         L.orc_hij.restype = d
+        L.orc_full_sort_unique.argtypes = [P, i64]
+        L.orc_full_sort_unique.restype = i64
+        L.orc_full_connections.argtypes = [P, i64, P, P, P]
+        L.orc_full_connections.restype = i32
+        L.orc_full_sigma.argtypes = [i32, P, P, d, P, i64, P, P, i32, P, P]
+        L.orc_full_sigma.restype = i32
+        L.orc_full_diag.argtypes = [i32, P, P, d, P, i64, P]
+        L.orc_full_diag.restype = i32
+        L.orc_full_dense_h.argtypes = [i32, P, P, d, P, i64, P]
+        L.orc_full_dense_h.restype = i32
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = i32
         _lib = L
@@ -213,6 +223,68 @@ class OracleSystem:
 
 
 # ---------------------------------------------------------------------------
+# Full-bitstring bases (Sec. II-F, Sec. III-F): arbitrary determinant lists
+# ---------------------------------------------------------------------------
+
+def full_sort_unique(dets) -> np.ndarray:
+    """Determinants as rows (alpha string, beta string), sorted by alpha then
+    beta ascending, duplicates removed."""
+    d = np.ascontiguousarray(np.asarray(dets, dtype=np.uint64).reshape(-1, 2)).copy()
+    k = lib().orc_full_sort_unique(_p(d), d.shape[0])
+    return d[:k].copy()
+
+
+class FullOracleSystem:
+    """A selected basis given as a list of determinants (one packed
+    spin-orbital string each: alpha word, beta word) with its Hamiltonian.
+    Connections come from comparing every pair of determinants; matrix
+    elements from the same generic Slater-Condon rules as OracleSystem."""
+
+    def __init__(self, norb, dets, h, eri, e_core):
+        self.norb = int(norb)
+        self.dets = full_sort_unique(dets)
+        self.N = self.dets.shape[0]
+        self.h = np.ascontiguousarray(h, dtype=np.float64)
+        self.eri = np.ascontiguousarray(eri, dtype=np.float64)
+        self.e_core = float(e_core)
+        rp = np.zeros(self.N + 1, dtype=np.int64)
+        lib().orc_full_connections(_p(self.dets), self.N, _p(rp), None, None)
+        nnz = int(rp[-1])
+        J = np.zeros(max(nnz, 1), dtype=np.int32)
+        deg = np.zeros(max(nnz, 1), dtype=np.int8)
+        lib().orc_full_connections(_p(self.dets), self.N, _p(rp), _p(J), _p(deg))
+        self.row_ptr, self.J, self.deg = rp, J[:nnz], deg[:nnz]
+
+    def _ham(self):
+        return (self.norb, _p(self.h), _p(self.eri), self.e_core, _p(self.dets), self.N)
+
+    def sigma(self, x: np.ndarray) -> np.ndarray:
+        """y = H x; x of shape (N,) or (nvec, N)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        X = x.reshape(-1, self.N)
+        Y = np.empty_like(X)
+        lib().orc_full_sigma(*self._ham(), _p(self.row_ptr), _p(self.J), X.shape[0], _p(X), _p(Y))
+        return Y.reshape(x.shape)
+
+    def diag(self) -> np.ndarray:
+        out = np.empty(self.N)
+        lib().orc_full_diag(*self._ham(), _p(out))
+        return out
+
+    def dense_h(self) -> np.ndarray:
+        """H over all determinant pairs, brute force (no connection lists)."""
+        if self.N > 20000:
+            raise ValueError("dense H only for small bases")
+        out = np.empty((self.N, self.N))
+        lib().orc_full_dense_h(*self._ham(), _p(out))
+        return out
+
+    def nnz(self) -> int:
+        """Stored terms of H: the diagonal plus every connection."""
+        return self.N + int(self.row_ptr[-1])
+
+
+# ---------------------------------------------------------------------------
 # Tier 0: operator definition of Eq. 3 on full spin-orbital strings (numpy)
 # ---------------------------------------------------------------------------
 
@@ -250,9 +322,15 @@ def tier0_dense_h(norb, alpha, beta, h, eri, e_core) -> np.ndarray:
     """
     alpha = sort_unique(alpha)
     beta = sort_unique(beta)
-    na, nb = alpha.size, beta.size
-    N = na * nb
-    full = np.array([int(a) | (int(b) << norb) for a in alpha for b in beta], dtype=np.int64)
+    dets = [(int(a), int(b)) for a in alpha for b in beta]
+    return tier0_dense_h_dets(norb, dets, h, eri, e_core)
+
+
+def tier0_dense_h_dets(norb, dets, h, eri, e_core) -> np.ndarray:
+    """tier0_dense_h over an explicit list of determinants (alpha string,
+    beta string), in the given order: row/column i is determinant dets[i]."""
+    N = len(dets)
+    full = np.array([int(a) | (int(b) << norb) for a, b in dets], dtype=np.int64)
     order = np.argsort(full)
     sorted_full = full[order]
     H = np.zeros((N, N))

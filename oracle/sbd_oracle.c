@@ -452,3 +452,116 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* Full-bitstring bases (Sec. II-F, Sec. III-F): an arbitrary list of  */
+/* determinants, each one packed spin-orbital string (alpha word,      */
+/* beta word), not a Cartesian product of alpha and beta strings.      */
+/* ------------------------------------------------------------------ */
+
+static int cmp_det(const void* a, const void* b) {
+    const uint64_t* x = (const uint64_t*)a;
+    const uint64_t* y = (const uint64_t*)b;
+    if (x[0] != y[0]) return x[0] < y[0] ? -1 : 1;
+    if (x[1] != y[1]) return x[1] < y[1] ? -1 : 1;
+    return 0;
+}
+
+/* Sort determinants (2 words each: alpha, beta) by alpha string, then beta
+ * string, ascending; remove duplicates; return the unique count. */
+int64_t orc_full_sort_unique(uint64_t* d, int64_t n) {
+    if (n <= 0) return 0;
+    qsort(d, (size_t)n, 2 * sizeof(uint64_t), cmp_det);
+    int64_t k = 1;
+    for (int64_t i = 1; i < n; ++i)
+        if (cmp_det(d + 2 * i, d + 2 * (k - 1)) != 0) {
+            d[2 * k] = d[2 * i];
+            d[2 * k + 1] = d[2 * i + 1];
+            ++k;
+        }
+    return k;
+}
+
+/*
+ * Connections of a determinant list by brute force over every pair: J is a
+ * neighbour of I (I != J) when the two differ by one or two electrons, i.e.
+ * popcount(I ^ J) over both words is 2 or 4 (the Slater-Condon neighbourhood,
+ * Eq. 4).  CSR rows sorted by J; deg = electrons moved (1 or 2).  With J and
+ * deg NULL only the row pointers are written.
+ */
+int orc_full_connections(const uint64_t* d, int64_t n, int64_t* rp, int32_t* J, int8_t* deg) {
+    rp[0] = 0;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            int x = popc(d[2 * i] ^ d[2 * j]) + popc(d[2 * i + 1] ^ d[2 * j + 1]);
+            c += (j != i && (x == 2 || x == 4));
+        }
+        rp[i + 1] = c;
+    }
+    for (int64_t i = 0; i < n; ++i) rp[i + 1] += rp[i];
+    if (!J && !deg) return ORC_OK;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = rp[i];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            int x = popc(d[2 * i] ^ d[2 * j]) + popc(d[2 * i + 1] ^ d[2 * j + 1]);
+            if (x == 2 || x == 4) {
+                if (J) J[c] = (int32_t)j;
+                if (deg) deg[c] = (int8_t)(x / 2);
+                ++c;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* y = H x over a determinant list (nvec vectors, [v][I]), from its connections. */
+int orc_full_sigma(int norb, const double* h, const double* eri, double e_core,
+                   const uint64_t* d, int64_t n, const int64_t* rp, const int32_t* J,
+                   int nvec, const double* x, double* y) {
+    if (nvec < 1) return ORC_ERR;
+    ham_t H = {norb, h, eri, e_core};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        det_t I = {{d[2 * i], d[2 * i + 1]}};
+        double hd = hij(&H, &I, &I);
+        for (int v = 0; v < nvec; ++v) y[v * n + i] = hd * x[v * n + i];
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            int64_t j = J[e];
+            det_t K = {{d[2 * j], d[2 * j + 1]}};
+            double hv = hij(&H, &I, &K);
+            for (int v = 0; v < nvec; ++v) y[v * n + i] += hv * x[v * n + j];
+        }
+    }
+    return ORC_OK;
+}
+
+/* Diagonal H_II of a determinant list. */
+int orc_full_diag(int norb, const double* h, const double* eri, double e_core,
+                  const uint64_t* d, int64_t n, double* out) {
+    ham_t H = {norb, h, eri, e_core};
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        det_t I = {{d[2 * i], d[2 * i + 1]}};
+        out[i] = hij(&H, &I, &I);
+    }
+    return ORC_OK;
+}
+
+/* Dense H over every pair of a determinant list (no connection lists). */
+int orc_full_dense_h(int norb, const double* h, const double* eri, double e_core,
+                     const uint64_t* d, int64_t n, double* out) {
+    ham_t H = {norb, h, eri, e_core};
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i) {
+        det_t I = {{d[2 * i], d[2 * i + 1]}};
+        for (int64_t j = 0; j < n; ++j) {
+            det_t K = {{d[2 * j], d[2 * j + 1]}};
+            out[i * n + j] = hij(&H, &I, &K);
+        }
+    }
+    return ORC_OK;
+}

@@ -207,6 +207,91 @@ def make_config(name: str, nstr: int | None = None) -> Workload:
                     meta=dict(seeds=c["seeds"], nstr=k))
 
 
+def sample_determinants(norb: int, n_alpha: int, n_beta: int, count: int, seed: int,
+                        decay: float = LEVEL_DECAY) -> np.ndarray:
+    """Unique determinants (rows: alpha string, beta string) drawn without
+    replacement, sorted by alpha then beta string: a stand-in for a list of
+    sampled full spin-orbital bitstrings that is not a Cartesian product.
+
+    P(det) is proportional to exp(-decay * (level_alpha + level_beta)); the
+    Aufbau determinant is always included.  Each candidate draws its alpha and
+    its beta excitation independently (level k with probability proportional
+    to C(n,k) C(norb-n,k) exp(-decay k), then k holes and k particles
+    uniformly), and the first occurrence of each determinant is kept.
+    """
+    total = math.comb(norb, n_alpha) * math.comb(norb, n_beta)
+    count = min(int(count), total)
+    if count <= 0:
+        return np.zeros((0, 2), dtype=np.uint64)
+    rng = np.random.default_rng(seed)
+    one = np.uint64(1)
+
+    def draw(n, M):
+        kmax = min(n, norb - n)
+        ks = np.arange(kmax + 1)
+        wk = np.array([math.comb(n, k) * math.comb(norb - n, k) * math.exp(-decay * k) for k in ks])
+        kk = rng.choice(kmax + 1, size=M, p=wk / wk.sum())
+        holes = np.argsort(rng.random((M, max(n, 1))), axis=1)[:, :kmax].astype(np.uint64)
+        parts = (np.argsort(rng.random((M, max(norb - n, 1))), axis=1)[:, :kmax] + n).astype(np.uint64)
+        cand = np.full(M, np.uint64((1 << n) - 1), dtype=np.uint64)
+        for j in range(kmax):
+            sel = kk > j
+            cand[sel] = (cand[sel] & ~(one << holes[sel, j])) | (one << parts[sel, j])
+        return cand
+
+    aufbau = ((1 << n_alpha) - 1, (1 << n_beta) - 1)
+    chosen, seen = [aufbau], {aufbau}
+    while len(chosen) < count:
+        M = max(1024, 2 * (count - len(chosen)))
+        ca, cb = draw(n_alpha, M), draw(n_beta, M)
+        for a, b in zip(ca.tolist(), cb.tolist()):
+            if (a, b) not in seen:
+                seen.add((a, b))
+                chosen.append((a, b))
+                if len(chosen) == count:
+                    break
+    out = np.array(sorted(chosen), dtype=np.uint64)
+    return out.reshape(-1, 2)
+
+
+@dataclass
+class FullWorkload:
+    """A full-bitstring workload: an explicit determinant list."""
+    name: str
+    norb: int
+    n_alpha: int
+    n_beta: int
+    dets: np.ndarray  # (N, 2) uint64: alpha string, beta string
+    h: np.ndarray
+    eri: np.ndarray
+    e_core: float
+    nroots: int = 1
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ndet(self) -> int:
+        return int(self.dets.shape[0])
+
+
+# Full-bitstring workloads: (norb, n per spin, determinants, roots, seeds (integrals, dets)).
+FULL_CONFIGS = {
+    "full16": dict(norb=16, n=8, ndet=100000, nroots=1, seeds=(102, 5001)),
+    "full26": dict(norb=26, n=7, ndet=400000, nroots=1, seeds=(103, 5002)),
+}
+
+
+def make_full_config(name: str, ndet: int | None = None) -> FullWorkload:
+    """A named full-bitstring workload (same integrals as the alpha x beta
+    workload of the same orbital count), optionally with fewer determinants."""
+    c = FULL_CONFIGS[name]
+    si, sd = c["seeds"]
+    h, eri, ecore = make_integrals(c["norb"], si)
+    n = ndet if ndet is not None else c["ndet"]
+    d = sample_determinants(c["norb"], c["n"], c["n"], n, sd)
+    return FullWorkload(name, c["norb"], c["n"], c["n"], d, h, eri, ecore, c["nroots"],
+                        meta=dict(seeds=c["seeds"], ndet=n))
+
+
 def serving_stream(nreq: int = 256, seed: int = 5000, rate: float = 20.0,
                    norb_range=(12, 32), ndet_range=(1e4, 2e7)):
     """Request descriptors of the serving workload (no arrays, cheap).
