@@ -168,6 +168,29 @@ int sbd_sigma(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h,
               const void* c, void* sigma, int layout, void* stream);
 
 /*
+ * sbd_sigma without device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, semantics, layouts and results as
+ * sbd_sigma (the same kernels and launch configuration, so the output is
+ * bitwise that of sbd_sigma); only the workspace differs: a static device
+ * array of SBD_NOALLOC_SCRATCH_BYTES that each GPU holds from the first call
+ * on it until the process ends.  The call makes no hipMalloc/hipFree and
+ * allocates nothing else on the device.
+ *   The workspace need is 2 * N * (layout ? nvec : 1) * (8 for FP64, 4 for
+ *   FP32) bytes; a larger need fails with SBD_ERR_NOMEM before any device
+ *   work.  A handle assembled in prec (sbd_ham_assemble) needs no workspace.
+ *   All calls on one device share its array: calls that overlap on one GPU
+ *   (other streams or threads) race and must be serialised by the caller;
+ *   calls ordered on one stream are safe.  The array keeps the last call's
+ *   contents; nothing has to be cleared between calls.
+ * Errors: those of sbd_sigma; SBD_ERR_NOMEM (workspace above the maximum).
+ */
+#define SBD_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int sbd_sigma_noalloc(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h,
+                      int nvec, int prec, double shift,
+                      const void* c, void* sigma, int layout, void* stream);
+
+/*
  * Autotuner of the sigma launch configuration (the schedule of the sigma
  * kernels: rows per wavefront of the same-spin stream kernel, LDS budget of
  * the alpha-beta kernel).  Times a fixed candidate set on scratch vectors of

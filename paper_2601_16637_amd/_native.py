@@ -28,7 +28,7 @@ EXPORTED = ["sbd_last_error", "sbd_version", "sbd_source_hash", "sbd_release_cac
             "sbd_memory_stats", "sbd_build_basis", "sbd_basis_sizes",
             "sbd_basis_strings", "sbd_free_basis", "sbd_build_excitations", "sbd_exc_count",
             "sbd_exc_export", "sbd_free_exc", "sbd_set_hamiltonian", "sbd_ham_diag",
-            "sbd_free_ham", "sbd_sigma", "sbd_sigma_timed", "sbd_autotune", "sbd_get_tune", "sbd_set_tune", "sbd_gram", "sbd_map_vectors",
+            "sbd_free_ham", "sbd_sigma", "sbd_sigma_noalloc", "sbd_sigma_timed", "sbd_autotune", "sbd_get_tune", "sbd_set_tune", "sbd_gram", "sbd_map_vectors",
             "sbd_ham_assemble", "sbd_ham_release_assembled", "sbd_ham_assembled",
             "sbd_davidson_default_opts", "sbd_davidson", "sbd_serve_estimate", "sbd_serve_create",
             "sbd_serve_submit", "sbd_serve_wait", "sbd_serve_destroy"]
@@ -134,6 +134,7 @@ def load():
     L.sbd_free_ham.argtypes = [P]
     L.sbd_free_ham.restype = None
     L.sbd_sigma.argtypes = [P, P, P, i32, i32, d, P, P, i32, P]
+    L.sbd_sigma_noalloc.argtypes = [P, P, P, i32, i32, d, P, P, i32, P]
     L.sbd_sigma_timed.argtypes = [P, P, P, i32, i32, d, P, P, i32, P, P]
     L.sbd_autotune.argtypes = [P, P, P, i32, i32, i32, P, ctypes.POINTER(d)]
     L.sbd_get_tune.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -336,6 +337,15 @@ def sigma(ham: Hamiltonian, c, out, nvec: int = 1, prec: int = FP64, shift: floa
     """out = (H - shift) c on device buffers (sbd_sigma)."""
     check(load().sbd_sigma(ham.basis._h, ham.exc._h, ham._h, int(nvec), int(prec), float(shift),
                            _dptr(c), _dptr(out), int(layout), _stream(stream)))
+    return out
+
+
+def sigma_noalloc(ham: Hamiltonian, c, out, nvec: int = 1, prec: int = FP64, shift: float = 0.0,
+                  layout: int = 0, stream=None):
+    """out = (H - shift) c with the workspace in the library's static device
+    scratch instead of a handle-owned buffer (sbd_sigma_noalloc)."""
+    check(load().sbd_sigma_noalloc(ham.basis._h, ham.exc._h, ham._h, int(nvec), int(prec), float(shift),
+                                   _dptr(c), _dptr(out), int(layout), _stream(stream)))
     return out
 
 

@@ -490,9 +490,10 @@ void* ham_workspace(const sbd_ham* Hc, hipStream_t st, size_t bytes, int* rc) {
 }
 }  // namespace sbd
 
-static int sigma_entry(const sbd_basis* b, const sbd_exc* x, const sbd_ham* H, int nvec, int prec,
-                       double shift, const void* c, void* sigma, int layout, void* stream,
-                       hipEvent_t* ev) {
+namespace sbd {
+// Argument checks shared by the sigma entry points (no device work).
+int sigma_validate(const sbd_basis* b, const sbd_exc* x, const sbd_ham* H, int nvec, int prec,
+                   double shift, const void* c, const void* sigma, int layout) {
     if (!b || !x || !H || !c || !sigma) return fail(SBD_ERR_ARG, "null argument");
     if (x->basis_id != b->id || H->basis_id != b->id || H->exc_id != x->id)
         return fail(SBD_ERR_STATE, "handles do not belong together");
@@ -504,8 +505,16 @@ static int sigma_entry(const sbd_basis* b, const sbd_exc* x, const sbd_ham* H, i
     if (c == sigma) return fail(SBD_ERR_ARG, "c and sigma must not alias");
     if (layout == 1 && nvec != 1 && nvec != 2 && nvec != 4 && nvec != 8)
         return fail(SBD_ERR_ARG, "interleaved layout supports nvec in {1, 2, 4, 8}");
+    return SBD_OK;
+}
+}  // namespace sbd
+
+static int sigma_entry(const sbd_basis* b, const sbd_exc* x, const sbd_ham* H, int nvec, int prec,
+                       double shift, const void* c, void* sigma, int layout, void* stream,
+                       hipEvent_t* ev) {
+    int rc = sigma_validate(b, x, H, nvec, prec, shift, c, sigma, layout);
+    if (rc) return rc;
     const int64_t N = H->na * H->nb;
-    int rc = 0;
     void* ws = ham_workspace(H, (hipStream_t)stream,
                              sigma_workspace_bytes(N, nvec, layout, prec == SBD_FP64 ? 8 : 4), &rc);
     if (!ws && N > 0) return rc;

@@ -44,10 +44,6 @@
 
 namespace sbd {
 
-int sigma_internal(const sbd_exc* x, const sbd_ham* H, int nvec, int prec, double shift,
-                   const void* c, void* y, int layout, void* ws, hipStream_t st,
-                   hipEvent_t* ev = nullptr);
-
 // Cyclic Jacobi eigensolver for a symmetric m x m matrix (row-major).  On exit
 // w holds eigenvalues ascending and Z (row-major, column k = eigenvector k).
 static void jacobi_eigh(int m, std::vector<double> A, std::vector<double>& w,

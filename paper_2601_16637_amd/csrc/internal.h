@@ -280,6 +280,13 @@ hipError_t launch_spmv(const int64_t* rp, const int32_t* col, const T* val, int6
 
 // Workspace bytes needed by launch_sigma for nvec vectors of type T.
 size_t sigma_workspace_bytes(int64_t N, int nvec, int layout, size_t elem);
+// Argument checks of the sigma entry points (abi.cpp; host only, no device work).
+int sigma_validate(const sbd_basis* b, const sbd_exc* x, const sbd_ham* H, int nvec, int prec,
+                   double shift, const void* c, const void* sigma, int layout);
+// sigma through the assembled CSR when H holds it for prec, else the five-launch
+// matrix-free product with ws as its workspace (sigma_workspace_bytes); ev nullable.
+int sigma_internal(const sbd_exc* x, const sbd_ham* H, int nvec, int prec, double shift,
+                   const void* c, void* y, int layout, void* ws, hipStream_t st, hipEvent_t* ev = nullptr);
 
 // ev (nullable): six events recorded on st around the five launches of the
 // first vector (transpose, alpha stream, beta stream, alpha-beta, transpose-add).

@@ -17,9 +17,6 @@
 
 namespace sbd {
 
-int sigma_internal(const sbd_exc* x, const sbd_ham* H, int nvec, int prec, double shift,
-                   const void* c, void* y, int layout, void* ws, hipStream_t st,
-                   hipEvent_t* ev = nullptr);
 hipError_t launch_fill_pattern(void* p, int64_t n, int prec, hipStream_t st);
 
 namespace {
