@@ -350,6 +350,114 @@ int sbd_davidson(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h, int nro
                  const sbd_davidson_opts* opts, double* energies, double* vectors,
                  sbd_davidson_report* report, void* stream);
 
+/* ------------------------------------------------------------------ SQD loop
+ * Successive solves of a sample-based quantum diagonalisation run (Sec. I: the
+ * classical diagonalisation is repeated as the configuration set is refined).
+ * Step s takes the first step_samples[s] sampled configurations (samples:
+ * host array of 2 * nsamples words, alpha string then beta string of each
+ * sampled determinant, in the order they were drawn, duplicates allowed),
+ * forms the selected basis as the Cartesian product of their distinct alpha
+ * and beta strings (Sec. II-B; with spin_union, when n_alpha == n_beta, both
+ * spins use every sampled string), builds tables and Hamiltonian, and solves
+ * for the lowest nroots eigenpairs with sbd_davidson.  With warm_start each
+ * step after the first starts from the previous step's eigenvectors carried
+ * into the new basis (sbd_map_vectors; Sec. II-C admits any start vector).
+ * energies: host, nsteps x nroots (roots beyond a step's N are 0).  steps
+ * (nullable): host array of nsteps reports.  step_samples must be
+ * non-decreasing, so the bases are nested and the lowest energy cannot rise
+ * from one step to the next (variational principle).
+ * Errors: SBD_ERR_ARG, SBD_ERR_INTEGRALS, those of the calls it makes.
+ */
+typedef struct {
+    sbd_davidson_opts davidson;  /* per-step solve options (guess must be unset) */
+    int warm_start;              /* default 1 */
+    int spin_union;              /* default 0 */
+} sbd_sqd_opts;
+typedef struct {
+    int status;                  /* sbd_davidson status of the step (0 or SBD_NOT_CONVERGED) */
+    int warm;                    /* 1 if started from the previous step's vectors */
+    int64_t samples;             /* configurations taken in */
+    int64_t n_alpha_str, n_beta_str, ndet;
+    int iterations, sigma_calls;
+    double residual;             /* largest final residual norm */
+    double setup_ms, solve_ms;   /* basis, tables, Hamiltonian (+ transfer); Davidson */
+} sbd_sqd_step;
+void sbd_sqd_default_opts(sbd_sqd_opts* o);
+int sbd_sqd_run(int norb, int n_alpha, int n_beta, const double* h1, const double* eri, double e_core,
+                const uint64_t* samples, int64_t nsamples, const int64_t* step_samples, int nsteps,
+                int nroots, const sbd_sqd_opts* opts, double* energies, sbd_sqd_step* steps, void* stream);
+
+/* ------------------------------------------------------------------ full bitstrings
+ * Full-bitstring representation (Sec. II-F "Support for Half- and
+ * Full-Bitstring Paths", Sec. III-F "Extension to Full-Bitstring
+ * Representations"): the selected basis is an arbitrary list of determinants,
+ * not a Cartesian product of alpha and beta strings.  A determinant is one
+ * packed spin-orbital string held in two uint64 words, {alpha string, beta
+ * string} (alpha orbital p = bit p of word 0, beta orbital p = bit p of word
+ * 1); phases follow the same convention as the alpha x beta path (alpha
+ * creators, ascending, before beta creators, ascending).  Excitations are
+ * generated from the bitstrings by popcounts, bit scans and parities, and
+ * matrix elements are formed from them on the fly in every sigma (Eq. 3, the
+ * Slater-Condon rules of Eq. 4), with the diagonal cached (Sec. II-E).
+ */
+typedef struct sbd_fbasis sbd_fbasis;  /* determinant list and its connections */
+typedef struct sbd_fham sbd_fham;      /* integrals and diagonal over an sbd_fbasis */
+
+/*
+ * Build a determinant list: dets is a host array of 2 * ndet words (alpha,
+ * beta per determinant), any order, duplicates allowed; each alpha word must
+ * have n_alpha set bits and each beta word n_beta, all below norb.  The list
+ * is sorted by (alpha word, beta word) ascending and deduplicated on the
+ * device; determinant I of every later call is row I of that order.  The
+ * connections of each determinant (the others that differ from it by one or
+ * two electrons, Eq. 4) are built too: CSR rows sorted by ket index.
+ * Errors: SBD_ERR_NORB, SBD_ERR_ARG (ndet < 1, ndet > 2^30, bad counts),
+ * SBD_ERR_STRING, SBD_ERR_NOMEM, SBD_ERR_HIP.
+ */
+int sbd_full_build_basis(int norb, int n_alpha, int n_beta, const uint64_t* dets, int64_t ndet,
+                         void* stream, sbd_fbasis** out);
+/* Unique determinants, stored connections (each ordered pair once) and
+ * distinct alpha strings of a list; each pointer nullable. */
+int sbd_full_basis_sizes(const sbd_fbasis* b, int64_t* ndet, int64_t* nconn, int64_t* nalpha);
+/* Host copies (each nullable): the sorted determinants (2 * ndet words), the
+ * connection row pointers (ndet + 1), kets (nconn) and electrons moved (1 or
+ * 2 per connection). */
+int sbd_full_basis_export(const sbd_fbasis* b, uint64_t* dets, int64_t* row_ptr, int32_t* J, int8_t* deg);
+void sbd_free_full_basis(sbd_fbasis* b);
+
+/*
+ * Hamiltonian over a determinant list (Eq. 3): h1 norb*norb and eri norb^4
+ * host arrays as in sbd_set_hamiltonian, e_core added to every diagonal
+ * element.  Uploads the integrals, derives the single-excitation spectator
+ * tables (ai|kk), (ak|ki) and caches the FP64 diagonal H_II (Sec. II-E).
+ * Errors: SBD_ERR_INTEGRALS, SBD_ERR_ARG, SBD_ERR_NOMEM, SBD_ERR_HIP.
+ */
+int sbd_full_set_hamiltonian(const sbd_fbasis* b, const double* h1, const double* eri, double e_core,
+                             void* stream, sbd_fham** out);
+/* Copy the FP64 diagonal H_II (ndet values) into a caller-owned device buffer. */
+int sbd_full_ham_diag(const sbd_fham* h, double* diag_dev, void* stream);
+void sbd_free_full_ham(sbd_fham* h);
+
+/*
+ * sigma = (H - shift I) c over a determinant list (apply_H of Sec. II-B over
+ * the full-bitstring path).  nvec, prec, layout and ownership as in
+ * sbd_sigma, N = ndet.  Every connection's element is formed in FP64 from the
+ * two bitstrings; in SBD_FP32 it is rounded once to FP32 and the gathers and
+ * accumulation are FP32.  One wavefront per row sums in a fixed order: results
+ * are bitwise reproducible.  No workspace.
+ * Errors: SBD_ERR_ARG, SBD_ERR_STATE (h built on another list), SBD_ERR_HIP.
+ */
+int sbd_full_sigma(const sbd_fbasis* b, const sbd_fham* h, int nvec, int prec, double shift,
+                   const void* c, void* sigma, int layout, void* stream);
+/*
+ * Lowest nroots eigenpairs over a determinant list (Eq. 2): the Davidson
+ * iteration of sbd_davidson (same options, report and outputs, vectors
+ * nroots x ndet) with sbd_full_sigma as its sigma.  use_autotune has no
+ * effect (the full-bitstring sigma has one launch configuration).
+ */
+int sbd_full_davidson(const sbd_fbasis* b, const sbd_fham* h, int nroots, const sbd_davidson_opts* opts,
+                      double* energies, double* vectors, sbd_davidson_report* report, void* stream);
+
 /* ------------------------------------------------------------------ serving
  * Continuous batching of whole solves (one SQD iteration each: the classical
  * diagonalisation that follows every sampling round, Sec. I and Sec. II).

@@ -69,6 +69,8 @@ def lib():
         L.orc_full_connections.restype = i32
         L.orc_full_sigma.argtypes = [i32, P, P, d, P, i64, P, P, i32, P, P]
         L.orc_full_sigma.restype = i32
+        L.orc_full_sigma_rows.argtypes = [i32, P, P, d, P, i64, P, i64, P, P]
+        L.orc_full_sigma_rows.restype = i32
         L.orc_full_diag.argtypes = [i32, P, P, d, P, i64, P]
         L.orc_full_diag.restype = i32
         L.orc_full_dense_h.argtypes = [i32, P, P, d, P, i64, P]
@@ -240,13 +242,18 @@ class FullOracleSystem:
     Connections come from comparing every pair of determinants; matrix
     elements from the same generic Slater-Condon rules as OracleSystem."""
 
-    def __init__(self, norb, dets, h, eri, e_core):
+    def __init__(self, norb, dets, h, eri, e_core, connections=True):
+        """connections=False skips the all-pairs connection lists (then only
+        diag, dense_h and sigma_rows are available)."""
         self.norb = int(norb)
         self.dets = full_sort_unique(dets)
         self.N = self.dets.shape[0]
         self.h = np.ascontiguousarray(h, dtype=np.float64)
         self.eri = np.ascontiguousarray(eri, dtype=np.float64)
         self.e_core = float(e_core)
+        self.row_ptr = self.J = self.deg = None
+        if not connections:
+            return
         rp = np.zeros(self.N + 1, dtype=np.int64)
         lib().orc_full_connections(_p(self.dets), self.N, _p(rp), None, None)
         nnz = int(rp[-1])
@@ -269,6 +276,15 @@ class FullOracleSystem:
     def diag(self) -> np.ndarray:
         out = np.empty(self.N)
         lib().orc_full_diag(*self._ham(), _p(out))
+        return out
+
+    def sigma_rows(self, x: np.ndarray, idx) -> np.ndarray:
+        """(H x)_I at the rows idx only, each row's neighbours found by
+        comparing it with every determinant (no connection lists)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        out = np.empty(idx.size)
+        lib().orc_full_sigma_rows(*self._ham(), _p(idx), idx.size, _p(x), _p(out))
         return out
 
     def dense_h(self) -> np.ndarray:

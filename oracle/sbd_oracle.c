@@ -539,6 +539,29 @@ int orc_full_sigma(int norb, const double* h, const double* eri, double e_core,
     return ORC_OK;
 }
 
+/* y_I = sum_J H_IJ x_J for the rows I = idx[0..m) only (one vector): each
+ * row's neighbours are found by comparing it with every determinant of the
+ * list (for spot checks of lists too large for the all-pairs connections). */
+int orc_full_sigma_rows(int norb, const double* h, const double* eri, double e_core,
+                        const uint64_t* d, int64_t n, const int64_t* idx, int64_t m,
+                        const double* x, double* y) {
+    ham_t H = {norb, h, eri, e_core};
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t r = 0; r < m; ++r) {
+        const int64_t i = idx[r];
+        det_t I = {{d[2 * i], d[2 * i + 1]}};
+        double acc = hij(&H, &I, &I) * x[i];
+        for (int64_t j = 0; j < n; ++j) {
+            int nd = popc(d[2 * i] ^ d[2 * j]) + popc(d[2 * i + 1] ^ d[2 * j + 1]);
+            if (j == i || (nd != 2 && nd != 4)) continue;
+            det_t K = {{d[2 * j], d[2 * j + 1]}};
+            acc += hij(&H, &I, &K) * x[j];
+        }
+        y[r] = acc;
+    }
+    return ORC_OK;
+}
+
 /* Diagonal H_II of a determinant list. */
 int orc_full_diag(int norb, const double* h, const double* eri, double e_core,
                   const uint64_t* d, int64_t n, double* out) {

@@ -31,7 +31,10 @@ EXPORTED = ["sbd_last_error", "sbd_version", "sbd_source_hash", "sbd_release_cac
             "sbd_free_ham", "sbd_sigma", "sbd_sigma_noalloc", "sbd_sigma_timed", "sbd_autotune", "sbd_get_tune", "sbd_set_tune", "sbd_gram", "sbd_map_vectors",
             "sbd_ham_assemble", "sbd_ham_release_assembled", "sbd_ham_assembled",
             "sbd_davidson_default_opts", "sbd_davidson", "sbd_serve_estimate", "sbd_serve_create",
-            "sbd_serve_submit", "sbd_serve_wait", "sbd_serve_destroy"]
+            "sbd_serve_submit", "sbd_serve_wait", "sbd_serve_destroy",
+            "sbd_full_build_basis", "sbd_full_basis_sizes", "sbd_full_basis_export", "sbd_free_full_basis",
+            "sbd_full_set_hamiltonian", "sbd_full_ham_diag", "sbd_free_full_ham", "sbd_full_sigma",
+            "sbd_full_davidson", "sbd_sqd_default_opts", "sbd_sqd_run"]
 
 
 class SBDError(RuntimeError):
@@ -74,6 +77,20 @@ class DavidsonReport(ctypes.Structure):
                     t_workspace_ms=self.t_workspace_ms, t_autotune_ms=self.t_autotune_ms,
                     theta_history=list(self.theta_history[:n]),
                     time_history_ms=list(self.time_history_ms[:n]))
+
+
+class SqdOpts(ctypes.Structure):
+    _fields_ = [("davidson", DavidsonOpts), ("warm_start", ctypes.c_int), ("spin_union", ctypes.c_int)]
+
+
+class SqdStep(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("warm", ctypes.c_int), ("samples", ctypes.c_int64),
+                ("n_alpha_str", ctypes.c_int64), ("n_beta_str", ctypes.c_int64), ("ndet", ctypes.c_int64),
+                ("iterations", ctypes.c_int), ("sigma_calls", ctypes.c_int), ("residual", ctypes.c_double),
+                ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class Request(ctypes.Structure):
@@ -149,6 +166,20 @@ def load():
     L.sbd_davidson_default_opts.restype = None
     L.sbd_davidson.argtypes = [P, P, P, i32, ctypes.POINTER(DavidsonOpts), P, P,
                                ctypes.POINTER(DavidsonReport), P]
+    L.sbd_full_build_basis.argtypes = [i32, i32, i32, P, i64, P, PP]
+    L.sbd_full_basis_sizes.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.sbd_full_basis_export.argtypes = [P, P, P, P, P]
+    L.sbd_free_full_basis.argtypes = [P]
+    L.sbd_full_set_hamiltonian.argtypes = [P, P, P, d, P, PP]
+    L.sbd_full_ham_diag.argtypes = [P, P, P]
+    L.sbd_free_full_ham.argtypes = [P]
+    L.sbd_full_sigma.argtypes = [P, P, i32, i32, d, P, P, i32, P]
+    L.sbd_full_davidson.argtypes = [P, P, i32, ctypes.POINTER(DavidsonOpts), P, P,
+                                    ctypes.POINTER(DavidsonReport), P]
+    L.sbd_sqd_default_opts.argtypes = [ctypes.POINTER(SqdOpts)]
+    L.sbd_sqd_default_opts.restype = None
+    L.sbd_sqd_run.argtypes = [i32, i32, i32, P, P, d, P, i64, P, i32, i32, ctypes.POINTER(SqdOpts), P,
+                              ctypes.POINTER(SqdStep), P]
     L.sbd_serve_estimate.argtypes = [ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_size_t)]
     L.sbd_serve_create.argtypes = [ctypes.c_size_t, i32, PP]
     L.sbd_serve_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
@@ -401,6 +432,115 @@ def davidson(ham: Hamiltonian, nroots: int = 1, vectors=None, stream=None, **kw)
                                    ctypes.byref(o), _host(e), _dptr(vectors), ctypes.byref(rep),
                                    _stream(stream)))
     return e, rep.as_dict(nroots), st
+
+
+class FullBasis:
+    """Full-bitstring basis: an arbitrary determinant list (sbd_full_build_basis).
+    ``dets`` has one row per determinant: alpha string, beta string."""
+
+    def __init__(self, norb, n_alpha, n_beta, dets, stream=None):
+        L = load()
+        d = np.ascontiguousarray(np.asarray(dets, dtype=np.uint64).reshape(-1, 2))
+        h = ctypes.c_void_p()
+        check(L.sbd_full_build_basis(int(norb), int(n_alpha), int(n_beta), _host(d), d.shape[0],
+                                     _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.norb, self.n_alpha, self.n_beta = int(norb), int(n_alpha), int(n_beta)
+        n, c, g = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(L.sbd_full_basis_sizes(h, ctypes.byref(n), ctypes.byref(c), ctypes.byref(g)))
+        self.N, self.nconn, self.nalpha = n.value, c.value, g.value
+
+    def export(self):
+        """(sorted determinants (N, 2), row_ptr, J, electrons moved) on the host."""
+        d = np.zeros((self.N, 2), dtype=np.uint64)
+        rp = np.zeros(self.N + 1, dtype=np.int64)
+        J = np.zeros(max(self.nconn, 1), dtype=np.int32)
+        deg = np.zeros(max(self.nconn, 1), dtype=np.int8)
+        check(load().sbd_full_basis_export(self._h, _host(d), _host(rp), _host(J), _host(deg)))
+        return d, rp, J[:self.nconn], deg[:self.nconn]
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.sbd_free_full_basis(self._h)
+            self._h = None
+
+
+class FullHamiltonian:
+    """Integrals and cached diagonal over a determinant list (sbd_full_set_hamiltonian)."""
+
+    def __init__(self, basis: FullBasis, h1, eri, e_core, stream=None):
+        self.basis = basis
+        h1 = np.ascontiguousarray(h1, dtype=np.float64)
+        eri = np.ascontiguousarray(eri, dtype=np.float64)
+        n = basis.norb
+        if h1.size != n * n or eri.size != n ** 4:
+            raise ValueError("integral arrays have the wrong size for norb")
+        h = ctypes.c_void_p()
+        check(load().sbd_full_set_hamiltonian(basis._h, _host(h1), _host(eri), float(e_core),
+                                              _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def diag_into(self, out, stream=None):
+        check(load().sbd_full_ham_diag(self._h, _dptr(out), _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.sbd_free_full_ham(self._h)
+            self._h = None
+
+
+def full_sigma(ham: FullHamiltonian, c, out, nvec: int = 1, prec: int = FP64, shift: float = 0.0,
+               layout: int = 0, stream=None):
+    """out = (H - shift) c over a determinant list (sbd_full_sigma)."""
+    check(load().sbd_full_sigma(ham.basis._h, ham._h, int(nvec), int(prec), float(shift), _dptr(c),
+                                _dptr(out), int(layout), _stream(stream)))
+    return out
+
+
+def full_davidson(ham: FullHamiltonian, nroots: int = 1, vectors=None, stream=None, **kw):
+    """Lowest eigenpairs over a determinant list (sbd_full_davidson); options and
+    return value as davidson()."""
+    o = default_opts()
+    for k, v in kw.items():
+        if k == "guess":
+            o.guess = _dptr(v).value if v is not None else None
+            continue
+        if not hasattr(o, k):
+            raise TypeError(f"unknown Davidson option {k}")
+        setattr(o, k, v)
+    e = np.zeros(nroots, dtype=np.float64)
+    rep = DavidsonReport()
+    st = check(load().sbd_full_davidson(ham.basis._h, ham._h, int(nroots), ctypes.byref(o), _host(e),
+                                        _dptr(vectors), ctypes.byref(rep), _stream(stream)))
+    return e, rep.as_dict(nroots), st
+
+
+def sqd_run(norb, n_alpha, n_beta, h1, eri, e_core, samples, step_samples, nroots: int = 1,
+            warm_start: bool = True, spin_union: bool = False, stream=None, **kw):
+    """Successive solves on a growing set of sampled configurations
+    (sbd_sqd_run): step s uses the first step_samples[s] rows of ``samples``
+    (alpha string, beta string).  Keyword options are DavidsonOpts fields.
+    Returns (energies (nsteps, nroots), list of step reports)."""
+    smp = np.ascontiguousarray(np.asarray(samples, dtype=np.uint64).reshape(-1, 2))
+    steps_in = np.ascontiguousarray(step_samples, dtype=np.int64)
+    h = np.ascontiguousarray(h1, dtype=np.float64)
+    g = np.ascontiguousarray(eri, dtype=np.float64)
+    if h.size != norb * norb or g.size != norb ** 4:
+        raise ValueError("integral arrays have the wrong size for norb")
+    o = SqdOpts()
+    load().sbd_sqd_default_opts(ctypes.byref(o))
+    o.warm_start, o.spin_union = int(bool(warm_start)), int(bool(spin_union))
+    for k, v in kw.items():
+        if not hasattr(o.davidson, k) or k == "guess":
+            raise TypeError(f"unknown or unsupported option {k}")
+        setattr(o.davidson, k, v)
+    ns = steps_in.size
+    e = np.zeros((ns, nroots), dtype=np.float64)
+    reps = (SqdStep * ns)()
+    check(load().sbd_sqd_run(int(norb), int(n_alpha), int(n_beta), _host(h), _host(g), float(e_core), _host(smp),
+                             smp.shape[0], _host(steps_in), ns, int(nroots), ctypes.byref(o), _host(e), reps,
+                             _stream(stream)))
+    return e, [r.as_dict() for r in reps]
 
 
 def _opts(**kw) -> DavidsonOpts:

@@ -45,6 +45,35 @@ static int validate_strings(int norb, int nel, const uint64_t* s, int64_t n, con
     return SBD_OK;
 }
 
+int validate_integrals(int n, const double* h, const double* eri) {
+    double hmax = 0.0, gmax = 0.0;
+    for (int i = 0; i < n * n; ++i) {
+        if (!std::isfinite(h[i])) return fail(SBD_ERR_INTEGRALS, "h has a non-finite entry");
+        hmax = std::max(hmax, std::fabs(h[i]));
+    }
+    const size_t n4 = (size_t)n * n * n * n;
+    for (size_t i = 0; i < n4; ++i) {
+        if (!std::isfinite(eri[i])) return fail(SBD_ERR_INTEGRALS, "eri has a non-finite entry");
+        gmax = std::max(gmax, std::fabs(eri[i]));
+    }
+    const double th = 1e-10 * std::max(hmax, 1e-300), tg = 1e-10 * std::max(gmax, 1e-300);
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q)
+            if (std::fabs(h[p * n + q] - h[q * n + p]) > th)
+                return fail(SBD_ERR_INTEGRALS, "h is not symmetric");
+    auto G = [&](int p, int q, int r, int s) { return eri[(((size_t)p * n + q) * n + r) * n + s]; };
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q)
+            for (int r = 0; r < n; ++r)
+                for (int s = 0; s < n; ++s) {
+                    double v = G(p, q, r, s);
+                    if (std::fabs(v - G(q, p, r, s)) > tg || std::fabs(v - G(p, q, s, r)) > tg ||
+                        std::fabs(v - G(r, s, p, q)) > tg)
+                        return fail(SBD_ERR_INTEGRALS, "eri is not 8-fold symmetric");
+                }
+    return SBD_OK;
+}
+
 }  // namespace sbd
 
 using namespace sbd;
@@ -288,35 +317,6 @@ int sbd_exc_export(const sbd_exc* x, int spin, int kind, int64_t* row_ptr, int32
 void sbd_free_exc(sbd_exc* x) { delete x; }
 
 // ------------------------------------------------------------------ hamiltonian
-static int validate_integrals(int n, const double* h, const double* eri) {
-    double hmax = 0.0, gmax = 0.0;
-    for (int i = 0; i < n * n; ++i) {
-        if (!std::isfinite(h[i])) return fail(SBD_ERR_INTEGRALS, "h has a non-finite entry");
-        hmax = std::max(hmax, std::fabs(h[i]));
-    }
-    const size_t n4 = (size_t)n * n * n * n;
-    for (size_t i = 0; i < n4; ++i) {
-        if (!std::isfinite(eri[i])) return fail(SBD_ERR_INTEGRALS, "eri has a non-finite entry");
-        gmax = std::max(gmax, std::fabs(eri[i]));
-    }
-    const double th = 1e-10 * std::max(hmax, 1e-300), tg = 1e-10 * std::max(gmax, 1e-300);
-    for (int p = 0; p < n; ++p)
-        for (int q = 0; q < n; ++q)
-            if (std::fabs(h[p * n + q] - h[q * n + p]) > th)
-                return fail(SBD_ERR_INTEGRALS, "h is not symmetric");
-    auto G = [&](int p, int q, int r, int s) { return eri[(((size_t)p * n + q) * n + r) * n + s]; };
-    for (int p = 0; p < n; ++p)
-        for (int q = 0; q < n; ++q)
-            for (int r = 0; r < n; ++r)
-                for (int s = 0; s < n; ++s) {
-                    double v = G(p, q, r, s);
-                    if (std::fabs(v - G(q, p, r, s)) > tg || std::fabs(v - G(p, q, s, r)) > tg ||
-                        std::fabs(v - G(r, s, p, q)) > tg)
-                        return fail(SBD_ERR_INTEGRALS, "eri is not 8-fold symmetric");
-                }
-    return SBD_OK;
-}
-
 int sbd_set_hamiltonian(const sbd_basis* b, const sbd_exc* x, const double* h1, const double* eri,
                         double e_core, void* stream, sbd_ham** out) {
     if (!b || !x || !h1 || !eri || !out) return fail(SBD_ERR_ARG, "null argument");

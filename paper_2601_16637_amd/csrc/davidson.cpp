@@ -142,8 +142,7 @@ struct OwnedStream {
 };
 
 struct Solver {
-    const sbd_exc* x;
-    const sbd_ham* H;
+    const SigmaOp* op;
     hipStream_t st;
     int64_t N;
     int ms, k, keep;
@@ -180,7 +179,7 @@ struct Solver {
         if (e == hipSuccess) e = part.alloc(sizeof(double) * kPartRows * kRedBlocks);
         if (e == hipSuccess) e = small.alloc(sizeof(double) * kSmall);
         if (e == hipSuccess) e = idx.alloc(sizeof(int64_t) * (kRedBlocks + 1));
-        if (e == hipSuccess) e = sws.alloc(sigma_workspace_bytes(N, nvmax, nvmax > 1 ? 1 : 0, sizeof(double)));
+        if (e == hipSuccess) e = sws.alloc(op->ws_bytes(nvmax, nvmax > 1 ? 1 : 0, sizeof(double)));
         const bool stage64 = nvmax > 1 || use_graph;  // FP64 staging: block sigma or graph replays
         if (stage64 && e == hipSuccess) e = x64.alloc(sizeof(double) * (size_t)nvmax * N);
         if (stage64 && e == hipSuccess) e = y64.alloc(sizeof(double) * (size_t)nvmax * N);
@@ -205,11 +204,11 @@ struct Solver {
         int rc = SBD_OK;
         hipError_t e = hipSuccess;
         if (nv == 1) {
-            if (p64) return sigma_internal(x, H, c, SBD_FP64, 0.0, Vr(j), Wr(j), 0, sws.p, st);
+            if (p64) return op->apply(c, SBD_FP64, 0.0, Vr(j), Wr(j), 0, sws.p, st);
             // the Gram-Schmidt sweep may have written the FP32 copy already
             if (!(c == 1 && staged_row == j)) e = launch_f64_to_f32(Vr(j), x32.as<float>(), (int64_t)c * N, st);
             staged_row = -1;
-            if (e == hipSuccess) rc = sigma_internal(x, H, c, SBD_FP32, shift, x32.p, y32.p, 0, sws.p, st);
+            if (e == hipSuccess) rc = op->apply(c, SBD_FP32, shift, x32.p, y32.p, 0, sws.p, st);
             if (e == hipSuccess && !rc) {
                 if (c == 1) {  // restore with the diagonal entry v . w of T
                     e = pass_restore(y32.as<float>(), Vr(j), shift, Wr(j), N, nullptr, part.as<double>(),
@@ -221,12 +220,12 @@ struct Solver {
             }
         } else if (p64) {
             e = launch_interleave<double>(Vr(j), nullptr, c, nv, N, x64.as<double>(), st);
-            if (e == hipSuccess) rc = sigma_internal(x, H, nv, SBD_FP64, 0.0, x64.p, y64.p, 1, sws.p, st);
+            if (e == hipSuccess) rc = op->apply(nv, SBD_FP64, 0.0, x64.p, y64.p, 1, sws.p, st);
             if (e == hipSuccess && !rc)
                 e = launch_deinterleave<double>(y64.as<double>(), c, nv, N, nullptr, 0.0, Wr(j), nullptr, st);
         } else {
             e = launch_interleave<float>(Vr(j), nullptr, c, nv, N, x32.as<float>(), st);
-            if (e == hipSuccess) rc = sigma_internal(x, H, nv, SBD_FP32, shift, x32.p, y32.p, 1, sws.p, st);
+            if (e == hipSuccess) rc = op->apply(nv, SBD_FP32, shift, x32.p, y32.p, 1, sws.p, st);
             if (e == hipSuccess && !rc)
                 e = launch_deinterleave<float>(y32.as<float>(), c, nv, N, Vr(j), shift, Wr(j), nullptr, st);
         }
@@ -245,12 +244,12 @@ struct Solver {
         const int layout = nv > 1 ? 1 : 0;
         if (p64) {
             e = launch_interleave<double>(V.as<double>(), dj, c, nv, N, x64.as<double>(), st);
-            if (e == hipSuccess) rc = sigma_internal(x, H, nv, SBD_FP64, 0.0, x64.p, y64.p, layout, sws.p, st);
+            if (e == hipSuccess) rc = op->apply(nv, SBD_FP64, 0.0, x64.p, y64.p, layout, sws.p, st);
             if (e == hipSuccess && !rc)
                 e = launch_deinterleave<double>(y64.as<double>(), c, nv, N, nullptr, 0.0, W.as<double>(), dj, st);
         } else {
             e = launch_interleave<float>(V.as<double>(), dj, c, nv, N, x32.as<float>(), st);
-            if (e == hipSuccess) rc = sigma_internal(x, H, nv, SBD_FP32, shift, x32.p, y32.p, layout, sws.p, st);
+            if (e == hipSuccess) rc = op->apply(nv, SBD_FP32, shift, x32.p, y32.p, layout, sws.p, st);
             if (e == hipSuccess && !rc) {
                 if (c == 1 && nv == 1)  // the same restore, with v . w, as the eager path
                     e = pass_restore(y32.as<float>(), V.as<double>(), shift, W.as<double>(), N, dj,
@@ -439,20 +438,11 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     if (x->basis_id != b->id || H->basis_id != b->id || H->exc_id != x->id)
         return fail(SBD_ERR_STATE, "handles do not belong together");
     sbd_davidson_opts o;
-    sbd_davidson_default_opts(&o);
-    if (opts_in) o = *opts_in;
     const int64_t N = H->na * H->nb;
     const int k = nroots;
-    if (k < 1 || k > 8 || k > N) return fail(SBD_ERR_ARG, "nroots must be in [1, min(8, N)]");
-    if (!(o.tol_residual > 0) || o.max_iter < 1 || !(o.precond_delta > 0))
-        return fail(SBD_ERR_ARG, "bad Davidson options");
-    if (o.sigma_prec != SBD_FP64 && o.sigma_prec != SBD_FP32) return fail(SBD_ERR_ARG, "bad sigma_prec");
-    if (o.n_guess < 0 || (o.n_guess > 0 && !o.guess)) return fail(SBD_ERR_ARG, "bad guess");
-    int ms = std::max(o.max_space, 2 * k + 1);
-    ms = (int)std::min<int64_t>(ms, std::max<int64_t>(N, 1));
-    ms = std::min(ms, 48);
-    hipStream_t st = (hipStream_t)stream;
-    double t_autotune = 0.0, t_workspace = 0.0;
+    int rc0 = davidson_options(k, N, opts_in, &o);
+    if (rc0) return rc0;
+    double t_autotune = 0.0;
     if (o.use_autotune) {
         const auto ta = clk::now();
         // launch configuration only: sigma values do not depend on it beyond rounding
@@ -467,6 +457,37 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
         t_autotune = ms_since(ta);
     }
 
+    SigmaOp op;
+    op.N = N;
+    op.diag = H->diag.as<double>();
+    op.apply = [x, H](int nvec, int prec, double shift, const void* c, void* y, int layout, void* ws,
+                      hipStream_t s2) { return sigma_internal(x, H, nvec, prec, shift, c, y, layout, ws, s2); };
+    op.ws_bytes = [N](int nvec, int layout, size_t elem) { return sigma_workspace_bytes(N, nvec, layout, elem); };
+    return davidson_run(op, k, o, energies, vectors, report, stream, t_start, t_autotune);
+}
+
+namespace sbd {
+
+int davidson_options(int k, int64_t N, const sbd_davidson_opts* in, sbd_davidson_opts* o) {
+    sbd_davidson_default_opts(o);
+    if (in) *o = *in;
+    if (k < 1 || k > 8 || k > N) return fail(SBD_ERR_ARG, "nroots must be in [1, min(8, N)]");
+    if (!(o->tol_residual > 0) || o->max_iter < 1 || !(o->precond_delta > 0))
+        return fail(SBD_ERR_ARG, "bad Davidson options");
+    if (o->sigma_prec != SBD_FP64 && o->sigma_prec != SBD_FP32) return fail(SBD_ERR_ARG, "bad sigma_prec");
+    if (o->n_guess < 0 || (o->n_guess > 0 && !o->guess)) return fail(SBD_ERR_ARG, "bad guess");
+    return SBD_OK;
+}
+
+int davidson_run(const SigmaOp& op, int k, const sbd_davidson_opts& o, double* energies, double* vectors,
+                 sbd_davidson_report* report, void* stream, std::chrono::steady_clock::time_point t_start,
+                 double t_autotune) {
+    const int64_t N = op.N;
+    int ms = std::max(o.max_space, 2 * k + 1);
+    ms = (int)std::min<int64_t>(ms, std::max<int64_t>(N, 1));
+    ms = std::min(ms, 48);
+    hipStream_t st = (hipStream_t)stream;
+    double t_workspace = 0.0;
     // graph capture needs a stream of its own (the legacy default stream cannot
     // be captured): the solve then runs on a private stream ordered after `stream`
     OwnedStream own;
@@ -477,8 +498,7 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     }
 
     Solver S;
-    S.x = x;
-    S.H = H;
+    S.op = &op;
     S.st = st;
     S.N = N;
     S.ms = ms;
@@ -495,7 +515,7 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     double* sm = S.sm;
     double* part = S.part.as<double>();
     double* tmp = S.tmp.as<double>();
-    const double* diag = H->diag.as<double>();
+    const double* diag = op.diag;
     double t_update = 0.0;
     int restarts = 0;
 
@@ -933,3 +953,5 @@ extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham*
     if (status != SBD_OK) return status;
     return converged ? SBD_OK : SBD_NOT_CONVERGED;
 }
+
+}  // namespace sbd

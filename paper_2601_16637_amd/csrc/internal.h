@@ -4,7 +4,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -19,6 +21,8 @@ namespace sbd {
 void set_error(const std::string& msg);
 int fail(int status, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
+// h symmetric and (pq|rs) 8-fold symmetric to 1e-10 relative, all finite
+int validate_integrals(int n, const double* h, const double* eri);
 
 #define SBD_HIP(call)                                           \
     do {                                                        \
@@ -293,6 +297,65 @@ int sigma_internal(const sbd_exc* x, const sbd_ham* H, int nvec, int prec, doubl
 template <class T>
 hipError_t launch_sigma(const SigmaArgs<T>& A, int nvec, const T* c, T* y, int layout, void* ws,
                         const SigmaTune& tune, hipStream_t st, hipEvent_t* ev = nullptr);
+
+// Full-bitstring determinant lists (k_full.hip).  A determinant is two words
+// {alpha string, beta string}; lists are sorted by (alpha, beta) ascending.
+// Sort and dedupe n determinants in `work` (device, capacity pow2(n)); unique
+// ones to `out`, their count to d_count (device int64).
+hipError_t launch_full_sort_unique(void* work, int64_t n, void* out, int64_t* d_count, hipStream_t st);
+// flag[i] = 1 where determinant i starts a group of equal alpha strings
+hipError_t launch_full_group_flags(const void* dets, int64_t n, int64_t* flag, hipStream_t st);
+// from gpos (gpos[i+1] = group starts in [0, i]): group alpha strings ua, group
+// offsets goff[ng + 1], group of each determinant grp
+hipError_t launch_full_group_fill(const void* dets, int64_t n, const int64_t* gpos, uint64_t* ua, int64_t* goff,
+                                  int32_t* grp, hipStream_t st);
+// groups whose alpha strings differ by at most two electrons (self included):
+// counts when rp is null, else neighbour group gj and alpha degree gd per row
+hipError_t launch_full_group_nbr(const uint64_t* ua, int64_t ng, int64_t* cnt, const int64_t* rp, int32_t* gj,
+                                 int8_t* gd, hipStream_t st);
+// connections (one or two electrons moved) of every determinant: counts when
+// rp is null, else ket J and electrons moved deg, rows sorted by J
+hipError_t launch_full_conn(const void* dets, int64_t n, const int32_t* grp, const int64_t* goff,
+                            const int64_t* gn_rp, const int32_t* gn_j, const int8_t* gn_d, int64_t* cnt,
+                            const int64_t* rp, int32_t* J, int8_t* deg, hipStream_t st);
+// integral tables: jt/kt norb^3 ((ai|kk), (ak|ki)), jd/kd norb^2 ((pp|qq), (pq|qp))
+hipError_t launch_full_tables(const double* eri, int n, double* jt, double* kt, double* jd, double* kd,
+                              hipStream_t st);
+hipError_t launch_full_diag(const void* dets, int64_t nd, int n, const double* h, const double* jd,
+                            const double* kd, double e_core, double* out, hipStream_t st);
+struct FullSigmaArgs {
+    int64_t n = 0;
+    int norb = 0;
+    const void* dets = nullptr;
+    const int64_t* rp = nullptr;
+    const int32_t* J = nullptr;
+    const double *h = nullptr, *eri = nullptr, *jt = nullptr, *kt = nullptr, *diag = nullptr;
+    double shift = 0.0;
+};
+// y = (H - shift) x over a determinant list (layout and nvec as sbd_sigma)
+template <class T>
+hipError_t launch_full_sigma(const FullSigmaArgs& S, int nvec, const T* x, T* y, int layout, hipStream_t st);
+
+// The operator a Davidson solve works on: N determinants, the FP64 diagonal
+// (start vectors, preconditioner), and y = (H - shift) c for nvec vectors in
+// either layout (as sbd_sigma), with a workspace of ws_bytes(nvec, layout,
+// element size) bytes.  The alpha x beta product basis and the
+// full-bitstring determinant list each provide one.
+struct SigmaOp {
+    int64_t N = 0;
+    const double* diag = nullptr;
+    std::function<int(int nvec, int prec, double shift, const void* c, void* y, int layout, void* ws,
+                      hipStream_t st)>
+        apply;
+    std::function<size_t(int nvec, int layout, size_t elem)> ws_bytes;
+};
+// Davidson options with defaults filled in and checked (nroots k, N determinants).
+int davidson_options(int k, int64_t N, const sbd_davidson_opts* in, sbd_davidson_opts* o);
+// The Davidson iteration of sbd_davidson on any operator (options already
+// validated; t_start: when the caller's call began, for the report's times).
+int davidson_run(const SigmaOp& op, int k, const sbd_davidson_opts& o, double* energies, double* vectors,
+                 sbd_davidson_report* report, void* stream, std::chrono::steady_clock::time_point t_start,
+                 double t_autotune);
 
 // Dense vector kernels for Davidson (FP64 unless noted).  Vectors are rows
 // of length N stored contiguously: A + j*N.

@@ -1,0 +1,480 @@
+// Full-bitstring determinant lists (Sec. II-F, Sec. III-F) on gfx950.
+//
+// A determinant is one packed spin-orbital string over 2 x 64 bits: alpha
+// orbital p is bit p of word 0, beta orbital p bit p of word 1.  Phases count
+// the occupied spin-orbitals below the one acted on, so alpha creators come
+// before beta creators (the same convention as the alpha x beta path).  The
+// list is any set of determinants, not a Cartesian product; it is kept sorted
+// by (alpha word, beta word) ascending, so determinants sharing an alpha string
+// form a contiguous group sorted by beta string.
+//
+// Connections (the Slater-Condon neighbourhood of Eq. 4: the determinants that
+// differ by one or two electrons) are found group-wise: the alpha strings of
+// the groups are compared all-pairs (popcount of the XOR <= 4, itself
+// included), and a determinant then scans only the groups whose alpha string is
+// that close, testing popcount(alpha XOR) + popcount(beta XOR) in {2, 4}.  Rows
+// come out sorted by ket index because groups and their members are visited in
+// ascending order and hits are placed by a wave ballot.
+//
+// sigma is matrix-free: each connection's matrix element is formed from the two
+// bitstrings alone (bit scans for the moved orbitals, popcounts of masked words
+// for the phase, integrals by index), as the excitation generator of the
+// full-bitstring representation prescribes, and accumulated per bra row by one
+// wavefront in a fixed order (bitwise reproducible, no atomics).
+#include "internal.h"
+
+namespace sbd {
+
+namespace {
+
+constexpr int kTile = 1024;
+
+struct Det {
+    uint64_t a, b;  // alpha word, beta word
+};
+
+__device__ __forceinline__ bool det_gt(const Det& x, const Det& y) {
+    return x.a > y.a || (x.a == y.a && x.b > y.b);
+}
+__device__ __forceinline__ bool det_ne(const Det& x, const Det& y) { return x.a != y.a || x.b != y.b; }
+__device__ __forceinline__ uint64_t below(int p) { return (1ull << p) - 1ull; }
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// ------------------------------------------------------------------ sort
+__global__ void k_det_pad(Det* a, int64_t n, int64_t P) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + n;
+    if (i < P) a[i] = Det{~0ull, ~0ull};
+}
+
+__global__ void k_det_bitonic_global(Det* a, int64_t P, int64_t k, int64_t j) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const int64_t l = i ^ j;
+    if (l <= i) return;
+    const bool up = (i & k) == 0;
+    const Det x = a[i], y = a[l];
+    if (det_gt(x, y) == up) {
+        a[i] = y;
+        a[l] = x;
+    }
+}
+
+// stages j = jstart, ..., 1 of merge size k inside tiles of T elements
+__global__ void __launch_bounds__(kTile) k_det_bitonic_local(Det* a, int64_t k, int64_t jstart, int T) {
+    __shared__ Det s[kTile];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * T;
+    s[t] = a[base + t];
+    for (int64_t j = jstart; j > 0; j >>= 1) {
+        __syncthreads();
+        const int l = t ^ (int)j;
+        if (l > t) {
+            const bool up = ((base + t) & k) == 0;
+            const Det x = s[t], y = s[l];
+            if (det_gt(x, y) == up) {
+                s[t] = y;
+                s[l] = x;
+            }
+        }
+    }
+    __syncthreads();
+    a[base + t] = s[t];
+}
+
+// exclusive scan of one int64 per thread over the block (blockDim == 1024)
+__device__ int64_t block_scan(int64_t v, int64_t* sh, int64_t* total) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        const int64_t add = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    const int64_t incl = sh[t];
+    *total = sh[blockDim.x - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// unique compaction of the sorted list (first n entries real), one workgroup
+__global__ void __launch_bounds__(1024) k_det_unique(const Det* a, int64_t n, Det* out, int64_t* count) {
+    __shared__ int64_t sh[1024];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < n; base += blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t f = (i < n && (i == 0 || det_ne(a[i], a[i - 1]))) ? 1 : 0;
+        int64_t tot;
+        const int64_t pos = block_scan(f, sh, &tot);
+        if (f) out[carry + pos] = a[i];
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *count = carry;
+}
+
+// ------------------------------------------------------------------ alpha groups
+__global__ void k_group_flags(const Det* d, int64_t n, int64_t* flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = (i == 0 || d[i].a != d[i - 1].a) ? 1 : 0;
+}
+
+// gpos[i + 1] = number of group starts in [0, i]
+__global__ void k_group_fill(const Det* d, int64_t n, const int64_t* gpos, uint64_t* ua, int64_t* goff,
+                             int32_t* grp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t g = gpos[i + 1] - 1;
+    grp[i] = (int32_t)g;
+    if (i == 0 || d[i].a != d[i - 1].a) {
+        ua[g] = d[i].a;
+        goff[g] = i;
+    }
+    if (i == n - 1) goff[g + 1] = n;
+}
+
+constexpr int kWaves = 8;      // rows per workgroup
+constexpr int kChunk = 2048;   // strings staged in LDS per pass
+
+__device__ __forceinline__ int wave_sum(int v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Alpha strings of the groups within two electrons of each group's (itself
+// included): count pass (FILL = false) and fill pass with the alpha degree
+// (electrons moved, 0..2) of each neighbour group.
+template <bool FILL>
+__global__ void __launch_bounds__(kWaves * 64) k_group_nbr(const uint64_t* __restrict__ ua, int64_t ng,
+                                                           int64_t* cnt, const int64_t* __restrict__ rp,
+                                                           int32_t* gj, int8_t* gd) {
+    __shared__ uint64_t chunk[kChunk];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t g = (int64_t)blockIdx.x * kWaves + w;
+    const uint64_t u = (g < ng) ? ua[g] : 0ull;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t o = (FILL && g < ng) ? rp[g] : 0;
+    int c = 0;
+    for (int64_t base = 0; base < ng; base += kChunk) {
+        const int len = (int)((ng - base) < kChunk ? (ng - base) : kChunk);
+        __syncthreads();
+        for (int t = threadIdx.x; t < len; t += blockDim.x) chunk[t] = ua[base + t];
+        __syncthreads();
+        if (g >= ng) continue;
+        for (int t0 = 0; t0 < len; t0 += 64) {
+            const int t = t0 + lane;
+            const uint64_t v = (t < len) ? chunk[t] : u;
+            const int pc = __popcll(u ^ v);
+            const bool hit = (t < len) && pc <= 4;
+            if (FILL) {
+                const uint64_t m = __ballot(hit);
+                if (hit) {
+                    const int64_t e = o + __popcll(m & lt);
+                    gj[e] = (int32_t)(base + t);
+                    gd[e] = (int8_t)(pc >> 1);
+                }
+                o += __popcll(m);
+            } else {
+                c += hit;
+            }
+        }
+    }
+    if (!FILL) {
+        c = wave_sum(c);
+        if (g < ng && lane == 0) cnt[g] = c;
+    }
+}
+
+// Connections of each determinant: count pass and fill pass (ket index and
+// electrons moved, 1 or 2), rows sorted by ket.
+template <bool FILL>
+__global__ void __launch_bounds__(kWaves * 64) k_conn(const Det* __restrict__ d, int64_t n,
+                                                      const int32_t* __restrict__ grp,
+                                                      const int64_t* __restrict__ goff,
+                                                      const int64_t* __restrict__ gn_rp,
+                                                      const int32_t* __restrict__ gn_j,
+                                                      const int8_t* __restrict__ gn_d, int64_t* cnt,
+                                                      const int64_t* __restrict__ rp, int32_t* J, int8_t* deg) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t I = (int64_t)blockIdx.x * kWaves + w;
+    if (I >= n) return;  // wave-uniform
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint64_t ib = d[I].b;
+    const int g = grp[I];
+    int64_t o = FILL ? rp[I] : 0;
+    int c = 0;
+    for (int64_t e = gn_rp[g]; e < gn_rp[g + 1]; ++e) {
+        const int h = gn_j[e];
+        const int pa = 2 * (int)gn_d[e];
+        const int64_t k0 = goff[h], k1 = goff[h + 1];
+        for (int64_t t0 = k0; t0 < k1; t0 += 64) {
+            const int64_t K = t0 + lane;
+            const bool ok = K < k1;
+            const int tot = pa + (ok ? __popcll(ib ^ d[K].b) : 0);
+            const bool hit = ok && (tot == 2 || tot == 4);
+            if (FILL) {
+                const uint64_t m = __ballot(hit);
+                if (hit) {
+                    const int64_t q = o + __popcll(m & lt);
+                    J[q] = (int32_t)K;
+                    deg[q] = (int8_t)(tot >> 1);
+                }
+                o += __popcll(m);
+            } else {
+                c += hit;
+            }
+        }
+    }
+    if (!FILL) {
+        c = wave_sum(c);
+        if (lane == 0) cnt[I] = c;
+    }
+}
+
+// ------------------------------------------------------------------ Hamiltonian
+// Tables of the single-excitation spectator terms: jt[(a n + i) n + k] = (ai|kk),
+// kt[(a n + i) n + k] = (ak|ki); and jd[p n + q] = (pp|qq), kd[p n + q] = (pq|qp).
+__global__ void k_full_tables(const double* __restrict__ eri, int n, double* jt, double* kt, double* jd,
+                              double* kd) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n3 = (int64_t)n * n * n;
+    if (t < n3) {
+        const int k = (int)(t % n), i = (int)((t / n) % n), a = (int)(t / ((int64_t)n * n));
+        const int64_t nn = n;
+        jt[t] = eri[((a * nn + i) * nn + k) * nn + k];
+        kt[t] = eri[((a * nn + k) * nn + k) * nn + i];
+    }
+    if (t < (int64_t)n * n) {
+        const int q = (int)(t % n), p = (int)(t / n);
+        const int64_t nn = n;
+        jd[t] = eri[((p * nn + p) * nn + q) * nn + q];
+        kd[t] = eri[((p * nn + q) * nn + q) * nn + p];
+    }
+}
+
+// H_II = E_core + sum_{p in I} h_pp + sum over occupied pairs of the same spin
+// [(pp|qq) - (pq|qp)] + sum over an alpha and a beta orbital (pp|qq).
+__global__ void k_full_diag(const Det* __restrict__ d, int64_t nd, int n, const double* __restrict__ h,
+                            const double* __restrict__ jd, const double* __restrict__ kd, double e_core,
+                            double* out) {
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nd) return;
+    const uint64_t w[2] = {d[I].a, d[I].b};
+    double v = e_core;
+    for (int s = 0; s < 2; ++s)
+        for (uint64_t m = w[s]; m; m &= m - 1) {
+            const int p = __builtin_ctzll(m);
+            v += h[p * n + p];
+            for (uint64_t r = m & (m - 1); r; r &= r - 1) {  // q > p of the same spin
+                const int q = __builtin_ctzll(r);
+                v += jd[p * n + q] - kd[p * n + q];
+            }
+        }
+    for (uint64_t m = w[0]; m; m &= m - 1) {
+        const int p = __builtin_ctzll(m);
+        for (uint64_t r = w[1]; r; r &= r - 1) v += jd[p * n + __builtin_ctzll(r)];
+    }
+    out[I] = v;
+}
+
+struct FullArgs {
+    int64_t n;
+    int norb;
+    const Det* d;
+    const int64_t* rp;
+    const int32_t* J;
+    const double* h;    // norb x norb
+    const double* eri;  // norb^4
+    const double* jt;   // norb^3: (ai|kk)
+    const double* kt;   // norb^3: (ak|ki)
+    const double* diag;
+    double shift;
+};
+
+// Phase of a+_a a_i |w> (i in w, a not): the occupied orbitals strictly between.
+__device__ __forceinline__ int single_parity(uint64_t w, int i, int a) {
+    return __popcll(w & below(i)) + __popcll((w ^ (1ull << i)) & below(a));
+}
+
+// <bra|H|ket> for bra != ket connected (one or two electrons moved), FP64.
+__device__ double full_element(const Det& bra, const Det& ket, const FullArgs& A) {
+    const int n = A.norb;
+    const int64_t nn = n;
+    const uint64_t da = bra.a ^ ket.a, db = bra.b ^ ket.b;
+    const int pa = __popcll(da), pb = __popcll(db);
+    if (pa + pb == 2) {  // single i -> a in one spin; spectators of both spins
+        const bool al = pa == 2;
+        const uint64_t wk = al ? ket.a : ket.b, wb = al ? bra.a : bra.b, other = al ? ket.b : ket.a;
+        const int i = __builtin_ctzll(wk & ~wb), a = __builtin_ctzll(wb & ~wk);
+        const double* jr = A.jt + (a * nn + i) * nn;
+        const double* kr = A.kt + (a * nn + i) * nn;
+        double v = A.h[a * n + i];
+        for (uint64_t m = wk; m; m &= m - 1) {
+            const int k = __builtin_ctzll(m);
+            v += jr[k] - kr[k];
+        }
+        for (uint64_t m = other; m; m &= m - 1) v += jr[__builtin_ctzll(m)];
+        return (single_parity(wk, i, a) & 1) ? -v : v;
+    }
+    if (pa == 4 || pb == 4) {  // double within one spin: a+_a a+_b a_j a_i, i < j, a < b
+        const uint64_t wk = pa == 4 ? ket.a : ket.b, wb = pa == 4 ? bra.a : bra.b;
+        const uint64_t x = wk & ~wb, y = wb & ~wk;
+        const int i = __builtin_ctzll(x), j = __builtin_ctzll(x & (x - 1));
+        const int a = __builtin_ctzll(y), b = __builtin_ctzll(y & (y - 1));
+        const uint64_t k1 = wk ^ (1ull << i), k2 = k1 ^ (1ull << j), k3 = k2 | (1ull << b);
+        const int par = __popcll(wk & below(i)) + __popcll(k1 & below(j)) + __popcll(k2 & below(b)) +
+                        __popcll(k3 & below(a));
+        const double v = A.eri[((a * nn + i) * nn + b) * nn + j] - A.eri[((a * nn + j) * nn + b) * nn + i];
+        return (par & 1) ? -v : v;
+    }
+    // one alpha and one beta electron: alpha i -> a, beta j -> b, element (ai|bj)
+    const int i = __builtin_ctzll(ket.a & ~bra.a), a = __builtin_ctzll(bra.a & ~ket.a);
+    const int j = __builtin_ctzll(ket.b & ~bra.b), b = __builtin_ctzll(bra.b & ~ket.b);
+    const int par = single_parity(ket.a, i, a) + single_parity(ket.b, j, b);
+    const double v = A.eri[((a * nn + i) * nn + b) * nn + j];
+    return (par & 1) ? -v : v;
+}
+
+// y[I] = (H_II - shift) x[I] + sum_J H_IJ x[J]: one wavefront per bra row, its
+// lanes over the row's connections, NV interleaved vectors per determinant.
+// Each element is formed once in FP64 and, for FP32 vectors, rounded once;
+// partial sums are combined by a fixed butterfly.
+template <class T, int NV>
+__global__ void __launch_bounds__(256) k_full_sigma(FullArgs A, const T* __restrict__ x, T* __restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int64_t I = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (I >= A.n) return;  // wave-uniform
+    const Det bra = A.d[I];
+    T acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = T(0);
+    const int64_t e1 = A.rp[I + 1];
+    for (int64_t e = A.rp[I] + lane; e < e1; e += 64) {
+        const int64_t J = A.J[e];
+        const T hv = (T)full_element(bra, A.d[J], A);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += hv * x[J * NV + v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        for (int off = 32; off > 0; off >>= 1) acc[v] += __shfl_xor(acc[v], off, 64);
+    if (lane == 0) {
+        const T dg = (T)(A.diag[I] - A.shift);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) y[I * NV + v] = dg * x[I * NV + v] + acc[v];
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_full_sort_unique(void* work, int64_t n, void* out, int64_t* d_count, hipStream_t st) {
+    Det* a = static_cast<Det*>(work);
+    int64_t P = 1;
+    while (P < n) P <<= 1;
+    if (P > n) hipLaunchKernelGGL(k_det_pad, dim3(blocks_for(P - n, 256)), dim3(256), 0, st, a, n, P);
+    const int T = (int)(P < kTile ? P : kTile);
+    const unsigned tiles = (unsigned)(P / T);
+    for (int64_t k = 2; k <= P; k <<= 1) {
+        int64_t j = k >> 1;
+        for (; j >= T; j >>= 1)
+            hipLaunchKernelGGL(k_det_bitonic_global, dim3(blocks_for(P, 256)), dim3(256), 0, st, a, P, k, j);
+        hipLaunchKernelGGL(k_det_bitonic_local, dim3(tiles), dim3(T), 0, st, a, k, j, T);
+    }
+    hipLaunchKernelGGL(k_det_unique, dim3(1), dim3(1024), 0, st, a, n, static_cast<Det*>(out), d_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_full_group_flags(const void* dets, int64_t n, int64_t* flag, hipStream_t st) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_group_flags, dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                           static_cast<const Det*>(dets), n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_full_group_fill(const void* dets, int64_t n, const int64_t* gpos, uint64_t* ua, int64_t* goff,
+                                  int32_t* grp, hipStream_t st) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_group_fill, dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                           static_cast<const Det*>(dets), n, gpos, ua, goff, grp);
+    return hipGetLastError();
+}
+
+hipError_t launch_full_group_nbr(const uint64_t* ua, int64_t ng, int64_t* cnt, const int64_t* rp, int32_t* gj,
+                                 int8_t* gd, hipStream_t st) {
+    if (ng <= 0) return hipGetLastError();
+    if (rp)
+        hipLaunchKernelGGL(k_group_nbr<true>, dim3(blocks_for(ng, kWaves)), dim3(kWaves * 64), 0, st, ua, ng,
+                           cnt, rp, gj, gd);
+    else
+        hipLaunchKernelGGL(k_group_nbr<false>, dim3(blocks_for(ng, kWaves)), dim3(kWaves * 64), 0, st, ua, ng,
+                           cnt, rp, gj, gd);
+    return hipGetLastError();
+}
+
+hipError_t launch_full_conn(const void* dets, int64_t n, const int32_t* grp, const int64_t* goff,
+                            const int64_t* gn_rp, const int32_t* gn_j, const int8_t* gn_d, int64_t* cnt,
+                            const int64_t* rp, int32_t* J, int8_t* deg, hipStream_t st) {
+    if (n <= 0) return hipGetLastError();
+    const Det* d = static_cast<const Det*>(dets);
+    if (rp)
+        hipLaunchKernelGGL(k_conn<true>, dim3(blocks_for(n, kWaves)), dim3(kWaves * 64), 0, st, d, n, grp, goff,
+                           gn_rp, gn_j, gn_d, cnt, rp, J, deg);
+    else
+        hipLaunchKernelGGL(k_conn<false>, dim3(blocks_for(n, kWaves)), dim3(kWaves * 64), 0, st, d, n, grp, goff,
+                           gn_rp, gn_j, gn_d, cnt, rp, J, deg);
+    return hipGetLastError();
+}
+
+hipError_t launch_full_tables(const double* eri, int n, double* jt, double* kt, double* jd, double* kd,
+                              hipStream_t st) {
+    const int64_t n3 = (int64_t)n * n * n;
+    hipLaunchKernelGGL(k_full_tables, dim3(blocks_for(n3, 256)), dim3(256), 0, st, eri, n, jt, kt, jd, kd);
+    return hipGetLastError();
+}
+
+hipError_t launch_full_diag(const void* dets, int64_t nd, int n, const double* h, const double* jd,
+                            const double* kd, double e_core, double* out, hipStream_t st) {
+    if (nd > 0)
+        hipLaunchKernelGGL(k_full_diag, dim3(blocks_for(nd, 256)), dim3(256), 0, st,
+                           static_cast<const Det*>(dets), nd, n, h, jd, kd, e_core, out);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_full_sigma(const FullSigmaArgs& S, int nvec, const T* x, T* y, int layout, hipStream_t st) {
+    if (S.n <= 0) return hipGetLastError();
+    FullArgs A{};
+    A.n = S.n;
+    A.norb = S.norb;
+    A.d = static_cast<const Det*>(S.dets);
+    A.rp = S.rp;
+    A.J = S.J;
+    A.h = S.h;
+    A.eri = S.eri;
+    A.jt = S.jt;
+    A.kt = S.kt;
+    A.diag = S.diag;
+    A.shift = S.shift;
+    const dim3 grid(blocks_for(S.n, 4)), block(256);
+    if (layout == 0) {
+        for (int v = 0; v < nvec; ++v)
+            hipLaunchKernelGGL((k_full_sigma<T, 1>), grid, block, 0, st, A, x + (size_t)v * S.n,
+                               y + (size_t)v * S.n);
+        return hipGetLastError();
+    }
+    switch (nvec) {
+        case 1: hipLaunchKernelGGL((k_full_sigma<T, 1>), grid, block, 0, st, A, x, y); break;
+        case 2: hipLaunchKernelGGL((k_full_sigma<T, 2>), grid, block, 0, st, A, x, y); break;
+        case 4: hipLaunchKernelGGL((k_full_sigma<T, 4>), grid, block, 0, st, A, x, y); break;
+        case 8: hipLaunchKernelGGL((k_full_sigma<T, 8>), grid, block, 0, st, A, x, y); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_full_sigma<double>(const FullSigmaArgs&, int, const double*, double*, int, hipStream_t);
+template hipError_t launch_full_sigma<float>(const FullSigmaArgs&, int, const float*, float*, int, hipStream_t);
+
+}  // namespace sbd

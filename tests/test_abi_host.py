@@ -114,3 +114,14 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_full_basis_validation_on_host():
+    ok = np.array([[0b1111, 0b1111]], dtype=np.uint64)
+    assert _status(lambda: sbd.FullBasis(0, 4, 4, ok)) == -2
+    assert _status(lambda: sbd.FullBasis(65, 4, 4, ok)) == -2
+    assert _status(lambda: sbd.FullBasis(8, 9, 4, ok)) == -1
+    assert _status(lambda: sbd.FullBasis(8, 4, 4, np.array([[0b1111, 0b111]], dtype=np.uint64))) == -3
+    assert _status(lambda: sbd.FullBasis(8, 4, 4, np.array([[0b111 | (1 << 9), 0b1111]], dtype=np.uint64))) == -3
+    assert _status(lambda: sbd.FullBasis(8, 4, 4, np.zeros((0, 2), dtype=np.uint64))) == -1
+    assert "determinant" in sbd.last_error()

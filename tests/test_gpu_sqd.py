@@ -1,0 +1,70 @@
+"""SQD outer loop (sbd_sqd_run, Sec. I): successive solves on a growing set of
+sampled configurations, through the C ABI.  Each step's energies are checked
+against the oracle's Davidson on the oracle's sigma over the same basis (the
+Cartesian product of the distinct sampled alpha and beta strings), within
+1e-8 Ha; warm and cold runs reach the same energies; the nested bases make the
+lowest energy non-increasing."""
+import numpy as np
+import pytest
+
+import oracle
+import workload as wl
+
+torch = pytest.importorskip("torch")
+sbd = pytest.importorskip("paper_2601_16637_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_energies(norb, na, nb, h, eri, ec, samples, m, nroots, union=False):
+    a, b = samples[:m, 0], samples[:m, 1]
+    if union:
+        a = b = np.concatenate([a, b])
+    S = oracle.OracleSystem(norb, a, b, h, eri, ec)
+    if S.N <= 1500:
+        return np.linalg.eigvalsh(S.dense_h())[:nroots], S.N
+    r = oracle.davidson(S.sigma, S.diag(), nroots, tol=1e-9, max_space=30)
+    return np.array(r.energies[:nroots]), S.N
+
+
+@pytest.mark.parametrize("nroots,union", [(1, False), (2, False), (1, True)])
+def test_sqd_steps_match_oracle(nroots, union):
+    norb, n = 10, 4
+    h, eri, ec = wl.make_integrals(norb, 610)
+    smp = wl.sample_configurations(norb, n, n, 400, 611)
+    steps = [20, 60, 150, 400]
+    e, rep = sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps, nroots=nroots, spin_union=union,
+                         tol_residual=1e-8)
+    for s, m in enumerate(steps):
+        eo, N = oracle_energies(norb, n, n, h, eri, ec, smp, m, nroots, union)
+        assert rep[s]["ndet"] == N and rep[s]["status"] == 0 and rep[s]["samples"] == m
+        assert np.abs(e[s, :eo.size] - eo).max() <= 1e-8, (s, e[s], eo)
+        assert rep[s]["warm"] == (1 if s > 0 else 0)
+    assert np.all(np.diff(e[:, 0]) <= 1e-10)
+
+
+def test_sqd_warm_equals_cold_and_saves_nothing_wrong():
+    """Warm starts change the path, not the answer; mixed precision stays
+    within 1e-6 Ha of the plain result."""
+    norb, n = 12, 5
+    h, eri, ec = wl.make_integrals(norb, 620)
+    smp = wl.sample_configurations(norb, n, n, 3000, 621)
+    steps = [500, 1500, 3000]
+    ew, rw = sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps, warm_start=True, tol_residual=1e-8)
+    ec_, rc = sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps, warm_start=False, tol_residual=1e-8)
+    assert np.abs(ew - ec_).max() <= 1e-8
+    assert [r["warm"] for r in rc] == [0, 0, 0] and [r["warm"] for r in rw] == [0, 1, 1]
+    em, rm = sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps, sigma_prec=1, tol_residual=1e-7)
+    assert np.abs(em - ew).max() <= 1e-6
+
+
+def test_sqd_rejects_bad_steps():
+    norb, n = 8, 3
+    h, eri, ec = wl.make_integrals(norb, 630)
+    smp = wl.sample_configurations(norb, n, n, 50, 631)
+    for steps in ([30, 20], [0, 10], [10, 51]):
+        with pytest.raises(sbd.SBDError) as ei:
+            sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps)
+        assert ei.value.status == -1
+    with pytest.raises(sbd.SBDError):
+        sbd.sqd_run(norb, n, n + 1, h, eri, ec, smp, [10], spin_union=True)

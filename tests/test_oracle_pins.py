@@ -529,3 +529,19 @@ def test_full_variational_subsets():
     e_s = np.linalg.eigvalsh(small.dense_h())[0]
     e_b = np.linalg.eigvalsh(big.dense_h())[0]
     assert e_fci <= e_b + 1e-10 and e_b <= e_s + 1e-10
+
+
+@pytest.mark.parametrize("norb,na,nb,count,seed", [(6, 3, 3, 200, 11), (7, 3, 2, 300, 12)])
+def test_full_sigma_rows_equals_dense(norb, na, nb, count, seed):
+    """The row-sampled sigma of a determinant list (neighbours found per row by
+    comparing with every determinant, no lists) equals the dense H applied to
+    the vector at those rows; it needs no connection lists."""
+    h, eri, ec = wl.make_integrals(norb, 80 + seed)
+    dets = _random_dets(norb, na, nb, count, seed)
+    S = oracle.FullOracleSystem(norb, dets, h, eri, ec)
+    S2 = oracle.FullOracleSystem(norb, dets, h, eri, ec, connections=False)
+    x = np.random.default_rng(seed).standard_normal(S.N)
+    idx = np.array([0, S.N - 1, S.N // 2, 7, 7, 3])
+    ref = S.dense_h()[idx] @ x
+    got = S2.sigma_rows(x, idx)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(S.dense_h()).max() * np.abs(x).sum()

@@ -60,3 +60,15 @@ def test_string_sets_nested_across_sizes():
     a = wl.make_config("sel26", nstr=6000).alpha
     b = wl.make_config("sel26", nstr=8000).alpha
     assert np.isin(a, b).all()
+
+
+def test_sample_configurations_counts_and_repeats():
+    s = wl.sample_configurations(12, 5, 4, 2000, 3)
+    assert s.shape == (2000, 2) and s.dtype == np.uint64
+    pa = np.array([bin(int(v)).count("1") for v in s[:, 0]])
+    pb = np.array([bin(int(v)).count("1") for v in s[:, 1]])
+    assert np.all(pa == 5) and np.all(pb == 4) and int(s.max()) < (1 << 12)
+    assert np.array_equal(s, wl.sample_configurations(12, 5, 4, 2000, 3))
+    # a measurement record repeats configurations
+    keys = np.unique(s[:, 0] * np.uint64(1 << 12) + s[:, 1])
+    assert keys.size < 2000

@@ -207,51 +207,72 @@ def make_config(name: str, nstr: int | None = None) -> Workload:
                     meta=dict(seeds=c["seeds"], nstr=k))
 
 
-def sample_determinants(norb: int, n_alpha: int, n_beta: int, count: int, seed: int,
-                        decay: float = LEVEL_DECAY) -> np.ndarray:
-    """Unique determinants (rows: alpha string, beta string) drawn without
-    replacement, sorted by alpha then beta string: a stand-in for a list of
-    sampled full spin-orbital bitstrings that is not a Cartesian product.
+def sample_product_subset(alpha: np.ndarray, beta: np.ndarray, n_alpha: int, n_beta: int, count: int,
+                          seed: int, decay: float = LEVEL_DECAY) -> np.ndarray:
+    """Unique determinants (rows: alpha string, beta string), sorted by alpha
+    then beta string, drawn from the product of two string pools without
+    replacement: a stand-in for a list of sampled configurations that is not a
+    Cartesian product (most pairs of the pools are absent).
 
-    P(det) is proportional to exp(-decay * (level_alpha + level_beta)); the
-    Aufbau determinant is always included.  Each candidate draws its alpha and
-    its beta excitation independently (level k with probability proportional
-    to C(n,k) C(norb-n,k) exp(-decay k), then k holes and k particles
-    uniformly), and the first occurrence of each determinant is kept.
+    P(alpha, beta) is proportional to exp(-decay * (level_alpha + level_beta))
+    (level = electrons outside the Aufbau orbitals): candidates draw their
+    alpha and beta strings independently with weights exp(-decay * level), and
+    the first occurrence of each pair is kept until `count` pairs are found.
+    The pair of the pools' first strings (their Aufbau strings when present)
+    is always included.
     """
-    total = math.comb(norb, n_alpha) * math.comb(norb, n_beta)
-    count = min(int(count), total)
+    alpha = np.ascontiguousarray(alpha, dtype=np.uint64)
+    beta = np.ascontiguousarray(beta, dtype=np.uint64)
+    na, nb = alpha.size, beta.size
+    count = min(int(count), na * nb)
     if count <= 0:
         return np.zeros((0, 2), dtype=np.uint64)
     rng = np.random.default_rng(seed)
-    one = np.uint64(1)
+    wa = np.exp(-decay * _level(alpha, n_alpha).astype(np.float64))
+    wb = np.exp(-decay * _level(beta, n_beta).astype(np.float64))
+    ca, cb = np.cumsum(wa / wa.sum()), np.cumsum(wb / wb.sum())
+    ia0 = int(np.argmin(_level(alpha, n_alpha)))
+    ib0 = int(np.argmin(_level(beta, n_beta)))
+    keys = np.array([ia0 * nb + ib0], dtype=np.int64)
+    while True:
+        _, first = np.unique(keys, return_index=True)
+        if first.size >= count:
+            break
+        M = max(1 << 16, 2 * (count - first.size))
+        ia = np.minimum(np.searchsorted(ca, rng.random(M), side="right"), na - 1)
+        ib = np.minimum(np.searchsorted(cb, rng.random(M), side="right"), nb - 1)
+        keys = np.concatenate([keys[np.sort(first)], ia.astype(np.int64) * nb + ib])
+    keep = np.sort(keys[np.sort(first)[:count]])
+    out = np.empty((count, 2), dtype=np.uint64)
+    out[:, 0] = alpha[keep // nb]
+    out[:, 1] = beta[keep % nb]
+    order = np.lexsort((out[:, 1], out[:, 0]))
+    return out[order]
 
-    def draw(n, M):
+
+def sample_configurations(norb: int, n_alpha: int, n_beta: int, count: int, seed: int,
+                          decay: float = LEVEL_DECAY) -> np.ndarray:
+    """Sampled configurations with repeats, in drawing order (rows: alpha
+    string, beta string): a stand-in for the measurement record of a quantum
+    device that an SQD run diagonalises in growing prefixes.  Each spin's
+    string draws its excitation level k with probability proportional to
+    C(n,k) C(norb-n,k) exp(-decay k), then k holes among the n lowest orbitals
+    and k particles among the others, uniformly."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((count, 2), dtype=np.uint64)
+    one = np.uint64(1)
+    for col, n in ((0, n_alpha), (1, n_beta)):
         kmax = min(n, norb - n)
-        ks = np.arange(kmax + 1)
-        wk = np.array([math.comb(n, k) * math.comb(norb - n, k) * math.exp(-decay * k) for k in ks])
-        kk = rng.choice(kmax + 1, size=M, p=wk / wk.sum())
-        holes = np.argsort(rng.random((M, max(n, 1))), axis=1)[:, :kmax].astype(np.uint64)
-        parts = (np.argsort(rng.random((M, max(norb - n, 1))), axis=1)[:, :kmax] + n).astype(np.uint64)
-        cand = np.full(M, np.uint64((1 << n) - 1), dtype=np.uint64)
+        wk = np.array([math.comb(n, k) * math.comb(norb - n, k) * math.exp(-decay * k) for k in range(kmax + 1)])
+        kk = rng.choice(kmax + 1, size=count, p=wk / wk.sum())
+        holes = np.argsort(rng.random((count, max(n, 1))), axis=1)[:, :kmax].astype(np.uint64)
+        parts = (np.argsort(rng.random((count, max(norb - n, 1))), axis=1)[:, :kmax] + n).astype(np.uint64)
+        s = np.full(count, np.uint64((1 << n) - 1), dtype=np.uint64)
         for j in range(kmax):
             sel = kk > j
-            cand[sel] = (cand[sel] & ~(one << holes[sel, j])) | (one << parts[sel, j])
-        return cand
-
-    aufbau = ((1 << n_alpha) - 1, (1 << n_beta) - 1)
-    chosen, seen = [aufbau], {aufbau}
-    while len(chosen) < count:
-        M = max(1024, 2 * (count - len(chosen)))
-        ca, cb = draw(n_alpha, M), draw(n_beta, M)
-        for a, b in zip(ca.tolist(), cb.tolist()):
-            if (a, b) not in seen:
-                seen.add((a, b))
-                chosen.append((a, b))
-                if len(chosen) == count:
-                    break
-    out = np.array(sorted(chosen), dtype=np.uint64)
-    return out.reshape(-1, 2)
+            s[sel] = (s[sel] & ~(one << holes[sel, j])) | (one << parts[sel, j])
+        out[:, col] = s
+    return out
 
 
 @dataclass
@@ -273,23 +294,25 @@ class FullWorkload:
         return int(self.dets.shape[0])
 
 
-# Full-bitstring workloads: (norb, n per spin, determinants, roots, seeds (integrals, dets)).
+# Full-bitstring workloads: determinant lists drawn from the product of a
+# product workload's alpha and beta string sets (same integrals), with the
+# seed of the draw.
 FULL_CONFIGS = {
-    "full16": dict(norb=16, n=8, ndet=100000, nroots=1, seeds=(102, 5001)),
-    "full26": dict(norb=26, n=7, ndet=400000, nroots=1, seeds=(103, 5002)),
+    "full16": dict(pool="sel16", ndet=1_000_000, nroots=1, seed=5101),
+    "full26": dict(pool="sel26", ndet=4_000_000, nroots=1, seed=5102),
 }
 
 
-def make_full_config(name: str, ndet: int | None = None) -> FullWorkload:
-    """A named full-bitstring workload (same integrals as the alpha x beta
-    workload of the same orbital count), optionally with fewer determinants."""
+def make_full_config(name: str, ndet: int | None = None, nstr: int | None = None) -> FullWorkload:
+    """A named full-bitstring workload, optionally with fewer determinants or
+    smaller string pools."""
     c = FULL_CONFIGS[name]
-    si, sd = c["seeds"]
-    h, eri, ecore = make_integrals(c["norb"], si)
+    P = make_config(c["pool"], nstr=nstr)
     n = ndet if ndet is not None else c["ndet"]
-    d = sample_determinants(c["norb"], c["n"], c["n"], n, sd)
-    return FullWorkload(name, c["norb"], c["n"], c["n"], d, h, eri, ecore, c["nroots"],
-                        meta=dict(seeds=c["seeds"], ndet=n))
+    d = sample_product_subset(P.alpha, P.beta, P.n_alpha, P.n_beta, n, c["seed"])
+    return FullWorkload(name, P.norb, P.n_alpha, P.n_beta, d, P.h, P.eri, P.e_core, c["nroots"],
+                        meta=dict(seeds=(P.meta["seeds"][0], P.meta["seeds"][1], P.meta["seeds"][2], c["seed"]),
+                                  ndet=n, pool=c["pool"], nstr=P.alpha.size))
 
 
 def serving_stream(nreq: int = 256, seed: int = 5000, rate: float = 20.0,
