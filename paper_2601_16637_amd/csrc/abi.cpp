@@ -277,6 +277,12 @@ int sbd_build_excitations(const sbd_basis* b, void* stream, sbd_exc** out) {
             e = launch_sell_fill(t1.row_ptr.as<int64_t>(), t1.pack.as<uint64_t>(),
                                  t1.sell_pos.as<int32_t>(), n, t1.sell_off.as<int64_t>(),
                                  t1.sell.as<uint64_t>(), st);
+        // 32-bit entries for the alpha-beta kernel (ket index in 18 bits)
+        if (e == hipSuccess && n <= ((int64_t)1 << kSellJBits)) {
+            e = t1.sell32.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(sell_total, 1));
+            if (e == hipSuccess)
+                e = launch_sell_compact(t1.sell.as<uint64_t>(), sell_total, b->norb, t1.sell32.as<uint32_t>(), st);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
             delete x;
@@ -408,6 +414,7 @@ SigmaArgs<double> make_args<double>(const sbd_exc* x, const sbd_ham* H, double s
     A.b1p = b1->row_ptr.as<int64_t>(); A.b1J = b1->J.as<int32_t>(); A.b1pack = b1->pack.as<uint64_t>();
     A.b1sell = b1->sell.as<uint64_t>(); A.b1sell_off = b1->sell_off.as<int64_t>();
     A.b1sell_pos = b1->sell_pos.as<int32_t>();
+    A.b1sell32 = b1->sell32.as<uint32_t>();
     A.b1c = H->sc[1].c1_64.as<double>(); A.b1ps = H->sc[1].ps1.as<int32_t>();
     A.b2p = b2->row_ptr.as<int64_t>(); A.b2J = b2->J.as<int32_t>(); A.b2c = H->sc[1].c2_64.as<double>();
     A.Ga = H->sc[0].G64.as<double>(); A.Gb = H->sc[1].G64.as<double>();
@@ -426,6 +433,7 @@ SigmaArgs<float> make_args<float>(const sbd_exc* x, const sbd_ham* H, double shi
     A.b1p = b1->row_ptr.as<int64_t>(); A.b1J = b1->J.as<int32_t>(); A.b1pack = b1->pack.as<uint64_t>();
     A.b1sell = b1->sell.as<uint64_t>(); A.b1sell_off = b1->sell_off.as<int64_t>();
     A.b1sell_pos = b1->sell_pos.as<int32_t>();
+    A.b1sell32 = b1->sell32.as<uint32_t>();
     A.b1c = H->sc[1].c1_32.as<float>(); A.b1ps = H->sc[1].ps1.as<int32_t>();
     A.b2p = b2->row_ptr.as<int64_t>(); A.b2J = b2->J.as<int32_t>(); A.b2c = H->sc[1].c2_32.as<float>();
     A.Ga = H->sc[0].G32.as<float>(); A.Gb = H->sc[1].G32.as<float>();

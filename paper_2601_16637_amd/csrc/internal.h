@@ -134,6 +134,10 @@ struct Table {
     DevBuf sell_off; // int64[nslice+1]: first entry of each slice (slot-major, 64 per slot)
     DevBuf sell_pos; // int32[n]: string held by each sliced-ELL position (see sell_positions)
     int64_t sell_entries = 0;
+    // singles only, when the spin has at most 2^18 strings: the sliced-ELL entries
+    // in 32 bits, J | (a*norb + i) << 18 | (sign < 0) << 31; padding J = 0,
+    // pair index norb*norb (it reads a zero of the staged integral slice)
+    DevBuf sell32;
 };
 }  // namespace sbd
 
@@ -156,6 +160,7 @@ struct SigmaTune {
     int stream_rw = 1;           // output rows per stream wavefront (1 or 2)
     int stream_wide = 1;         // 1: 16-byte lane loads in the row streams where possible
     int stream_split = 1;        // ket entries per load step of a stream wavefront (1, 2, 4)
+    int ab_compact = 1;          // 1: alpha-beta walk over the 32-bit beta entries where built
 };
 
 struct SpinCoef {
@@ -209,6 +214,9 @@ hipError_t launch_exclusive_scan(const int64_t* d_in, int64_t n, int64_t* d_out 
 hipError_t launch_exc_fill(const uint64_t* d_s, int64_t n, const int64_t* rp1, const int64_t* rp2,
                            int32_t* J1, uint32_t* orb1, int8_t* sg1, int32_t* J2, uint32_t* orb2,
                            int8_t* sg2, hipStream_t st);
+// 32-bit sliced-ELL entries (Table::sell32) from the 64-bit ones
+constexpr int kSellJBits = 18;
+hipError_t launch_sell_compact(const uint64_t* sell, int64_t n_entries, int norb, uint32_t* out, hipStream_t st);
 hipError_t launch_pack_singles(int64_t nnz, const int32_t* J, const uint32_t* orb, const int8_t* sg,
                                uint64_t* pack, hipStream_t st);
 // sliced-ELL: slots[slice] = 64 * longest row of the slice; then fill from the scan
@@ -251,6 +259,7 @@ struct SigmaArgs {
     const int64_t* b1p; const int32_t* b1J; const T* b1c; const int32_t* b1ps;
     const uint64_t* b1pack;
     const uint64_t* b1sell; const int64_t* b1sell_off; const int32_t* b1sell_pos;
+    const uint32_t* b1sell32;  // null when the compact table is absent
     const int64_t* b2p; const int32_t* b2J; const T* b2c;
     const T* Ga;   // [npair][na]  sum_{k in alpha(ia)} (pair|kk)
     const T* Gb;   // [npair][nb]

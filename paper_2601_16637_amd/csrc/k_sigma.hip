@@ -541,6 +541,142 @@ __global__ void __launch_bounds__(1024) k_ab(AbArgs<T> A, const T* __restrict__ 
     }
 }
 
+// Alpha-beta term over the 32-bit sliced-ELL beta singles (Table::sell32).  The
+// same work as k_ab with a lean walk: the alpha single's sign is folded into
+// its staged integral slice, the beta single's sign is the entry's top bit, and
+// padding entries read a zero placed after the slice, so the walk has no
+// per-lane branches; a wavefront's 64 positions form one slice, so its slot
+// loop is uniform (scalar loop bound and offsets).  WIN: ket rows staged in
+// column windows (entries outside the window read the zero).
+template <class T>
+struct Ab2Args {
+    int64_t na, nb;
+    int norb;
+    int64_t win;    // ket columns staged per row (nb: whole rows)
+    int krows;      // alpha singles staged together
+    const int64_t* a1p;
+    const uint64_t* a1pack;
+    const uint32_t* sell;
+    const int64_t* sell_off;
+    const int32_t* pos;
+    const T* eri;
+};
+
+template <class T, int NV, int Q, int KT, bool WIN>
+__global__ void __launch_bounds__(1024) k_ab2(Ab2Args<T> A, const T* __restrict__ c, T* __restrict__ y) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = A.norb, n2 = n * n;
+    const int S = (n2 + 1 + 3) & ~3;  // slice stride: the pair's integrals, then a zero
+    T* slices = reinterpret_cast<T*>(smem);
+    T* rows = slices + (size_t)KT * S;
+    const int64_t rstride = A.win * NV;
+    const int64_t ia = blockIdx.x;
+    const int64_t nb = A.nb;
+    const int64_t t0 = A.a1p[ia], t1 = A.a1p[ia + 1];
+    if (t0 == t1) return;  // no alpha single: nothing to add (uniform exit)
+    const int lane = threadIdx.x & 63;
+    const int64_t wcol0 = (int64_t)blockIdx.y * blockDim.x * Q +
+                          __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
+    int64_t soff[Q];
+    int slen[Q];
+    T acc[Q][NV];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t ibw = wcol0 + (int64_t)q * blockDim.x;
+        const int64_t sl = ibw >> 6;
+        soff[q] = ibw < nb ? A.sell_off[sl] : 0;
+        slen[q] = ibw < nb ? (int)((A.sell_off[sl + 1] - A.sell_off[sl]) >> 6) : 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[q][v] = T(0);
+    }
+    const uint32_t jmask = (1u << kSellJBits) - 1u;
+    const uint32_t pad = (uint32_t)n2 << kSellJBits;  // reads the zero after the slice
+    constexpr int UA = 4;  // entries whose loads, then LDS reads, are issued together
+    for (int64_t tg = t0; tg < t1; tg += KT) {
+        const int kk = (int)((t1 - tg) < KT ? (t1 - tg) : KT);
+        // rows of unused slots alias row 0: their slices are all zero
+        int rb[KT];
+#pragma unroll
+        for (int tt = 0; tt < KT; ++tt) rb[tt] = (tt < kk ? tt : 0) * (int)rstride;
+        for (int64_t w0 = 0; w0 < nb; w0 += A.win) {
+            const int64_t wl = (nb - w0) < A.win ? (nb - w0) : A.win;
+            __syncthreads();
+            for (int tt = 0; tt < KT; ++tt) {
+                if (w0 == 0) {  // (a_a i_a | . .) times the alpha single's sign; zeros for unused slots
+                    if (tt < kk) {
+                        const uint64_t pa = A.a1pack[tg + tt];
+                        const int ai = (int)((pa >> 32) & 255), aa = (int)((pa >> 40) & 255);
+                        const bool neg = (pa >> 48) & 1;
+                        const T* sl = A.eri + ((size_t)aa * n + ai) * n2;
+                        for (int k = threadIdx.x; k < n2; k += blockDim.x) {
+                            const T v = sl[k];
+                            slices[tt * S + k] = neg ? -v : v;
+                        }
+                    } else {
+                        for (int k = threadIdx.x; k < n2; k += blockDim.x) slices[tt * S + k] = T(0);
+                    }
+                    if (threadIdx.x == 0) slices[tt * S + n2] = T(0);
+                }
+                if (tt < kk) {
+                    const int64_t ja = (int64_t)(A.a1pack[tg + tt] & 0xffffffffull);
+                    stage_row<T>(rows + tt * rstride, c + (ja * nb + w0) * NV, wl * NV);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const uint32_t* ep = A.sell + soff[q] + lane;
+                const int L = slen[q];
+                // UA slots' entries are loaded before any is used (slots past the
+                // slice's end read as padding), then all their LDS reads are issued
+                for (int s = 0; s < L; s += UA) {
+                    uint32_t e[UA];
+#pragma unroll
+                    for (int u = 0; u < UA; ++u) e[u] = (s + u < L) ? ep[(int64_t)(s + u) * 64] : pad;
+                    T gv[UA][KT], xv[UA][KT][NV];
+                    bool ng[UA];
+#pragma unroll
+                    for (int u = 0; u < UA; ++u) {
+                        int jb = (int)(e[u] & jmask);
+                        int g = (int)((e[u] >> kSellJBits) & 0x1fffu);
+                        ng[u] = (e[u] >> 31) != 0;
+                        if (WIN) {
+                            const bool in = (unsigned)(jb - w0) < (unsigned)wl;
+                            jb = in ? (int)(jb - w0) : 0;
+                            g = in ? g : n2;
+                        }
+#pragma unroll
+                        for (int tt = 0; tt < KT; ++tt) {
+                            gv[u][tt] = slices[tt * S + g];
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) xv[u][tt][v] = rows[rb[tt] + jb * NV + v];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < UA; ++u)
+#pragma unroll
+                        for (int tt = 0; tt < KT; ++tt) {
+                            const T gs = ng[u] ? -gv[u][tt] : gv[u][tt];
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) acc[q][v] += gs * xv[u][tt][v];
+                        }
+                }
+            }
+        }
+    }
+    const int64_t col0 = (int64_t)blockIdx.y * blockDim.x * Q + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t p = col0 + (int64_t)q * blockDim.x;  // sliced-ELL position
+        if (p < nb) {
+            const int64_t ib = A.pos[p];
+            T* dst = y + (ia * nb + ib) * NV;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) dst[v] += acc[q][v];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 // 16-byte aligned (vectors are only guaranteed 8-byte alignment)
 inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
@@ -644,6 +780,39 @@ hipError_t ab_launch(const AbArgs<T>& A, const T* c, T* y, int threads, size_t l
     return hipGetLastError();
 }
 
+template <class T, int NV, int Q, int KT>
+hipError_t ab2_launch_k(const Ab2Args<T>& A, const T* c, T* y, int threads, size_t lds, int64_t passes,
+                        hipStream_t st) {
+    const bool win = A.win < A.nb;
+    auto kern = win ? k_ab2<T, NV, Q, KT, true> : k_ab2<T, NV, Q, KT, false>;
+    static const hipError_t attr_w = max_lds_per_block() > 65536
+                                         ? hipFuncSetAttribute((const void*)k_ab2<T, NV, Q, KT, true>,
+                                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                               max_lds_per_block())
+                                         : hipSuccess;
+    static const hipError_t attr_f = max_lds_per_block() > 65536
+                                         ? hipFuncSetAttribute((const void*)k_ab2<T, NV, Q, KT, false>,
+                                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                               max_lds_per_block())
+                                         : hipSuccess;
+    const hipError_t attr = win ? attr_w : attr_f;
+    if (lds > 65536 && attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(kern, dim3((unsigned)A.na, (unsigned)passes), dim3(threads), lds, st, A, c, y);
+    return hipGetLastError();
+}
+
+// KT: staged rows per group as a compile-time count (1, 2 or 4; A.krows is set to it)
+template <class T, int NV, int Q>
+hipError_t ab2_launch(Ab2Args<T> A, const T* c, T* y, int threads, size_t slice_bytes, size_t row_bytes,
+                      int64_t passes, hipStream_t st) {
+    const int KT = A.krows >= 4 ? 4 : (A.krows >= 2 ? 2 : 1);
+    A.krows = KT;
+    const size_t lds = (size_t)KT * (slice_bytes + row_bytes);
+    if (KT == 4) return ab2_launch_k<T, NV, Q, 4>(A, c, y, threads, lds, passes, st);
+    if (KT == 2) return ab2_launch_k<T, NV, Q, 2>(A, c, y, threads, lds, passes, st);
+    return ab2_launch_k<T, NV, Q, 1>(A, c, y, threads, lds, passes, st);
+}
+
 // Largest columns-per-thread of the alpha-beta kernel that keeps the
 // accumulators and entry bounds within 64 VGPRs (1024-thread workgroups allow 128).
 template <class T, int NV>
@@ -654,7 +823,8 @@ constexpr int ab_qmax() {
 }
 
 template <class T, int NV>
-hipError_t alpha_beta(AbArgs<T> A, const T* c, T* y, const SigmaTune& tune, hipStream_t st) {
+hipError_t alpha_beta(AbArgs<T> A, const T* c, T* y, const SigmaTune& tune, const uint32_t* sell32,
+                      hipStream_t st) {
     if (A.na > 0x7fffffffLL) return hipErrorInvalidValue;
     const int threads = ab_block_threads(A.nb);
     constexpr int QM = ab_qmax<T, NV>();
@@ -668,7 +838,8 @@ hipError_t alpha_beta(AbArgs<T> A, const T* c, T* y, const SigmaTune& tune, hipS
             Q = s;
             if (s >= per) break;
         }
-    const size_t slice_bytes = (size_t)((A.norb * A.norb + 3) & ~3) * sizeof(T);
+    // the compact walk stages one more slice element (a zero read by padding entries)
+    const size_t slice_bytes = (size_t)((A.norb * A.norb + (sell32 ? 1 : 0) + 3) & ~3) * sizeof(T);
     size_t budget = (size_t)tune.ab_lds_bytes;
     const size_t hw = (size_t)max_lds_per_block();
     if (budget > hw) budget = hw;
@@ -685,6 +856,22 @@ hipError_t alpha_beta(AbArgs<T> A, const T* c, T* y, const SigmaTune& tune, hipS
         A.win = win > A.nb ? A.nb : win;
     }
     const size_t lds = (size_t)A.krows * (slice_bytes + (size_t)A.win * NV * sizeof(T));
+    if (sell32) {
+        Ab2Args<T> B{};
+        B.na = A.na; B.nb = A.nb; B.norb = A.norb; B.win = A.win; B.krows = A.krows;
+        B.a1p = A.a1p; B.a1pack = A.a1pack; B.sell = sell32; B.sell_off = A.b1sell_off; B.pos = A.b1pos;
+        B.eri = A.eri;
+        const size_t rb = (size_t)A.win * NV * sizeof(T);
+        switch (Q) {
+            case 1: return ab2_launch<T, NV, 1>(B, c, y, threads, slice_bytes, rb, passes, st);
+            case 2: return ab2_launch<T, NV, (QM < 2 ? QM : 2)>(B, c, y, threads, slice_bytes, rb, passes, st);
+            case 4: return ab2_launch<T, NV, (QM < 4 ? QM : 4)>(B, c, y, threads, slice_bytes, rb, passes, st);
+            case 6: return ab2_launch<T, NV, (QM < 6 ? QM : 6)>(B, c, y, threads, slice_bytes, rb, passes, st);
+            case 8: return ab2_launch<T, NV, (QM < 8 ? QM : 8)>(B, c, y, threads, slice_bytes, rb, passes, st);
+            case 10: return ab2_launch<T, NV, (QM < 10 ? QM : 10)>(B, c, y, threads, slice_bytes, rb, passes, st);
+            default: return ab2_launch<T, NV, QM>(B, c, y, threads, slice_bytes, rb, passes, st);
+        }
+    }
     switch (Q) {
         case 1: return ab_launch<T, NV, 1>(A, c, y, threads, lds, passes, st);
         case 2: return ab_launch<T, NV, (QM < 2 ? QM : 2)>(A, c, y, threads, lds, passes, st);
@@ -727,7 +914,7 @@ hipError_t sigma_nv(const SigmaArgs<T>& A, const T* c, T* y, T* cT, T* yT, const
     B.a1p = A.a1p; B.a1pack = A.a1pack; B.b1sell = A.b1sell; B.b1sell_off = A.b1sell_off;
     B.b1pos = A.b1sell_pos;
     B.eri = A.eri;
-    e = alpha_beta<T, NV>(B, c, y, tune, st);
+    e = alpha_beta<T, NV>(B, c, y, tune, tune.ab_compact ? A.b1sell32 : nullptr, st);
     if (e == hipSuccess) e = mark(4);
     if (e != hipSuccess) return e;
     e = transpose<T, NV, true>(yT, y, nb, na, st);

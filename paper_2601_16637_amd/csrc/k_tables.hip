@@ -256,9 +256,30 @@ __global__ void k_sell_fill(const int64_t* __restrict__ rp, const uint64_t* __re
         sell[off[sl] + s * 64 + lane] = (s < rl) ? pack[r0 + s] : ~0ull;
 }
 
+// 32-bit form of the sliced-ELL singles: J | (a*norb + i) << 18 | neg << 31;
+// padding entries take J = 0 and the pair index norb*norb.
+__global__ void k_sell_compact(const uint64_t* __restrict__ sell, int64_t ne, int norb, uint32_t* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ne) return;
+    const uint64_t e = sell[i];
+    if (e == ~0ull) {
+        out[i] = (uint32_t)(norb * norb) << kSellJBits;
+        return;
+    }
+    const uint32_t J = (uint32_t)(e & 0xffffffffull);
+    const uint32_t g = (uint32_t)((e >> 40) & 255) * (uint32_t)norb + (uint32_t)((e >> 32) & 255);
+    out[i] = J | (g << kSellJBits) | ((uint32_t)((e >> 48) & 1) << 31);
+}
+
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
+
+hipError_t launch_sell_compact(const uint64_t* sell, int64_t ne, int norb, uint32_t* out, hipStream_t st) {
+    if (ne > 0)
+        hipLaunchKernelGGL(k_sell_compact, dim3(blocks_for(ne, 256)), dim3(256), 0, st, sell, ne, norb, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_sort_unique(uint64_t* d_work, int64_t n, uint64_t* d_out, int64_t* d_count,
                               int64_t* /*d_tmp*/, hipStream_t st) {

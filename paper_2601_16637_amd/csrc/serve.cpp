@@ -231,9 +231,9 @@ extern "C" int sbd_serve_estimate(const sbd_request* q, size_t* bytes) {
         const double s1 = std::min(n * (double)(norb - n), ns - 1);
         const double s2 = std::min(binom(n, 2) * binom(norb - n, 2), ns - 1);
         total += np * ns * 12 + ns * 8;
-        // tables: J, orbitals, sign, packed and sliced-ELL singles, coefficients, row pointers,
-        // build temporaries; the basis sort's power-of-two scratch
-        total += ns * (s1 * (4 + 4 + 1 + 8 + 16 + 12 + 4) + s2 * (4 + 4 + 1 + 12)) + 6 * (ns + 1) * 8;
+        // tables: J, orbitals, sign, packed, sliced-ELL (64- and 32-bit) singles, coefficients,
+        // row pointers, build temporaries; the basis sort's power-of-two scratch
+        total += ns * (s1 * (4 + 4 + 1 + 8 + 16 + 8 + 12 + 4) + s2 * (4 + 4 + 1 + 12)) + 6 * (ns + 1) * 8;
         double p2 = 1;
         while (p2 < ns) p2 *= 2;
         total += p2 * 8 + ns * 8 + 64;
