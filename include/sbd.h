@@ -305,6 +305,16 @@ typedef struct {
     int verbose;           /* 1: print one line per iteration to stderr                            */
     int block_sigma;       /* 1 (default): the new vectors of an iteration share one interleaved
                               sigma (several roots); 0: one sigma launch sequence per vector      */
+    int device_iterations; /* 0 (default): the host takes each iteration's decisions.  n > 0:
+                              iterations run device-driven (Ritz pairs by a one-workgroup Jacobi,
+                              convergence, restart and acceptance of corrections decided on the
+                              device, two Gram-Schmidt passes per correction) in batches of n
+                              between host checks; with use_graph each iteration is one replay of
+                              a captured HIP graph that serves every subspace size.  When the
+                              device stops (convergence, an FP64 refresh of a mixed-precision
+                              solve, stagnation) one host iteration handles it.  Needs
+                              nroots <= 8, max_space >= 2 nroots + 1 and, for several roots,
+                              block_sigma; otherwise the host decides every iteration         */
 } sbd_davidson_opts;
 
 typedef struct {
@@ -324,6 +334,8 @@ typedef struct {
     int n_history;         /* entries filled in theta_history                                       */
     double theta_history[512]; /* lowest Ritz value per iteration (first 512 iterations)            */
     double time_history_ms[512]; /* wall time since the call started, per iteration                 */
+    int device_iterations; /* iterations run device-driven (opts.device_iterations)                 */
+    double t_device_ms;    /* wall time of the device-driven batches (their sigma included)         */
 } sbd_davidson_report;
 
 void sbd_davidson_default_opts(sbd_davidson_opts* o);

@@ -49,7 +49,7 @@ class DavidsonOpts(ctypes.Structure):
                 ("sigma_prec", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("use_autotune", ctypes.c_int), ("guess", ctypes.c_void_p),
                 ("n_guess", ctypes.c_int), ("verbose", ctypes.c_int),
-                ("block_sigma", ctypes.c_int)]
+                ("block_sigma", ctypes.c_int), ("device_iterations", ctypes.c_int)]
 
 
 class DavidsonReport(ctypes.Structure):
@@ -62,7 +62,8 @@ class DavidsonReport(ctypes.Structure):
                 ("t_update_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("t_workspace_ms", ctypes.c_double), ("t_autotune_ms", ctypes.c_double),
                 ("n_history", ctypes.c_int), ("theta_history", ctypes.c_double * 512),
-                ("time_history_ms", ctypes.c_double * 512)]
+                ("time_history_ms", ctypes.c_double * 512), ("device_iterations", ctypes.c_int),
+                ("t_device_ms", ctypes.c_double)]
 
     def as_dict(self, nroots: int) -> dict:
         n = self.n_history
@@ -76,7 +77,8 @@ class DavidsonReport(ctypes.Structure):
                     t_update_ms=self.t_update_ms, t_total_ms=self.t_total_ms,
                     t_workspace_ms=self.t_workspace_ms, t_autotune_ms=self.t_autotune_ms,
                     theta_history=list(self.theta_history[:n]),
-                    time_history_ms=list(self.time_history_ms[:n]))
+                    time_history_ms=list(self.time_history_ms[:n]),
+                    device_iterations=self.device_iterations, t_device_ms=self.t_device_ms)
 
 
 class SqdOpts(ctypes.Structure):

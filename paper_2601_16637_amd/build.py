@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(HERE, "libsbd.so")
-SOURCES = ["abi.cpp", "davidson.cpp", "tune.cpp", "serve.cpp", "pool.cpp", "noalloc.cpp", "full.cpp", "sqd.cpp", "k_tables.hip", "k_ham.hip", "k_sigma.hip", "k_vec.hip", "k_project.hip", "k_csr.hip", "k_full.hip"]
+SOURCES = ["abi.cpp", "davidson.cpp", "tune.cpp", "serve.cpp", "pool.cpp", "noalloc.cpp", "full.cpp", "sqd.cpp", "k_tables.hip", "k_ham.hip", "k_sigma.hip", "k_vec.hip", "k_project.hip", "k_csr.hip", "k_full.hip", "k_devloop.hip"]
 ARCH = os.environ.get("SBD_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -37,6 +37,8 @@
 #include <cmath>
 #include <cstdio>
 #include <map>
+#include <cstring>
+#include <memory>
 #include <tuple>
 #include <vector>
 
@@ -160,30 +162,43 @@ struct Solver {
     std::map<std::tuple<int, int, bool>, hipGraphExec_t> graphs;
     std::map<std::tuple<int, int, bool>, int> seen;
     DevBuf rowsel;           // device int: basis row of the sigma being replayed
+    // device-driven iterations: state, partial sums, captured iteration graph
+    bool dev = false;
+    DevBuf dls, dlpart;
+    hipGraphExec_t dl_graph = nullptr;
+    int dev_iters = 0;       // iterations run device-driven
+    double t_device = 0.0;
     int staged_row = -1;     // basis row whose FP32 copy already sits in x32 (eager path)
     int dot_row = -1;        // basis row whose v . w the last restore left at sm + kDot
     double dot_value = 0.0;  // that v . w, read back by apply_sigma
 
     ~Solver() {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+        if (dl_graph) (void)hipGraphExecDestroy(dl_graph);
     }
 
     double* Vr(int j) { return V.as<double>() + (size_t)j * N; }
     double* Wr(int j) { return W.as<double>() + (size_t)j * N; }
 
     int alloc() {
-        hipError_t e = V.alloc(sizeof(double) * (size_t)ms * N);
-        if (e == hipSuccess) e = W.alloc(sizeof(double) * (size_t)ms * N);
+        // device-driven iterations: spare rows past ms take the sigma of a stopped iteration
+        const size_t rows = (size_t)ms + (dev ? kDlMaxRoots : 0);
+        hipError_t e = V.alloc(sizeof(double) * rows * N);
+        if (e == hipSuccess) e = W.alloc(sizeof(double) * rows * N);
         if (e == hipSuccess) e = tmp.alloc(sizeof(double) * (size_t)std::max(k, keep) * N);
-        if (e == hipSuccess) e = scr.alloc(sizeof(double) * (size_t)keep * N);
+        // (device-driven iterations collapse V and W together through scratch)
+        if (e == hipSuccess) e = scr.alloc(sizeof(double) * (size_t)keep * N * (dev ? 2 : 1));
         if (e == hipSuccess) e = part.alloc(sizeof(double) * kPartRows * kRedBlocks);
         if (e == hipSuccess) e = small.alloc(sizeof(double) * kSmall);
         if (e == hipSuccess) e = idx.alloc(sizeof(int64_t) * (kRedBlocks + 1));
         if (e == hipSuccess) e = sws.alloc(op->ws_bytes(nvmax, nvmax > 1 ? 1 : 0, sizeof(double)));
-        const bool stage64 = nvmax > 1 || use_graph;  // FP64 staging: block sigma or graph replays
+        // FP64 staging: block sigma, graph replays, device-driven iterations
+        const bool stage64 = nvmax > 1 || use_graph || dev;
         if (stage64 && e == hipSuccess) e = x64.alloc(sizeof(double) * (size_t)nvmax * N);
         if (stage64 && e == hipSuccess) e = y64.alloc(sizeof(double) * (size_t)nvmax * N);
-        if (use_graph && e == hipSuccess) e = rowsel.alloc(sizeof(int));
+        if ((use_graph || dev) && e == hipSuccess) e = rowsel.alloc(sizeof(int));
+        if (dev && e == hipSuccess) e = dls.alloc(sizeof(DlState));
+        if (dev && e == hipSuccess) e = dlpart.alloc(sizeof(double) * (size_t)kDlBlocks * kDlMaxSpace * kDlMaxRoots);
         if (mixed && e == hipSuccess) e = x32.alloc(sizeof(float) * (size_t)std::max(ms, nvmax) * N);
         if (mixed && e == hipSuccess) e = y32.alloc(sizeof(float) * (size_t)std::max(ms, nvmax) * N);
         if (e != hipSuccess) return hip_fail(e, "sbd_davidson workspace");
@@ -319,6 +334,98 @@ struct Solver {
         return SBD_OK;
     }
 
+    // One device-driven iteration (no host decision): the pre-sigma kernels, the
+    // sigma of rows [m_old, m_old + k) through the staging buffers, the T update.
+    int dl_launch(int nv) {
+        DlState* d = dls.as<DlState>();
+        SBD_HIP(dl_iteration_pre(d, V.as<double>(), W.as<double>(), op->diag, tmp.as<double>(), scr.as<double>(),
+                                 N, k, dlpart.as<double>(), rowsel.as<int>(), st));
+        const int rc = sigma_launches_indexed(k, nv, !mixed);
+        if (rc) return rc;
+        SBD_HIP(dl_iteration_post(d, V.as<double>(), W.as<double>(), N, dlpart.as<double>(), st));
+        return SBD_OK;
+    }
+
+    // Device-driven iterations from the host's state (m, T, error bounds) until
+    // the device stops; the host reads the state back every `batch` iterations.
+    // The iteration is replayed from a graph captured on first use when graphs
+    // are on (one graph for every subspace size: all sizes live on the device).
+    int device_batches(int batch, int max_iter, double tol, double delta, double rho, int& m,
+                       std::vector<double>& T, std::vector<double>& ebound, int& since_cert, int& it,
+                       int& restarts, std::vector<double>& hist_theta, std::vector<double>& hist_time,
+                       int& hist_n, clk::time_point t_start) {
+        const auto t0 = clk::now();
+        std::unique_ptr<DlState> h(new DlState());
+        std::memset(h.get(), 0, sizeof(DlState));
+        h->m = m; h->k = k; h->ms = ms; h->keep = keep;
+        h->it = it; h->max_iter = max_iter; h->since_cert = since_cert;
+        h->tol = tol; h->delta = delta; h->rho = mixed ? rho : 0.0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) h->T[i * ms + j] = T[i * ms + j];
+        for (int j = 0; j < ms + 8 && j < kDlMaxSpace + 8; ++j) h->ebound[j] = ebound[j];
+        DlState* d = dls.as<DlState>();
+        SBD_HIP(hipMemcpyAsync(d, h.get(), sizeof(DlState), hipMemcpyHostToDevice, st));
+        SBD_HIP(hipStreamSynchronize(st));
+        static const double clock_khz = [] {
+            int dev = 0, r = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&r, hipDeviceAttributeWallClockRate, dev) != hipSuccess || r <= 0)
+                return 100000.0;
+            return (double)r;
+        }();
+        const double host0 = ms_since(t_start);
+        SBD_HIP(launch_clock_read(&d->hist_clock[kDlHistory - 1], st));
+        const int nv = k == 1 ? 1 : block_width(k);
+        const int it0 = it;
+        while (true) {
+            for (int b = 0; b < batch; ++b) {
+                if (use_graph) {
+                    if (!dl_graph) {
+                        SBD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                        const int rc = dl_launch(nv);
+                        hipGraph_t g = nullptr;
+                        const hipError_t e = hipStreamEndCapture(st, &g);
+                        if (rc) {
+                            if (g) (void)hipGraphDestroy(g);
+                            return rc;
+                        }
+                        if (e != hipSuccess) return hip_fail(e, "device iteration capture");
+                        const hipError_t e2 = hipGraphInstantiate(&dl_graph, g, nullptr, nullptr, 0);
+                        (void)hipGraphDestroy(g);
+                        if (e2 != hipSuccess) return hip_fail(e2, "device iteration graph instantiate");
+                    }
+                    SBD_HIP(hipGraphLaunch(dl_graph, st));
+                } else {
+                    const int rc = dl_launch(nv);
+                    if (rc) return rc;
+                }
+            }
+            SBD_HIP(hipMemcpyAsync(h.get(), d, sizeof(DlState), hipMemcpyDeviceToHost, st));
+            SBD_HIP(hipStreamSynchronize(st));
+            if (h->stop) break;
+        }
+        // the host's view of the state
+        m = h->m;
+        for (int i = 0; i < ms; ++i)
+            for (int j = 0; j < ms; ++j) T[i * ms + j] = (i < m && j < m) ? h->T[i * ms + j] : 0.0;
+        for (int j = 0; j < ms + 8 && j < kDlMaxSpace + 8; ++j) ebound[j] = h->ebound[j];
+        since_cert = h->since_cert;
+        restarts += h->restarts;
+        const int done = h->it - it0;
+        it = h->it;
+        dev_iters += done;
+        sigma_calls += done * k;
+        if (!mixed) sigma64 += done * k;
+        const unsigned long long c0 = h->hist_clock[kDlHistory - 1];
+        for (int i = 0; i < h->hist_n && hist_n < 512; ++i) {
+            hist_theta.push_back(h->hist_theta[i]);
+            hist_time.push_back(host0 + (double)(h->hist_clock[i] - c0) / clock_khz);
+            ++hist_n;
+        }
+        t_device += ms_since(t0);
+        return SBD_OK;
+    }
+
     // out[j*k + q] = P_j . X_q for j < mp, q < k (host copy); k <= 8, mp <= 48
     int project(const double* P, int mp, const double* X, int k, std::vector<double>& out) {
         out.assign((size_t)mp * k, 0.0);
@@ -428,6 +535,7 @@ extern "C" void sbd_davidson_default_opts(sbd_davidson_opts* o) {
     o->n_guess = 0;
     o->verbose = 0;
     o->block_sigma = 1;
+    o->device_iterations = 0;
 }
 
 extern "C" int sbd_davidson(const sbd_basis* b, const sbd_exc* x, const sbd_ham* H, int nroots,
@@ -508,6 +616,8 @@ int davidson_run(const SigmaOp& op, int k, const sbd_davidson_opts& o, double* e
     // block solves gather all new vectors of an iteration in one interleaved sigma
     S.nvmax = (k < 2 || !o.block_sigma) ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));
     S.use_graph = o.use_graph != 0;
+    S.dev = o.device_iterations > 0 && k <= kDlMaxRoots && ms >= 2 * k + 1 && ms <= kDlMaxSpace &&
+            S.keep <= kDlMaxKeep && (k == 1 || S.nvmax >= k);
     const auto tw = clk::now();
     int rc = S.alloc();
     if (rc) return rc;
@@ -607,6 +717,15 @@ int davidson_run(const SigmaOp& op, int k, const sbd_davidson_opts& o, double* e
     std::vector<double> hist_theta, hist_time;
     int status = SBD_OK;
     while (true) {
+        if (S.dev) {
+            // device-driven iterations until the device stops; the host iteration
+            // below then handles the stop (convergence, FP64 refresh, stagnation)
+            int hn = hist_n;
+            rc = S.device_batches(o.device_iterations, o.max_iter, o.tol_residual, o.precond_delta, rho, m, T,
+                                  ebound, since_cert, it, restarts, hist_theta, hist_time, hn, t_start);
+            if (rc) return rc;
+            hist_n = hn;
+        }
         ++it;
         auto tu0 = clk::now();
         std::vector<double> Tm((size_t)m * m);
@@ -945,6 +1064,8 @@ int davidson_run(const SigmaOp& op, int k, const sbd_davidson_opts& o, double* e
         report->t_workspace_ms = t_workspace;
         report->t_autotune_ms = t_autotune;
         report->n_history = hist_n;
+        report->device_iterations = S.dev_iters;
+        report->t_device_ms = S.t_device;
         for (int i = 0; i < hist_n; ++i) {
             report->theta_history[i] = hist_theta[i];
             report->time_history_ms[i] = hist_time[i];

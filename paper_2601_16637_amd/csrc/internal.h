@@ -345,6 +345,45 @@ struct FullSigmaArgs {
 template <class T>
 hipError_t launch_full_sigma(const FullSigmaArgs& S, int nvec, const T* x, T* y, int layout, hipStream_t st);
 
+// Device-resident state of device-driven Davidson iterations (k_devloop.hip).
+constexpr int kDlMaxSpace = 48;   // subspace rows
+constexpr int kDlMaxRoots = 8;
+constexpr int kDlMaxKeep = 16;    // vectors kept by a thick restart
+constexpr int kDlBlocks = 256;    // grid of the sweeps (partial sums per block)
+constexpr int kDlHistory = 512;
+enum { kDlRunning = 0, kDlConverged = 1, kDlRefresh = 2, kDlMaxIter = 3, kDlStagnation = 4, kDlNumeric = 5 };
+struct DlState {
+    int m, k, ms, keep;          // subspace size, roots, maximum size, restart size
+    int it, max_iter;            // iterations so far (all of the solve), limit
+    int stop;                    // kDl* reason; nonzero makes the rest of a queued batch a no-op
+    int restart, m_old, m_cur, since_cert, restarts;
+    int active[kDlMaxRoots], row[kDlMaxRoots];
+    int hist_n;
+    unsigned cnt[8];             // completion counters of the fused reductions (zero between launches)
+    double tol, delta, rho;
+    double theta[kDlMaxRoots], rnorm[kDlMaxRoots], tnorm[kDlMaxRoots], ebnd[kDlMaxRoots];
+    double scale[kDlMaxRoots];
+    double evals[kDlMaxSpace];
+    double h[kDlMaxSpace];
+    double T[kDlMaxSpace * kDlMaxSpace];
+    double Y[kDlMaxSpace * kDlMaxRoots];
+    double Yc[kDlMaxSpace * kDlMaxKeep];
+    double ebound[kDlMaxSpace + 8];
+    double red[kDlMaxSpace * kDlMaxRoots];
+    double hist_theta[kDlHistory];
+    unsigned long long hist_clock[kDlHistory];  // device wall clock at each iteration's decision
+};
+// One device-driven iteration: Ritz pairs, residuals, decisions, restart,
+// Gram-Schmidt of the corrections, the row index of the coming sigma
+// (rows [m_old, m_old + k); row ms when stopped); then, after that sigma,
+// the new entries of T.  part: kDlBlocks x (kDlMaxSpace x kDlMaxRoots) doubles.
+hipError_t dl_iteration_pre(DlState* S, double* V, double* W, const double* diag, double* tmp, double* scr,
+                            int64_t N, int k, double* part, int* rowsel, hipStream_t st);
+// *out = the device wall clock (s_memrealtime)
+hipError_t launch_clock_read(unsigned long long* out, hipStream_t st);
+hipError_t dl_iteration_post(DlState* S, const double* V, const double* W, int64_t N, double* part,
+                             hipStream_t st);
+
 // The operator a Davidson solve works on: N determinants, the FP64 diagonal
 // (start vectors, preconditioner), and y = (H - shift) c for nvec vectors in
 // either layout (as sbd_sigma), with a workspace of ws_bytes(nvec, layout,
