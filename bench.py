@@ -10,8 +10,9 @@ Davidson solve to ||r|| <= 1e-6 in plain FP64 and in the chosen form (FP32
 sigma with FP64 Gram-Schmidt / Rayleigh-Ritz / residuals and refinement),
 repeated the same number of times, with per-solve phase splits and the time
 to 1e-6 Ha of a tight FP64 reference energy; sigma rows of the sel16 and
-block20 workloads; the block, successive-solve, explicit-realization and
-serving legs; and the CPU oracle's sigma rate.
+block20 workloads; the block, SQD-loop (sbd_sqd_run on a sampled
+configuration record), explicit-realization, full-bitstring,
+device-driven-iteration and serving legs; and the CPU oracle's sigma rate.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sel26]
 """
@@ -53,18 +54,24 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel, workload):
-    """HBM bytes per launch from the committed rocprofv3 counter summary
-    (profiles/sigma_traffic.txt, lines 'kernel workload source_hash bytes'),
-    or None if it is missing or was taken on a different kernel source."""
+def traffic_lines(workload):
+    """{kernel: HBM bytes per launch} from the committed rocprofv3 counter
+    summary (profiles/sigma_traffic.txt, lines 'kernel workload source_hash
+    bytes') for kernels measured on the current kernel source."""
     p = os.path.join(ROOT, "profiles", "sigma_traffic.txt")
+    out = {}
     if not os.path.exists(p):
-        return None
+        return out
     for line in open(p):
         f = line.split()
-        if len(f) == 4 and not line.startswith("#") and f[0] == kernel and f[1] == workload:
-            return float(f[3]) if f[2] == kernel_source_hash() else None
-    return None
+        if len(f) == 4 and not line.startswith("#") and f[1] == workload and f[2] == kernel_source_hash():
+            out[f[0]] = float(f[3])
+    return out
+
+
+def traffic_for(kernel, workload):
+    """HBM bytes per launch of one kernel, or None if not measured on this source."""
+    return traffic_lines(workload).get(kernel)
 
 
 def time_to(hist_theta, hist_time, e_ref, tol=1e-6):
@@ -76,13 +83,14 @@ def time_to(hist_theta, hist_time, e_ref, tol=1e-6):
 
 def kernel_only(sbd, W, stream, prec):
     """Short run for hardware-counter passes: five sigma launches in precision
-    `prec` after autotuning, then one device copy of known size (N elements of
-    that precision read and written) that calibrates the counters."""
+    `prec` in the handle's default launch configuration (no autotuning, so each
+    stage runs exactly one kernel instantiation), then one device copy of known
+    size (N elements of that precision read and written) that calibrates the
+    counters."""
     import torch
     B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
     X = sbd.Excitations(B, stream=stream)
     H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
-    H.autotune(prec, stream=stream)
     dt = torch.float64 if prec == sbd.FP64 else torch.float32
     w = 8 if prec == sbd.FP64 else 4
     x = torch.randn(W.ndet, device="cuda", dtype=dt)
@@ -232,12 +240,15 @@ def _counter_values(csv_path, counter):
     return acc
 
 
+SIGMA_KERNELS = ("k_transpose", "k_transpose_v", "k_stream", "k_stream_ks", "k_ab", "k_ab2")
+
+
 def traffic_summary(fetch_csv, write_csv, kernel_json, workload):
-    """HBM bytes per launch of `kernel` from FETCH_SIZE / WRITE_SIZE runs (KiB per
-    dispatch), each scaled by what the counter reads for the calibration copy of
-    known size in the same --kernel-only run."""
+    """HBM bytes per launch of every sigma kernel of a --kernel-only run from
+    FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch, averaged over the kernel's
+    dispatches), each scaled by what the counter reads for the calibration copy
+    of known size in the same run."""
     info = json.loads([l for l in open(kernel_json) if l.startswith("{")][-1])
-    kernel = info["stream_kernel"]
     fv = _counter_values(fetch_csv, "FETCH_SIZE")
     wv = _counter_values(write_csv, "WRITE_SIZE")
     # the calibration copy is the largest blit of the run (the others upload inputs)
@@ -247,15 +258,19 @@ def traffic_summary(fetch_csv, write_csv, kernel_json, workload):
     fetch[copy], write[copy] = max(fv[copy]), max(wv[copy])
     f_scale = info["copy_bytes_read"] / (1024.0 * fetch[copy])
     w_scale = info["copy_bytes_written"] / (1024.0 * write[copy])
-    kf, kw = fetch[kernel] * 1024.0, write[kernel] * 1024.0
-    total = kf * f_scale + kw * w_scale
-    lines = [f"# {kernel} on {workload}: FETCH_SIZE {fetch[kernel]:.0f} KiB/dispatch (x{f_scale:.3f}), "
-             f"WRITE_SIZE {write[kernel]:.0f} KiB/dispatch (x{w_scale:.3f}); calibration copy "
-             f"{copy}: read {info['copy_bytes_read']} B, FETCH_SIZE {fetch[copy]:.0f} KiB, "
-             f"WRITE_SIZE {write[copy]:.0f} KiB",
-             f"# mean over {len(fv[kernel])} dispatches (alpha and beta launches)",
-             f"{kernel} {workload} {kernel_source_hash()} {total:.0f}"]
-    return "\n".join(lines)
+    lines = [f"# calibration copy {copy}: read {info['copy_bytes_read']} B, FETCH_SIZE {fetch[copy]:.0f} KiB "
+             f"(x{f_scale:.3f}), written {info['copy_bytes_written']} B, WRITE_SIZE {write[copy]:.0f} KiB "
+             f"(x{w_scale:.3f})"]
+    data = []
+    for kernel in sorted(fv):
+        if not kernel.split("<")[0] in SIGMA_KERNELS or kernel not in wv:
+            continue
+        kf, kw = fetch[kernel] * 1024.0, write[kernel] * 1024.0
+        total = kf * f_scale + kw * w_scale
+        lines.append(f"# {kernel}: FETCH_SIZE {fetch[kernel]:.0f} KiB, WRITE_SIZE {write[kernel]:.0f} KiB per "
+                     f"dispatch, mean over {len(fv[kernel])} dispatches")
+        data.append(f"{kernel} {workload} {kernel_source_hash()} {total:.0f}")
+    return "\n".join(lines + data)
 
 
 def block_leg(sbd, wl, stream):
@@ -290,48 +305,110 @@ def block_leg(sbd, wl, stream):
     return out
 
 
-def sqd_leg(sbd, wl, stream, sequences=(("coarse", (6000, 8000, 10000)), ("fine", (9000, 9500, 10000)))):
-    """Successive solves of an SQD run on a growing configuration set: sel26
-    string sets of increasing size per spin (nested: the same seeds draw the
-    larger sets as supersets), in a coarse and a fine growth sequence.  Cold:
-    each solve starts from the unit vector on the lowest diagonal entry.  Warm:
-    each solve after the first starts from the previous eigenvector carried
-    into the new basis (sbd_map_vectors).  Chosen form (FP32 sigma, FP64
-    refinement); each sequence runs once untimed (autotuning of its shapes) and
-    then cold and warm, timed, basis, tables and Hamiltonian included."""
+def sqd_leg(sbd, wl, stream, steps=(2500, 5000, 7500, 10000)):
+    """SQD outer loop (sbd_sqd_run, Sec. I) on a synthetic measurement record:
+    norb 26 with 7 + 7 electrons (the sel26 integrals), configurations drawn
+    with level weights, taken in growing prefixes; each step diagonalises over
+    the product of the distinct sampled strings (up to 1e8 determinants) in
+    the chosen form, cold and warm (previous eigenvector carried over)."""
     import torch
+    W = wl.make_config("sel26", nstr=10)
+    smp = wl.sample_configurations(W.norb, W.n_alpha, W.n_beta, max(steps), 3101)
+    out = dict(workload="sel26 integrals, sampled configurations", samples=max(steps), tol_residual=1e-6)
+    kw = dict(sigma_prec=sbd.FP32, tol_residual=1e-6, max_space=MAX_SPACE, use_autotune=1)
+    # untimed pass over every step first: the autotuner's measurements of each shape are cached
+    sbd.sqd_run(W.norb, W.n_alpha, W.n_beta, W.h, W.eri, W.e_core, smp, steps, stream=stream, **kw)
+    for name, warm in (("cold", False), ("warm", True)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e, rep = sbd.sqd_run(W.norb, W.n_alpha, W.n_beta, W.h, W.eri, W.e_core, smp, steps, warm_start=warm,
+                             stream=stream, **kw)
+        torch.cuda.synchronize()
+        out[name] = dict(ms=1e3 * (time.perf_counter() - t0), energies=[float(x) for x in e[:, 0]],
+                         steps=[dict(samples=r["samples"], strings=[r["n_alpha_str"], r["n_beta_str"]],
+                                     determinants=r["ndet"], iterations=r["iterations"],
+                                     setup_ms=r["setup_ms"], solve_ms=r["solve_ms"], status=r["status"])
+                                for r in rep])
+    out["energy_max_diff"] = float(max(abs(a - b) for a, b in zip(out["cold"]["energies"], out["warm"]["energies"])))
+    return out
 
-    def run(Ws, warm):
-        steps, prev = [], None
-        for W in Ws:
-            t0 = time.perf_counter()
-            B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
-            X = sbd.Excitations(B, stream=stream)
-            H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
-            kw = {}
-            if warm and prev is not None:
-                g = torch.empty(W.ndet, device="cuda", dtype=torch.float64)
-                sbd.map_vectors(prev[0], B, prev[1], g, stream=stream)
-                kw = dict(guess=g.view(1, -1), n_guess=1)
-            v = torch.empty(W.ndet, device="cuda", dtype=torch.float64)
-            e, rep, st = sbd.davidson(H, 1, vectors=v, stream=stream, tol_residual=1e-6, sigma_prec=sbd.FP32,
-                                      max_space=MAX_SPACE, use_autotune=1, **kw)
+
+def full_leg(sbd, wl, stream):
+    """Full-bitstring path (Sec. II-F, III-F) on determinant lists that are not
+    Cartesian products (full16: 1e6, full26: 4e6 determinants drawn from the
+    sel16 / sel26 string products): basis build (sort, groups, connections),
+    Hamiltonian, sigma per precision, and plain / chosen-form solves."""
+    import torch
+    out = []
+    for name in ("full16", "full26"):
+        F = wl.make_full_config(name)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B = sbd.FullBasis(F.norb, F.n_alpha, F.n_beta, F.dets, stream=stream)
+        t1 = time.perf_counter()
+        H = sbd.FullHamiltonian(B, F.h, F.eri, F.e_core, stream=stream)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        row = dict(workload=name, determinants=B.N, connections=B.nconn, alpha_strings=B.nalpha,
+                   basis_ms=1e3 * (t1 - t0), hamiltonian_ms=1e3 * (t2 - t1))
+        for prec, tag in ((sbd.FP64, "f64"), (sbd.FP32, "f32")):
+            dt = torch.float64 if prec == sbd.FP64 else torch.float32
+            x = torch.randn(B.N, device="cuda", dtype=dt)
+            y = torch.empty_like(x)
+            sbd.full_sigma(H, x, y, prec=prec, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(10):
+                sbd.full_sigma(H, x, y, prec=prec, stream=stream)
+            e1.record(stream)
             torch.cuda.synchronize()
-            steps.append(dict(strings_per_spin=int(W.alpha.size), determinants=W.ndet,
-                              ms=1e3 * (time.perf_counter() - t0), solver_ms=rep["t_total_ms"],
-                              iterations=rep["iterations"], sigma_calls=rep["sigma_calls"],
-                              energy=float(e[0]), status=int(st)))
-            prev = (B, v)
-        return steps
+            ms = e0.elapsed_time(e1) / 10
+            row[f"sigma_ms_{tag}"] = ms
+            row[f"sigma_det_per_s_{tag}"] = B.N / (ms * 1e-3)
+            row[f"connections_per_s_{tag}"] = (B.N + B.nconn) / (ms * 1e-3)
+        for form, prec in (("plain_fp64", sbd.FP64), ("chosen", sbd.FP32)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, rep, st = sbd.full_davidson(H, 1, stream=stream, tol_residual=1e-6, sigma_prec=prec,
+                                           max_space=MAX_SPACE)
+            torch.cuda.synchronize()
+            row[form] = dict(ms=1e3 * (time.perf_counter() - t0), iterations=rep["iterations"],
+                             sigma_calls=rep["sigma_calls"], energy=float(e[0]), status=int(st))
+        out.append(row)
+        del H, B
+    return out
 
-    out = dict(workload="sel26 nested string sets", tol_residual=1e-6)
-    for name, sizes in sequences:
-        Ws = [wl.make_config("sel26", nstr=n) for n in sizes]
-        run(Ws, False)
-        cold, warm = run(Ws, False), run(Ws, True)
-        out[name] = dict(strings_per_spin=list(sizes), cold=cold, warm=warm,
-                         cold_ms=sum(x["ms"] for x in cold), warm_ms=sum(x["ms"] for x in warm),
-                         energy_max_diff=max(abs(a["energy"] - b["energy"]) for a, b in zip(cold, warm)))
+
+def devloop_leg(sbd, wl, stream, sizes=(100, 300)):
+    """Device-driven iterations (opts.device_iterations = 8, whole iterations
+    replayed from one captured graph, one host synchronisation per batch)
+    against host-driven ones (sigma sequences replayed from graphs) on small
+    solves (sel16 subsets of 1e4 and 9e4 determinants), 1 and 2 roots, plain
+    and chosen form; median of three solves each."""
+    import torch
+    out = []
+    for nstr in sizes:
+        W = wl.make_config("sel16", nstr=nstr)
+        B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta, stream=stream)
+        X = sbd.Excitations(B, stream=stream)
+        H = sbd.Hamiltonian(B, X, W.h, W.eri, W.e_core, stream=stream)
+        for prec in (sbd.FP64, sbd.FP32):
+            for k in (1, 2):
+                row = dict(determinants=W.ndet, roots=k, precision="f64" if prec == sbd.FP64 else "f32")
+                for name, dev in (("host_driven", 0), ("device_driven", 8)):
+                    kw = dict(tol_residual=1e-6, sigma_prec=prec, max_space=20, use_graph=1, device_iterations=dev,
+                              use_autotune=1)
+                    sbd.davidson(H, k, stream=stream, **kw)
+                    ts = []
+                    for _ in range(3):
+                        torch.cuda.synchronize()
+                        e, rep, st = sbd.davidson(H, k, stream=stream, **kw)
+                        ts.append(rep["t_total_ms"])
+                    t = float(np.median(ts))
+                    row[name] = dict(ms=t, iterations=rep["iterations"], ms_per_iteration=t / rep["iterations"],
+                                     device_iterations=rep["device_iterations"], energy=float(e[0]))
+                out.append(row)
+        del H, X, B
     return out
 
 
@@ -506,6 +583,8 @@ def main():
     ap.add_argument("--no-block", action="store_true")
     ap.add_argument("--no-sqd", action="store_true")
     ap.add_argument("--no-assembled", action="store_true")
+    ap.add_argument("--no-full", action="store_true", help="skip the full-bitstring leg")
+    ap.add_argument("--no-devloop", action="store_true", help="skip the device-driven iteration leg")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a few sigma launches and a calibration copy (counter runs)")
     ap.add_argument("--prec", type=int, default=0, help="precision of --kernel-only (0 FP64, 1 FP32)")
@@ -612,6 +691,22 @@ def main():
         traffic_rate_TBps=None if traffic is None else traffic / (t_stream / 2) / 1e12,
         traffic_over_algorithmic=None if traffic is None else traffic / ((b_alpha + b_beta) / 2),
         stage_share_of_sigma=share)
+    # whole-sigma HBM traffic from the counters (profiles/sigma_traffic.txt, taken in the
+    # handle's default launch configuration): valid when this run's configuration matches
+    tl = {k: v for k, v in traffic_lines(W.name).items() if "<double," in k}
+    t_sigma = sum(s64.values()) * 1e-3
+    whole = None
+    if kname in tl and any(k.startswith("k_ab") for k in tl) and \
+            any(k.startswith("k_transpose") and k.endswith("false>") for k in tl) and \
+            any(k.startswith("k_transpose") and k.endswith("true>") for k in tl) and \
+            sum(1 for k in tl if k.startswith("k_stream")) == 1:
+        per = {k: v * (2 if k.startswith("k_stream") else 1) for k, v in tl.items()}
+        tot = sum(per.values())
+        whole = dict(bytes_per_sigma=tot, sigma_ms=1e3 * t_sigma, TBps=tot / t_sigma / 1e12,
+                     frac_of_hbm_peak=tot / t_sigma / PEAK_HBM, per_kernel_bytes=per,
+                     algorithmic_bytes=rows["sel26_f64"]["compulsory_bytes"],
+                     traffic_over_algorithmic=tot / rows["sel26_f64"]["compulsory_bytes"])
+    roofline["whole_sigma_hbm_counters"] = whole
     log(f"[bench] sigma f64 {rows['sel26_f64']['sigma_ms']:.3f} ms {s64}; "
         f"f32 {rows['sel26_f32']['sigma_ms']:.3f} ms; roofline {roofline['bound']} {roofline['frac']:.3f}")
 
@@ -652,12 +747,25 @@ def main():
         sbd.release_cached_memory()
     if not args.no_sqd:
         extra["sqd_loop"] = sqd_leg(sbd, wl, stream)
-        for name in ("coarse", "fine"):
-            q = extra["sqd_loop"][name]
-            log(f"[bench] sqd loop {name} {q['strings_per_spin']}: cold {q['cold_ms']:.0f} ms "
-                f"{[x['iterations'] for x in q['cold']]} it, warm {q['warm_ms']:.0f} ms "
-                f"{[x['iterations'] for x in q['warm']]} it, energies {[round(x['energy'], 6) for x in q['warm']]}")
+        q = extra["sqd_loop"]
+        for name in ("cold", "warm"):
+            log(f"[bench] sqd loop {name}: {q[name]['ms']:.0f} ms, steps "
+                f"{[(x['determinants'], x['iterations'], round(x['solve_ms'], 1)) for x in q[name]['steps']]}, "
+                f"energies {[round(x, 6) for x in q[name]['energies']]}")
         sbd.release_cached_memory()
+    if not args.no_full:
+        extra["full_bitstring"] = full_leg(sbd, wl, stream)
+        for r in extra["full_bitstring"]:
+            log(f"[bench] full bitstring {r['workload']}: N={r['determinants']} connections={r['connections']} "
+                f"basis {r['basis_ms']:.1f} ms; sigma f64 {r['sigma_ms_f64']:.3f} f32 {r['sigma_ms_f32']:.3f} ms; "
+                f"solve plain {r['plain_fp64']['ms']:.1f} chosen {r['chosen']['ms']:.1f} ms")
+        sbd.release_cached_memory()
+    if not args.no_devloop:
+        extra["device_iterations"] = devloop_leg(sbd, wl, stream)
+        for r in extra["device_iterations"]:
+            log(f"[bench] device-driven iterations N={r['determinants']} k={r['roots']} {r['precision']}: "
+                f"host {r['host_driven']['ms_per_iteration']:.3f} device {r['device_driven']['ms_per_iteration']:.3f} "
+                f"ms/iteration")
     if not args.no_assembled:
         extra["assembled"] = assembled_leg(sbd, wl, stream)
         for r in extra["assembled"]:
