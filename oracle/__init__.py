@@ -39,9 +39,10 @@ def lib():
     """Load the oracle's C library, compiling it with gcc if it is not built."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        path = os.environ.get("ORC_LIB_PATH") or LIB_PATH  # e.g. the sanitized build
+        if path == LIB_PATH and not os.path.exists(LIB_PATH):
             build_oracle()
-        L = ctypes.CDLL(LIB_PATH)
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i64, i32 = ctypes.c_int64, ctypes.c_int
         d = ctypes.c_double

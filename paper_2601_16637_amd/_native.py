@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsbd.so")
+# SBD_LIB_PATH selects another build of the same sources (the sanitized host build)
+LIB_PATH = os.environ.get("SBD_LIB_PATH") or os.path.join(HERE, "libsbd.so")
 
 SBD_OK = 0
 SBD_NOT_CONVERGED = 1

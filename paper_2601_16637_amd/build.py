@@ -64,5 +64,42 @@ def build(verbose: bool = False) -> str:
     return LIB_PATH
 
 
+ASAN_BUILD = os.path.join(HERE, "_build_asan")
+ASAN_LIB_PATH = os.path.join(ASAN_BUILD, "libsbd_asan.so")
+# AddressSanitizer and UBSan on the host code only (the device code is built as usual)
+ASAN_FLAGS = ["-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+              "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-g"]
+
+
+def build_sanitized() -> str:
+    """libsbd with its host code instrumented by AddressSanitizer and UBSan, for
+    CPU-only checks of the host logic (argument validation, handles, the
+    serving queue bookkeeping).  Load it with SBD_LIB_PATH pointing at it and
+    the compiler's ASan runtime preloaded (it records the same source hash)."""
+    os.makedirs(ASAN_BUILD, exist_ok=True)
+    digest = source_hash()
+
+    def one(src):
+        obj = os.path.join(ASAN_BUILD, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC, *FLAGS, *ASAN_FLAGS, f'-DSBD_SOURCE_HASH="{digest}"', "-x", "hip", "-c",
+               os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
+        return obj
+
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        objs = list(ex.map(one, SOURCES))
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Xarch_host", "-fsanitize=address,undefined",
+           "-shared-libsan", *objs, "-o", ASAN_LIB_PATH]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    return ASAN_LIB_PATH
+
+
 if __name__ == "__main__":
-    print(build(verbose=True))
+    if len(sys.argv) > 1 and sys.argv[1] == "--sanitize":
+        print(build_sanitized())
+    else:
+        print(build(verbose=True))
