@@ -164,7 +164,7 @@ struct Solver {
     DevBuf rowsel;           // device int: basis row of the sigma being replayed
     // device-driven iterations: state, partial sums, captured iteration graph
     bool dev = false;
-    DevBuf dls, dlpart;
+    DevBuf dls, dlpart, dlz;
     hipGraphExec_t dl_graph = nullptr;
     int dev_iters = 0;       // iterations run device-driven
     double t_device = 0.0;
@@ -199,6 +199,7 @@ struct Solver {
         if ((use_graph || dev) && e == hipSuccess) e = rowsel.alloc(sizeof(int));
         if (dev && e == hipSuccess) e = dls.alloc(sizeof(DlState));
         if (dev && e == hipSuccess) e = dlpart.alloc(sizeof(double) * (size_t)kDlBlocks * kDlMaxSpace * kDlMaxRoots);
+        if (dev && e == hipSuccess) e = dlz.alloc(sizeof(double) * (size_t)kDlMaxSpace * (kDlMaxSpace + 1));
         if (mixed && e == hipSuccess) e = x32.alloc(sizeof(float) * (size_t)std::max(ms, nvmax) * N);
         if (mixed && e == hipSuccess) e = y32.alloc(sizeof(float) * (size_t)std::max(ms, nvmax) * N);
         if (e != hipSuccess) return hip_fail(e, "sbd_davidson workspace");
@@ -339,10 +340,10 @@ struct Solver {
     int dl_launch(int nv) {
         DlState* d = dls.as<DlState>();
         SBD_HIP(dl_iteration_pre(d, V.as<double>(), W.as<double>(), op->diag, tmp.as<double>(), scr.as<double>(),
-                                 N, k, dlpart.as<double>(), rowsel.as<int>(), st));
+                                 N, k, ms, dlpart.as<double>(), rowsel.as<int>(), dlz.as<double>(), st));
         const int rc = sigma_launches_indexed(k, nv, !mixed);
         if (rc) return rc;
-        SBD_HIP(dl_iteration_post(d, V.as<double>(), W.as<double>(), N, dlpart.as<double>(), st));
+        SBD_HIP(dl_iteration_post(d, V.as<double>(), W.as<double>(), N, k, dlpart.as<double>(), st));
         return SBD_OK;
     }
 
@@ -377,8 +378,17 @@ struct Solver {
         SBD_HIP(launch_clock_read(&d->hist_clock[kDlHistory - 1], st));
         const int nv = k == 1 ? 1 : block_width(k);
         const int it0 = it;
+        // Batch length: the replays queued after the device stops still launch
+        // (as no-ops), so each batch is sized to end near the predicted stop:
+        // from each root's residual decrease per iteration over the last batch,
+        // the iterations until every root meets tol (or, in mixed precision,
+        // until the first root's sigma error bound reaches a fifth of its
+        // residual, which asks for an FP64 refresh); at most `batch`.
+        int nb = std::min(batch, 4);
+        std::vector<double> r_prev(k, -1.0);
+        int it_prev = it;
         while (true) {
-            for (int b = 0; b < batch; ++b) {
+            for (int b = 0; b < nb; ++b) {
                 if (use_graph) {
                     if (!dl_graph) {
                         SBD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -403,6 +413,28 @@ struct Solver {
             SBD_HIP(hipMemcpyAsync(h.get(), d, sizeof(DlState), hipMemcpyDeviceToHost, st));
             SBD_HIP(hipStreamSynchronize(st));
             if (h->stop) break;
+            double n_conv = 0.0, n_err = INFINITY;
+            bool known = h->it > it_prev;
+            for (int q = 0; q < k && known; ++q) {
+                const double r = h->rnorm[q];
+                if (r <= tol) continue;
+                if (!(r_prev[q] > r)) {
+                    known = false;
+                    break;
+                }
+                const double lrate = std::log(r / r_prev[q]) / (double)(h->it - it_prev);
+                n_conv = std::max(n_conv, std::log(tol / r) / lrate);
+                if (mixed && h->ebnd[q] > 0.0) n_err = std::min(n_err, std::log(5.0 * h->ebnd[q] / r) / lrate);
+            }
+            for (int q = 0; q < k; ++q) r_prev[q] = h->rnorm[q];
+            it_prev = h->it;
+            if (known) {
+                const double n = std::max(1.0, std::ceil(std::min(n_conv, n_err)));
+                nb = (int)std::min<double>(n, (double)batch);
+            } else {
+                nb = batch;
+            }
+            nb = std::max(1, std::min(nb, max_iter - h->it));
         }
         // the host's view of the state
         m = h->m;
@@ -725,6 +757,9 @@ int davidson_run(const SigmaOp& op, int k, const sbd_davidson_opts& o, double* e
                                   ebound, since_cert, it, restarts, hist_theta, hist_time, hn, t_start);
             if (rc) return rc;
             hist_n = hn;
+            // the host iteration below repeats the Ritz step and residual of the
+            // device's last iteration (counted there) to act on its stop
+            --it;
         }
         ++it;
         auto tu0 = clk::now();

@@ -359,6 +359,7 @@ struct DlState {
     int restart, m_old, m_cur, since_cert, restarts;
     int active[kDlMaxRoots], row[kDlMaxRoots];
     int hist_n;
+    int zm;                      // size of the previous Ritz step's decomposition kept for a warm start (0: none)
     unsigned cnt[8];             // completion counters of the fused reductions (zero between launches)
     double tol, delta, rho;
     double theta[kDlMaxRoots], rnorm[kDlMaxRoots], tnorm[kDlMaxRoots], ebnd[kDlMaxRoots];
@@ -376,12 +377,15 @@ struct DlState {
 // One device-driven iteration: Ritz pairs, residuals, decisions, restart,
 // Gram-Schmidt of the corrections, the row index of the coming sigma
 // (rows [m_old, m_old + k); row ms when stopped); then, after that sigma,
-// the new entries of T.  part: kDlBlocks x (kDlMaxSpace x kDlMaxRoots) doubles.
+// the new entries of T.  part: kDlBlocks x (kDlMaxSpace x kDlMaxRoots) doubles;
+// zbuf: kDlMaxSpace x (kDlMaxSpace + 1) doubles, the previous Ritz step's
+// eigenvectors and eigenvalues (valid while S->zm > 0).  ms is the subspace
+// limit of the solve (the kernels are specialised for k and ms).
 hipError_t dl_iteration_pre(DlState* S, double* V, double* W, const double* diag, double* tmp, double* scr,
-                            int64_t N, int k, double* part, int* rowsel, hipStream_t st);
+                            int64_t N, int k, int ms, double* part, int* rowsel, double* zbuf, hipStream_t st);
 // *out = the device wall clock (s_memrealtime)
 hipError_t launch_clock_read(unsigned long long* out, hipStream_t st);
-hipError_t dl_iteration_post(DlState* S, const double* V, const double* W, int64_t N, double* part,
+hipError_t dl_iteration_post(DlState* S, const double* V, const double* W, int64_t N, int k, double* part,
                              hipStream_t st);
 
 // The operator a Davidson solve works on: N determinants, the FP64 diagonal
