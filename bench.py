@@ -214,13 +214,19 @@ def _short(name):
     return n.replace(", ", ",").strip()
 
 
-def stats_summary(csv_path, top=25):
-    """Markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv)."""
+def stats_summary(csv_path, top=25, prefix=None):
+    """Markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv),
+    optionally only of the kernels whose short name starts with `prefix`."""
     rows = _csv_rows(csv_path)
+    if prefix:
+        rows = [r for r in rows if _short(_col(r, "Name")).startswith(prefix)]
     rows.sort(key=lambda r: -float(_col(r, "TotalDurationNs")))
     out = ["| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
     for r in rows[:top]:
-        out.append(f"| `{_short(_col(r, 'Name'))}` | {_col(r, 'Calls')} | "
+        name = _short(_col(r, "Name"))
+        if len(name) > 80:
+            name = name[:77] + "..."
+        out.append(f"| `{name}` | {_col(r, 'Calls')} | "
                    f"{float(_col(r, 'TotalDurationNs')) / 1e6:.2f} | "
                    f"{float(_col(r, 'AverageNs')) / 1e3:.1f} | {float(_col(r, 'Percentage')):.1f} |")
     return "\n".join(out)
@@ -241,6 +247,39 @@ def _counter_values(csv_path, counter):
 
 
 SIGMA_KERNELS = ("k_transpose", "k_transpose_v", "k_stream", "k_stream_ks", "k_ab", "k_ab2")
+
+
+def counters_summary(csv_paths):
+    """Markdown table of the L1/L2-side counters of every sigma kernel from
+    rocprofv3 --pmc runs (counter_collection.csv files), each counter averaged
+    over the kernel's dispatches: L1 TLB miss rate, L1->L2 read requests, L2
+    hits, misses and miss rate, mean L1->L2 read latency in cycles."""
+    names = ("TCP_UTCL1_TRANSLATION_MISS_sum", "TCP_UTCL1_REQUEST_sum", "TCP_TCC_READ_REQ_sum",
+             "TCP_TCC_READ_REQ_LATENCY_sum", "TCC_HIT_sum", "TCC_MISS_sum")
+    vals = {n: {} for n in names}
+    for path in csv_paths:
+        for n in names:
+            for k, v in _counter_values(path, n).items():
+                vals[n].setdefault(k, []).extend(v)
+    mean = {n: {k: sum(v) / len(v) for k, v in d.items()} for n, d in vals.items()}
+    kernels = sorted({k for d in mean.values() for k in d if k.split("<")[0] in SIGMA_KERNELS})
+
+    def get(n, k):
+        return mean[n].get(k)
+
+    out = ["| kernel | TLB miss | L1->L2 reads | L2 hit | L2 miss | miss % | latency |",
+           "|---|---|---|---|---|---|---|"]
+    for k in kernels:
+        tm, tr = get(names[0], k), get(names[1], k)
+        rq, lat = get(names[2], k), get(names[3], k)
+        hit, miss = get(names[4], k), get(names[5], k)
+        cell = lambda v, f: "-" if v is None else f.format(v)
+        tlb = f"{100.0 * tm / tr:.3f} %" if tm is not None and tr else "-"
+        mp = f"{100.0 * miss / (hit + miss):.1f}" if hit is not None and miss is not None and hit + miss > 0 else "-"
+        lt = f"{lat / rq:.0f}" if lat is not None and rq else "-"
+        out.append(f"| `{k}` | {tlb} | {cell(rq, '{:.3g}')} | {cell(hit, '{:.3g}')} | {cell(miss, '{:.3g}')} | "
+                   f"{mp} | {lt} |")
+    return "\n".join(out)
 
 
 def traffic_summary(fetch_csv, write_csv, kernel_json, workload):
@@ -590,11 +629,18 @@ def main():
     ap.add_argument("--prec", type=int, default=0, help="precision of --kernel-only (0 FP64, 1 FP32)")
     ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
                     help="print a markdown summary of a rocprofv3 --stats run and exit")
+    ap.add_argument("--stats-prefix", metavar="PREFIX",
+                    help="with --stats-summary: only kernels whose name starts with PREFIX")
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_ONLY_LOG"),
                     help="print calibrated HBM bytes per launch of the dominant kernel and exit")
+    ap.add_argument("--counters-summary", nargs="+", metavar="COUNTER_CSV",
+                    help="print the L1/L2-side counters of the sigma kernels from rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.counters_summary:
+        print(counters_summary(args.counters_summary))
+        return
     if args.stats_summary:
-        print(stats_summary(args.stats_summary))
+        print(stats_summary(args.stats_summary, prefix=args.stats_prefix))
         return
     if args.traffic_summary:
         print(traffic_summary(*args.traffic_summary, workload=args.workload))
