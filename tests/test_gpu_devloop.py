@@ -85,3 +85,23 @@ def test_device_iterations_fall_back_when_unsupported():
     W, ham = system()
     e, rep, st = sbd.davidson(ham, 2, tol_residual=1e-7, device_iterations=4, block_sigma=0)
     assert st == 0 and rep["device_iterations"] == 0
+
+
+@pytest.mark.parametrize("nroots,prec", [(1, 0), (2, 0), (1, 1)])
+def test_device_iterations_count_like_host_driven(nroots, prec):
+    """A device-driven solve takes the host-driven solve's path: the same
+    energies (to the tolerance) in about the same number of iterations (the
+    warm-started Ritz step rounds differently), each counted once across the
+    hand-overs between device batches and host iterations."""
+    W, ham = system(nstr=250)
+    res = {}
+    for dev in (0, 8):
+        e, rep, st = sbd.davidson(ham, nroots, tol_residual=1e-8, sigma_prec=prec, max_space=16,
+                                  device_iterations=dev, use_graph=1)
+        assert st == 0
+        res[dev] = (e[:nroots], rep)
+    (eh, rh), (ed, rd) = res[0], res[8]
+    assert rd["device_iterations"] > 0 and rh["device_iterations"] == 0
+    assert np.abs(eh - ed).max() <= 1e-9
+    assert abs(rd["iterations"] - rh["iterations"]) <= 2, (rh["iterations"], rd["iterations"])
+    assert rd["device_iterations"] <= rd["iterations"]
