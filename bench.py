@@ -232,6 +232,36 @@ def stats_summary(csv_path, top=25, prefix=None):
     return "\n".join(out)
 
 
+def launch_gaps(trace_csv):
+    """Idle time between the five launches of each FP64 single-vector sigma
+    (transpose, two row streams, alpha-beta, transpose-add) in a rocprofv3
+    --kernel-trace run: per sigma, the sum over the four launch boundaries of
+    (start of a launch - end of the one before it)."""
+    rows = _csv_rows(trace_csv)
+    rows.sort(key=lambda r: int(_col(r, "Start_Timestamp")))
+    names = [_short(_col(r, "Kernel_Name")) for r in rows]
+    stages = ("k_transpose<double,1,false>", "k_stream", "k_stream", "k_ab", "k_transpose<double,1,true>")
+    seqs = {}
+    for i in range(len(rows) - 4):
+        if not all(names[i + j].startswith(stages[j]) for j in range(5)):
+            continue
+        g = sum(int(_col(rows[i + j + 1], "Start_Timestamp")) - int(_col(rows[i + j], "End_Timestamp"))
+                for j in range(4))
+        span = int(_col(rows[i + 4], "End_Timestamp")) - int(_col(rows[i], "Start_Timestamp"))
+        seqs.setdefault(tuple(names[i:i + 5]), []).append((g / 1e3, span / 1e3))
+    if not seqs:
+        return "no FP64 single-vector sigma sequence in the trace"
+    # the launch configuration the run used most (the benchmark's steps; the
+    # autotuner's candidates and the per-stage timing, which records events
+    # between the stages, appear less often)
+    key, v = max(seqs.items(), key=lambda kv: len(kv[1]))
+    gaps = [a for a, _ in v]
+    spans = [b for _, b in v]
+    return (f"{len(v)} sigma sequences of {' -> '.join(key)}: launch gaps per sigma median "
+            f"{float(np.median(gaps)):.1f} us, max {max(gaps):.1f} us; sigma span median "
+            f"{float(np.median(spans)):.1f} us")
+
+
 def _counter_values(csv_path, counter):
     """Counter value of every dispatch, per short kernel name."""
     acc = {}
@@ -633,9 +663,14 @@ def main():
                     help="with --stats-summary: only kernels whose name starts with PREFIX")
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_ONLY_LOG"),
                     help="print calibrated HBM bytes per launch of the dominant kernel and exit")
+    ap.add_argument("--launch-gaps", metavar="KERNEL_TRACE_CSV",
+                    help="print the idle time between the launches of each FP64 sigma in a kernel trace and exit")
     ap.add_argument("--counters-summary", nargs="+", metavar="COUNTER_CSV",
                     help="print the L1/L2-side counters of the sigma kernels from rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.launch_gaps:
+        print(launch_gaps(args.launch_gaps))
+        return
     if args.counters_summary:
         print(counters_summary(args.counters_summary))
         return
