@@ -101,9 +101,11 @@ def kernel_only(sbd, W, stream, prec):
     z.copy_(x)
     torch.cuda.synchronize()
     tune = H.get_tune(prec)
+    c = table_counts(B, X)
     print(json.dumps(dict(kernel_only=True, workload=W.name, ndet=W.ndet, precision=prec,
                           copy_bytes_read=w * W.ndet, copy_bytes_written=w * W.ndet,
-                          tune=tune, stream_kernel=stream_kernel(tune, prec))))
+                          tune=tune, stream_kernel=stream_kernel(tune, prec), table_entries=c,
+                          alpha_beta_fma=c["p1a"] * c["p1b"])))
 
 
 def cpu_baseline(W, target_s=15.0):
@@ -262,6 +264,15 @@ def launch_gaps(trace_csv):
             f"{float(np.median(spans)):.1f} us")
 
 
+def _counter_values_all(csv_paths, counter):
+    """_counter_values over several runs, dispatch values pooled per kernel."""
+    acc = {}
+    for path in csv_paths:
+        for k, v in _counter_values(path, counter).items():
+            acc.setdefault(k, []).extend(v)
+    return acc
+
+
 def _counter_values(csv_path, counter):
     """Counter value of every dispatch, per short kernel name."""
     acc = {}
@@ -283,7 +294,9 @@ def counters_summary(csv_paths):
     """Markdown table of the L1/L2-side counters of every sigma kernel from
     rocprofv3 --pmc runs (counter_collection.csv files), each counter averaged
     over the kernel's dispatches: L1 TLB miss rate, L1->L2 read requests, L2
-    hits, misses and miss rate, mean L1->L2 read latency in cycles."""
+    hits, misses and miss rate, mean L1->L2 read latency in cycles, and the
+    wavefront-level vector and scalar instruction counts and wavefronts where
+    a run collected them."""
     names = ("TCP_UTCL1_TRANSLATION_MISS_sum", "TCP_UTCL1_REQUEST_sum", "TCP_TCC_READ_REQ_sum",
              "TCP_TCC_READ_REQ_LATENCY_sum", "TCC_HIT_sum", "TCC_MISS_sum")
     vals = {n: {} for n in names}
@@ -297,8 +310,10 @@ def counters_summary(csv_paths):
     def get(n, k):
         return mean[n].get(k)
 
-    out = ["| kernel | TLB miss | L1->L2 reads | L2 hit | L2 miss | miss % | latency |",
-           "|---|---|---|---|---|---|---|"]
+    sq = {n: {k: sum(v) / len(v) for k, v in _counter_values_all(csv_paths, n).items()}
+          for n in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_WAVES")}
+    out = ["| kernel | TLB miss | L1->L2 reads | L2 hit | L2 miss | miss % | latency | VALU insts | SALU insts | waves |",
+           "|---|---|---|---|---|---|---|---|---|---|"]
     for k in kernels:
         tm, tr = get(names[0], k), get(names[1], k)
         rq, lat = get(names[2], k), get(names[3], k)
@@ -308,7 +323,8 @@ def counters_summary(csv_paths):
         mp = f"{100.0 * miss / (hit + miss):.1f}" if hit is not None and miss is not None and hit + miss > 0 else "-"
         lt = f"{lat / rq:.0f}" if lat is not None and rq else "-"
         out.append(f"| `{k}` | {tlb} | {cell(rq, '{:.3g}')} | {cell(hit, '{:.3g}')} | {cell(miss, '{:.3g}')} | "
-                   f"{mp} | {lt} |")
+                   f"{mp} | {lt} | {cell(sq['SQ_INSTS_VALU'].get(k), '{:.3g}')} | "
+                   f"{cell(sq['SQ_INSTS_SALU'].get(k), '{:.3g}')} | {cell(sq['SQ_WAVES'].get(k), '{:.3g}')} |")
     return "\n".join(out)
 
 
