@@ -464,6 +464,32 @@ def full_leg(sbd, wl, stream):
     return out
 
 
+def projection_leg(sbd, N, stream, rows=(4, 10, 20), reps=5):
+    """HBM rate of the Davidson update's tall-skinny projection pass
+    (sbd_gram: out = A^T x over ma rows of N doubles and one vector, the pass
+    behind the Gram-Schmidt and Rayleigh-Ritz projections) at the benchmark's
+    vector length: algorithmic bytes (ma + 1) 8 N per call over the median
+    wall time of `reps` calls (each synchronises)."""
+    import torch
+    A = torch.randn(max(rows), N, device="cuda", dtype=torch.float64)
+    x = torch.randn(N, device="cuda", dtype=torch.float64)
+    out = []
+    for ma in rows:
+        sbd.gram(A, ma, x, 1, N, stream=stream)
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sbd.gram(A, ma, x, 1, N, stream=stream)
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        b = (ma + 1) * 8.0 * N
+        out.append(dict(rows=ma, determinants=N, ms=1e3 * t, algorithmic_bytes=b, TBps=b / t / 1e12,
+                        hbm_frac=b / t / PEAK_HBM))
+    del A, x
+    return out
+
+
 def devloop_leg(sbd, wl, stream, sizes=(100, 300)):
     """Device-driven iterations (opts.device_iterations = 8, whole iterations
     replayed from one captured graph, one host synchronisation per batch)
@@ -670,6 +696,7 @@ def main():
     ap.add_argument("--no-assembled", action="store_true")
     ap.add_argument("--no-full", action="store_true", help="skip the full-bitstring leg")
     ap.add_argument("--no-devloop", action="store_true", help="skip the device-driven iteration leg")
+    ap.add_argument("--no-projection", action="store_true", help="skip the projection-pass rate leg")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a few sigma launches and a calibration copy (counter runs)")
     ap.add_argument("--prec", type=int, default=0, help="precision of --kernel-only (0 FP64, 1 FP32)")
@@ -856,6 +883,12 @@ def main():
             log(f"[bench] full bitstring {r['workload']}: N={r['determinants']} connections={r['connections']} "
                 f"basis {r['basis_ms']:.1f} ms; sigma f64 {r['sigma_ms_f64']:.3f} f32 {r['sigma_ms_f32']:.3f} ms; "
                 f"solve plain {r['plain_fp64']['ms']:.1f} chosen {r['chosen']['ms']:.1f} ms")
+        sbd.release_cached_memory()
+    if not args.no_projection:
+        extra["projection_pass"] = projection_leg(sbd, N, stream)
+        for r in extra["projection_pass"]:
+            log(f"[bench] projection pass {r['rows']} rows x 1 vector, N={N}: {r['ms']:.3f} ms, "
+                f"{r['TBps']:.2f} TB/s ({r['hbm_frac']:.2f} of HBM peak)")
         sbd.release_cached_memory()
     if not args.no_devloop:
         extra["device_iterations"] = devloop_leg(sbd, wl, stream)
