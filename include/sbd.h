@@ -313,8 +313,10 @@ typedef struct {
                               a captured HIP graph that serves every subspace size.  When the
                               device stops (convergence, an FP64 refresh of a mixed-precision
                               solve, stagnation) one host iteration handles it.  Needs
-                              nroots <= 8, max_space >= 2 nroots + 1 and, for several roots,
-                              block_sigma; otherwise the host decides every iteration         */
+                              N <= 2^21 determinants (larger bases stream gigabytes per
+                              iteration, where the host's decisions cost nothing), nroots <= 8,
+                              max_space >= 2 nroots + 1 and, for several roots, block_sigma;
+                              otherwise the host decides every iteration                      */
 } sbd_davidson_opts;
 
 typedef struct {

@@ -648,8 +648,8 @@ int davidson_run(const SigmaOp& op, int k, const sbd_davidson_opts& o, double* e
     // block solves gather all new vectors of an iteration in one interleaved sigma
     S.nvmax = (k < 2 || !o.block_sigma) ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));
     S.use_graph = o.use_graph != 0;
-    S.dev = o.device_iterations > 0 && k <= kDlMaxRoots && ms >= 2 * k + 1 && ms <= kDlMaxSpace &&
-            S.keep <= kDlMaxKeep && (k == 1 || S.nvmax >= k);
+    S.dev = o.device_iterations > 0 && N <= kDlMaxN && k <= kDlMaxRoots && ms >= 2 * k + 1 &&
+            ms <= kDlMaxSpace && S.keep <= kDlMaxKeep && (k == 1 || S.nvmax >= k);
     const auto tw = clk::now();
     int rc = S.alloc();
     if (rc) return rc;

@@ -351,6 +351,10 @@ constexpr int kDlMaxRoots = 8;
 constexpr int kDlMaxKeep = 16;    // vectors kept by a thick restart
 constexpr int kDlBlocks = 256;    // grid of the sweeps (partial sums per block)
 constexpr int kDlHistory = 512;
+// Largest basis the device-driven iterations take: their sweeps run on at most
+// kDlBlocks workgroups (few waves per CU), which pays where an iteration is
+// bound by launches and host round trips, not where it streams gigabytes.
+constexpr int64_t kDlMaxN = (int64_t)1 << 21;
 enum { kDlRunning = 0, kDlConverged = 1, kDlRefresh = 2, kDlMaxIter = 3, kDlStagnation = 4, kDlNumeric = 5 };
 struct DlState {
     int m, k, ms, keep;          // subspace size, roots, maximum size, restart size

@@ -218,9 +218,16 @@ extern "C" int sbd_serve_estimate(const sbd_request* q, size_t* bytes) {
     const double keep = std::max<double>(k, std::min<double>(2 * k, ms - k));
     const bool mixed = o.sigma_prec == SBD_FP32;
     const double nvmax = (k < 2 || !o.block_sigma) ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));  // block width
-    double total = 2 * ms * N * 8 + std::max<double>(k, keep) * N * 8 + keep * N * 8 +
-                   2 * N * nvmax * 8 + ((nvmax > 1 || o.use_graph) ? 2 * nvmax * N * 8 : 0.0) +
+    // device-driven iterations (when the solve can take them): spare rows of V and W, a
+    // second collapse scratch, FP64 staging, the device state and its partial sums
+    const bool dev = o.device_iterations > 0 && k <= kDlMaxRoots && N <= (double)kDlMaxN;
+    const bool stage64 = nvmax > 1 || o.use_graph || dev;
+    double total = 2 * (ms + (dev ? kDlMaxRoots : 0)) * N * 8 + std::max<double>(k, keep) * N * 8 +
+                   keep * N * 8 * (dev ? 2 : 1) + 2 * N * nvmax * 8 + (stage64 ? 2 * nvmax * N * 8 : 0.0) +
                    (mixed ? 2 * std::max(ms, nvmax) * N * 4 : 0.0) + 8.0 * kPassRows * kRedBlocks +
+                   (dev ? sizeof(DlState) + 8.0 * kDlBlocks * kDlMaxSpace * kDlMaxRoots +
+                              8.0 * kDlMaxSpace * (kDlMaxSpace + 1)
+                        : 0.0) +
                    65536.0;
     // Hamiltonian: integrals, diagonal, spectator tables and per-string diagonal parts
     const double np = norb * (norb + 1) / 2.0;

@@ -81,9 +81,14 @@ def test_device_iterations_fci8_dense_and_full_bitstring():
 
 
 def test_device_iterations_fall_back_when_unsupported():
-    """Several roots without block sigma keep the host-driven iteration."""
+    """Several roots without block sigma, and bases above 2^21 determinants,
+    keep the host-driven iteration."""
     W, ham = system()
     e, rep, st = sbd.davidson(ham, 2, tol_residual=1e-7, device_iterations=4, block_sigma=0)
+    assert st == 0 and rep["device_iterations"] == 0
+    W, ham = system(nstr=1500)
+    assert W.ndet > 1 << 21
+    e, rep, st = sbd.davidson(ham, 1, tol_residual=1e-6, device_iterations=4)
     assert st == 0 and rep["device_iterations"] == 0
 
 

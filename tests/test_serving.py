@@ -40,6 +40,8 @@ def test_estimate_grows_with_size_and_precision():
     # the estimate covers the Davidson vectors at least
     N = W.alpha.size * W.beta.size
     assert estimate(W, max_space=20) >= 2 * 20 * N * 8
+    # device-driven iterations add spare rows of V and W (8 each) and a second collapse scratch
+    assert estimate(W, device_iterations=8) >= estimate(W) + 2 * 8 * N * 8
 
 
 def test_estimate_rejects_bad_requests():
@@ -128,6 +130,29 @@ def test_serve_admission_respects_budget():
         assert live <= budget
     # and the budget did force some requests to wait for memory
     assert max(r["queue_ms"] for r in res) > 0.0
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("graph", [0, 1])
+def test_serve_device_driven_iterations(graph):
+    """Requests with device-driven iterations (and, optionally, the iteration
+    replayed from a graph) fit the regions their estimate reserves and reach
+    the host-driven requests' energies, in both precisions."""
+    reqs = small_stream(8, seed=7400)
+    precs = [sbd.FP64 if i % 2 == 0 else sbd.FP32 for i in range(len(reqs))]
+    s = sbd.Server(16 << 30, 4)
+    host = [submit(s, W, sigma_prec=p, tol_residual=1e-7) for W, p in zip(reqs, precs)]
+    dev = [submit(s, W, sigma_prec=p, tol_residual=1e-7, device_iterations=8, use_graph=graph)
+           for W, p in zip(reqs, precs)]
+    rh = [s.wait(t) for t in host]
+    rd = [s.wait(t) for t in dev]
+    s.close()
+    for W, a, b in zip(reqs, rh, rd):
+        assert a["status"] == 0 and b["status"] == 0, (a["message"], b["message"])
+        assert b["report"]["device_iterations"] > 0
+        assert 0 < b["peak_bytes"] <= b["region_bytes"]
+        k = W.nroots
+        assert np.abs(a["energies"][:k] - b["energies"][:k]).max() <= 1e-9
 
 
 @pytest.mark.gpu
