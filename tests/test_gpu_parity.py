@@ -842,3 +842,79 @@ def test_assembled_sigma_timed_reports_the_product():
     assert rel(yd.cpu().numpy(), S.sigma(x)) <= 1e-12
     assert st["alpha_stream"] > 0.0
     assert all(v <= 0.05 for k, v in st.items() if k != "alpha_stream"), st
+
+
+# ------------------------------------------------------------------ random shapes
+def _random_system(seed):
+    """A small selected basis of random shape: norb 2-13, any electron counts
+    (empty and full shells included), string sets from one string to all of
+    them, ragged sizes."""
+    rng = np.random.default_rng(seed)
+    norb = int(rng.integers(2, 14))
+    na, nb = int(rng.integers(0, norb + 1)), int(rng.integers(0, norb + 1))
+    ca, cb = math.comb(norb, na), math.comb(norb, nb)
+    kind = seed % 3  # 0: one string on a side, 1: all strings, 2: a random subset
+    sa = 1 if kind == 0 else (ca if kind == 1 else int(rng.integers(1, ca + 1)))
+    sb = int(rng.integers(1, cb + 1)) if kind != 1 else cb
+    while sa * sb > 60000:  # keep the oracle's sigma quick
+        sa, sb = max(1, sa // 2), max(1, sb // 2)
+    A = wl.sample_strings(norb, na, sa, seed + 1)
+    B = wl.sample_strings(norb, nb, sb, seed + 2)
+    h, eri, ec = wl.make_integrals(norb, seed + 3)
+    return norb, na, nb, A, B, h, eri, ec
+
+
+@pytest.mark.parametrize("seed", range(9000, 9036))
+def test_sigma_random_shapes(seed):
+    """FP64 sigma elementwise within 1e-12 of the oracle's (relative to the
+    row's magnitude sum), and FP32 sigma within its componentwise rounding
+    bound, on random small bases, in the default launch configuration and in
+    two others (two rows per stream wavefront with a small alpha-beta LDS
+    budget; ket-split loads with 8-byte lanes)."""
+    norb, na, nb, A, B, h, eri, ec = _random_system(seed)
+    _, _, ham = gpu_system(norb, na, nb, A, B, h, eri, ec)
+    S = oracle.OracleSystem(norb, A, B, h, eri, ec)
+    N = S.N
+    idx = np.arange(N)
+    x = wl.random_vector(N, seed + 4)[0]
+    ref = S.sigma(x)
+    mag = S.sigma_abs_at(x, idx)
+    z = S.row_terms(idx)
+    shift = float(S.diag().min())
+    x32 = x.astype(np.float32).astype(np.float64)
+    ref32 = S.sigma(x32) - shift * x32
+    # the FP32 rounding bound, plus the FP64 rounding of the two sides' diagonals
+    # (summed in different orders), which H - shift exposes where H_II = shift
+    bound32 = 2 * (z + 2) * 2.0 ** -24 * S.sigma_abs_at(x32, idx, shift) + \
+        1e-13 * np.abs(S.diag()) * np.abs(x32)
+    for cfg in (None, (2, 49152, 1, 1), (1, 147456, 0, 4)):
+        if cfg is not None:
+            ham.set_tune(0, *cfg)
+            ham.set_tune(1, *cfg)
+        y = gpu_sigma(ham, x)
+        assert np.all(np.abs(y - ref) <= 1e-12 * (mag + 1e-300)), (cfg, np.max(np.abs(y - ref) / mag))
+        y32 = gpu_sigma(ham, x32, prec=1, shift=shift)
+        assert np.all(np.abs(y32 - ref32) <= bound32), (cfg, np.max(np.abs(y32 - ref32) / bound32))
+
+
+@pytest.mark.parametrize("seed", range(9100, 9118))
+def test_davidson_random_shapes_vs_dense(seed):
+    """The lowest eigenvalues of random small bases (N from 1 to 2,000) in the
+    plain form (1e-8 Ha), the chosen form (1e-6 Ha) and with device-driven
+    iterations, against the dense eigenvalues of the oracle's H."""
+    norb, na, nb, A, B, h, eri, ec = _random_system(seed)
+    S = oracle.OracleSystem(norb, A, B, h, eri, ec)
+    if S.N > 2000:
+        A, B = A[: max(1, 2000 // max(B.size, 1))], B
+        if A.size * B.size > 2000:
+            B = B[: max(1, 2000 // A.size)]
+        S = oracle.OracleSystem(norb, A, B, h, eri, ec)
+    _, _, ham = gpu_system(norb, na, nb, A, B, h, eri, ec)
+    ev = np.linalg.eigvalsh(S.dense_h())
+    k = min(2, S.N)
+    for kw, tol in ((dict(sigma_prec=0), 1e-8), (dict(sigma_prec=1), 1e-6),
+                    (dict(sigma_prec=0, device_iterations=4, use_graph=1), 1e-8)):
+        e, rep, st = sbd.davidson(ham, k, tol_residual=1e-8 if kw["sigma_prec"] == 0 else 1e-7,
+                                  max_space=12, **kw)
+        assert st == 0, (kw, st)
+        assert np.abs(e[:k] - ev[:k]).max() <= tol, (kw, e[:k], ev[:k])
