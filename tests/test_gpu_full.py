@@ -258,3 +258,33 @@ def test_full_size_sampled_rows(name):
     y = run_sigma(H, x)
     yo = S.sigma_rows(x, idx)
     assert np.abs(y[idx] - yo).max() <= 1e-12 * np.abs(yo).max()
+
+
+@pytest.mark.parametrize("seed", range(9200, 9224))
+def test_full_random_shapes(seed):
+    """Random small determinant lists (norb 2-12, any electron counts, from one
+    determinant up to a few thousand, duplicates given): bit-exact sorted lists
+    and connections, FP64 sigma elementwise within 1e-12 of the oracle's
+    (relative to the row's magnitude sum) and the lowest energy against the
+    oracle's dense H."""
+    rng = np.random.default_rng(seed)
+    norb = int(rng.integers(2, 13))
+    na, nb = int(rng.integers(0, norb + 1)), int(rng.integers(0, norb + 1))
+    total = len(wl.all_strings(norb, na)) * len(wl.all_strings(norb, nb))
+    count = int(rng.integers(1, min(total, 3000) + 1))
+    dets = random_dets(norb, na, nb, count, seed)
+    h, eri, ec = wl.make_integrals(norb, seed + 1)
+    given = np.concatenate([dets, dets[: max(1, count // 5)]])[rng.permutation(count + max(1, count // 5))]
+    B, H = gpu_full(norb, na, nb, given, h, eri, ec)
+    S = oracle.FullOracleSystem(norb, dets, h, eri, ec)
+    d, rp, J, deg = B.export()
+    assert np.array_equal(d, S.dets) and np.array_equal(rp, S.row_ptr)
+    assert np.array_equal(J, S.J) and np.array_equal(deg, S.deg)
+    Hd = S.dense_h()
+    x = wl.random_vector(S.N, seed + 2)[0]
+    y = run_sigma(H, x)
+    mag = np.abs(Hd) @ np.abs(x)
+    assert np.all(np.abs(y - Hd @ x) <= 1e-12 * mag)
+    e, rep, st = sbd.full_davidson(H, 1, tol_residual=1e-8)
+    assert st == 0
+    assert abs(e[0] - np.linalg.eigvalsh(Hd)[0]) <= 1e-8
