@@ -422,9 +422,36 @@ def full_leg(sbd, wl, stream):
     """Full-bitstring path (Sec. II-F, III-F) on determinant lists that are not
     Cartesian products (full16: 1e6, full26: 4e6 determinants drawn from the
     sel16 / sel26 string products): basis build (sort, groups, connections),
-    Hamiltonian, sigma per precision, and plain / chosen-form solves."""
+    Hamiltonian, sigma per precision, and plain / chosen-form solves; then the
+    same with every connection's element kept (sbd_full_assemble, Sec. II-A)."""
     import torch
     out = []
+
+    def sigma_ms(B, H, prec):
+        dt = torch.float64 if prec == sbd.FP64 else torch.float32
+        x = torch.randn(B.N, device="cuda", dtype=dt)
+        y = torch.empty_like(x)
+        sbd.full_sigma(H, x, y, prec=prec, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            sbd.full_sigma(H, x, y, prec=prec, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 10
+
+    def solves(H):
+        res = {}
+        for form, prec in (("plain_fp64", sbd.FP64), ("chosen", sbd.FP32)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, rep, st = sbd.full_davidson(H, 1, stream=stream, tol_residual=1e-6, sigma_prec=prec,
+                                           max_space=MAX_SPACE)
+            torch.cuda.synchronize()
+            res[form] = dict(ms=1e3 * (time.perf_counter() - t0), iterations=rep["iterations"],
+                             sigma_calls=rep["sigma_calls"], energy=float(e[0]), status=int(st))
+        return res
+
     for name in ("full16", "full26"):
         F = wl.make_full_config(name)
         torch.cuda.synchronize()
@@ -437,28 +464,27 @@ def full_leg(sbd, wl, stream):
         row = dict(workload=name, determinants=B.N, connections=B.nconn, alpha_strings=B.nalpha,
                    basis_ms=1e3 * (t1 - t0), hamiltonian_ms=1e3 * (t2 - t1))
         for prec, tag in ((sbd.FP64, "f64"), (sbd.FP32, "f32")):
-            dt = torch.float64 if prec == sbd.FP64 else torch.float32
-            x = torch.randn(B.N, device="cuda", dtype=dt)
-            y = torch.empty_like(x)
-            sbd.full_sigma(H, x, y, prec=prec, stream=stream)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(10):
-                sbd.full_sigma(H, x, y, prec=prec, stream=stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / 10
+            ms = sigma_ms(B, H, prec)
             row[f"sigma_ms_{tag}"] = ms
             row[f"sigma_det_per_s_{tag}"] = B.N / (ms * 1e-3)
             row[f"connections_per_s_{tag}"] = (B.N + B.nconn) / (ms * 1e-3)
-        for form, prec in (("plain_fp64", sbd.FP64), ("chosen", sbd.FP32)):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            e, rep, st = sbd.full_davidson(H, 1, stream=stream, tol_residual=1e-6, sigma_prec=prec,
-                                           max_space=MAX_SPACE)
-            torch.cuda.synchronize()
-            row[form] = dict(ms=1e3 * (time.perf_counter() - t0), iterations=rep["iterations"],
-                             sigma_calls=rep["sigma_calls"], energy=float(e[0]), status=int(st))
+        row.update(solves(H))
+        # explicit realization: the elements kept (12 bytes per connection for both precisions)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.assemble(3, stream=stream)
+        asm = dict(assemble_ms=1e3 * (time.perf_counter() - t0), element_bytes=12 * B.nconn)
+        for prec, tag in ((sbd.FP64, "f64"), (sbd.FP32, "f32")):
+            ms = sigma_ms(B, H, prec)
+            w = 8 if prec == sbd.FP64 else 4
+            # algorithmic bytes: elements and ket indices once, x and y once, the diagonal once
+            b = B.nconn * (w + 4) + 8 * (B.N + 1) + 2 * w * B.N + 8 * B.N
+            asm[f"sigma_ms_{tag}"] = ms
+            asm[f"hbm_TBps_{tag}"] = b / (ms * 1e-3) / 1e12
+        asm.update(solves(H))
+        asm["energy_diff_vs_matrix_free"] = abs(asm["plain_fp64"]["energy"] - row["plain_fp64"]["energy"])
+        row["assembled"] = asm
+        H.release_assembled()
         out.append(row)
         del H, B
     return out
@@ -883,6 +909,10 @@ def main():
             log(f"[bench] full bitstring {r['workload']}: N={r['determinants']} connections={r['connections']} "
                 f"basis {r['basis_ms']:.1f} ms; sigma f64 {r['sigma_ms_f64']:.3f} f32 {r['sigma_ms_f32']:.3f} ms; "
                 f"solve plain {r['plain_fp64']['ms']:.1f} chosen {r['chosen']['ms']:.1f} ms")
+            a = r["assembled"]
+            log(f"[bench] full bitstring {r['workload']} assembled: {a['assemble_ms']:.1f} ms; sigma f64 "
+                f"{a['sigma_ms_f64']:.3f} ({a['hbm_TBps_f64']:.2f} TB/s) f32 {a['sigma_ms_f32']:.3f} ms; solve plain "
+                f"{a['plain_fp64']['ms']:.1f} chosen {a['chosen']['ms']:.1f} ms")
         sbd.release_cached_memory()
     if not args.no_projection:
         extra["projection_pass"] = projection_leg(sbd, N, stream)

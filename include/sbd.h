@@ -472,6 +472,27 @@ int sbd_full_sigma(const sbd_fbasis* b, const sbd_fham* h, int nvec, int prec, d
 int sbd_full_davidson(const sbd_fbasis* b, const sbd_fham* h, int nroots, const sbd_davidson_opts* opts,
                       double* energies, double* vectors, sbd_davidson_report* report, void* stream);
 
+/*
+ * Explicit realization over a determinant list (Sec. II-A for the list of
+ * Sec. II-F): the element of every stored connection of b, formed once by the
+ * evaluation sbd_full_sigma uses and kept with h in the connection order
+ * (FP64 and, when requested, its FP32 rounding: 8 and 4 bytes per connection;
+ * the diagonal stays the cached FP64 H_II).  precisions: 1 = FP64, 2 = FP32,
+ * 3 = both.  max_bytes (0 = no limit) bounds the bytes of the elements; a
+ * larger need fails with SBD_ERR_NOMEM before any allocation.  While a
+ * precision is assembled, sbd_full_sigma and sbd_full_davidson in that
+ * precision read the stored elements instead of evaluating them, summing in
+ * the same order, so the product is bitwise the matrix-free one.
+ * sbd_full_release_assembled returns to the matrix-free product.  Synchronises
+ * the stream; a failure leaves h unchanged.  Not to be called while other
+ * calls use h.  Errors: SBD_ERR_ARG (null, precisions outside 1..3),
+ * SBD_ERR_STATE (h built on another list), SBD_ERR_NOMEM, SBD_ERR_HIP.
+ */
+int sbd_full_assemble(sbd_fham* h, const sbd_fbasis* b, int precisions, size_t max_bytes, void* stream);
+int sbd_full_release_assembled(sbd_fham* h);
+/* The assembled precisions of h (bit 0 FP64, bit 1 FP32; 0 = matrix-free). */
+int sbd_full_assembled(const sbd_fham* h, int* precisions);
+
 /* ------------------------------------------------------------------ serving
  * Continuous batching of whole solves (one SQD iteration each: the classical
  * diagonalisation that follows every sampling round, Sec. I and Sec. II).

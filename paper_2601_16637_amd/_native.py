@@ -35,7 +35,8 @@ EXPORTED = ["sbd_last_error", "sbd_version", "sbd_source_hash", "sbd_release_cac
             "sbd_serve_submit", "sbd_serve_wait", "sbd_serve_destroy",
             "sbd_full_build_basis", "sbd_full_basis_sizes", "sbd_full_basis_export", "sbd_free_full_basis",
             "sbd_full_set_hamiltonian", "sbd_full_ham_diag", "sbd_free_full_ham", "sbd_full_sigma",
-            "sbd_full_davidson", "sbd_sqd_default_opts", "sbd_sqd_run"]
+            "sbd_full_davidson", "sbd_full_assemble", "sbd_full_release_assembled", "sbd_full_assembled",
+            "sbd_sqd_default_opts", "sbd_sqd_run"]
 
 
 class SBDError(RuntimeError):
@@ -179,6 +180,9 @@ def load():
     L.sbd_full_sigma.argtypes = [P, P, i32, i32, d, P, P, i32, P]
     L.sbd_full_davidson.argtypes = [P, P, i32, ctypes.POINTER(DavidsonOpts), P, P,
                                     ctypes.POINTER(DavidsonReport), P]
+    L.sbd_full_assemble.argtypes = [P, P, i32, ctypes.c_size_t, P]
+    L.sbd_full_release_assembled.argtypes = [P]
+    L.sbd_full_assembled.argtypes = [P, ctypes.POINTER(i32)]
     L.sbd_sqd_default_opts.argtypes = [ctypes.POINTER(SqdOpts)]
     L.sbd_sqd_default_opts.restype = None
     L.sbd_sqd_run.argtypes = [i32, i32, i32, P, P, d, P, i64, P, i32, i32, ctypes.POINTER(SqdOpts), P,
@@ -485,6 +489,20 @@ class FullHamiltonian:
 
     def diag_into(self, out, stream=None):
         check(load().sbd_full_ham_diag(self._h, _dptr(out), _stream(stream)))
+
+    def assemble(self, precisions: int = 3, max_bytes: int = 0, stream=None):
+        """Keep every connection's element (sbd_full_assemble); precisions: 1 FP64, 2 FP32, 3 both."""
+        check(load().sbd_full_assemble(self._h, self.basis._h, int(precisions), int(max_bytes),
+                                       _stream(stream)))
+
+    def release_assembled(self):
+        check(load().sbd_full_release_assembled(self._h))
+
+    def assembled(self) -> int:
+        """Assembled precision bits (sbd_full_assembled): 1 FP64, 2 FP32, 0 none."""
+        pr = ctypes.c_int()
+        check(load().sbd_full_assembled(self._h, ctypes.byref(pr)))
+        return pr.value
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

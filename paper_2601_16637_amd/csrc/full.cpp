@@ -33,6 +33,8 @@ struct sbd_fham {
     int64_t n = 0;
     double e_core = 0.0;
     DevBuf h64, eri64, jt, kt, jd, kd, diag;
+    DevBuf v64, v32;   // assembled elements per connection (explicit realization)
+    int asm_prec = 0;  // bit 0: FP64 assembled, bit 1: FP32
 };
 
 namespace {
@@ -66,6 +68,8 @@ int full_sigma_launch(const sbd_fbasis* B, const sbd_fham* H, int nvec, int prec
     A.kt = H->kt.as<double>();
     A.diag = H->diag.as<double>();
     A.shift = shift;
+    if (H->asm_prec & 1) A.v64 = H->v64.as<double>();
+    if (H->asm_prec & 2) A.v32 = H->v32.as<float>();
     hipError_t e = prec == SBD_FP64
                        ? launch_full_sigma<double>(A, nvec, (const double*)c, (double*)y, layout, st)
                        : launch_full_sigma<float>(A, nvec, (const float*)c, (float*)y, layout, st);
@@ -241,6 +245,57 @@ int sbd_full_sigma(const sbd_fbasis* B, const sbd_fham* H, int nvec, int prec, d
     if (!std::isfinite(shift)) return fail(SBD_ERR_ARG, "shift is not finite");
     if (c == sigma) return fail(SBD_ERR_ARG, "c and sigma must not alias");
     return full_sigma_launch(B, H, nvec, prec, shift, c, sigma, layout, (hipStream_t)stream);
+}
+
+int sbd_full_assemble(sbd_fham* H, const sbd_fbasis* B, int precisions, size_t max_bytes, void* stream) {
+    if (!B || !H) return fail(SBD_ERR_ARG, "null argument");
+    if (H->basis_id != B->id) return fail(SBD_ERR_STATE, "Hamiltonian belongs to another basis");
+    if (precisions < 1 || precisions > 3) return fail(SBD_ERR_ARG, "precisions must be 1, 2 or 3");
+    const size_t nc = (size_t)B->nconn;
+    const size_t bytes = nc * (((precisions & 1) ? 8 : 0) + ((precisions & 2) ? 4 : 0));
+    if (max_bytes && bytes > max_bytes)
+        return fail(SBD_ERR_NOMEM, "sbd_full_assemble: the elements need " + std::to_string(bytes) +
+                                       " bytes, more than max_bytes = " + std::to_string(max_bytes));
+    hipStream_t st = (hipStream_t)stream;
+    FullSigmaArgs A;
+    A.n = B->n;
+    A.norb = B->norb;
+    A.dets = B->dets.p;
+    A.rp = B->rp.as<int64_t>();
+    A.J = B->J.as<int32_t>();
+    A.h = H->h64.as<double>();
+    A.eri = H->eri64.as<double>();
+    A.jt = H->jt.as<double>();
+    A.kt = H->kt.as<double>();
+    A.diag = H->diag.as<double>();
+    // built aside, so that a failure leaves the handle as it was
+    DevBuf v64, v32;
+    hipError_t e = hipSuccess;
+    if ((precisions & 1) && nc) e = v64.alloc(sizeof(double) * nc);
+    if (e == hipSuccess && (precisions & 2) && nc) e = v32.alloc(sizeof(float) * nc);
+    if (e != hipSuccess) return hip_fail(e, "sbd_full_assemble allocation");
+    if ((precisions & 1) && nc) e = launch_full_values<double>(A, v64.as<double>(), st);
+    if (e == hipSuccess && (precisions & 2) && nc) e = launch_full_values<float>(A, v32.as<float>(), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "sbd_full_assemble");
+    H->v64 = std::move(v64);
+    H->v32 = std::move(v32);
+    H->asm_prec = precisions;
+    return SBD_OK;
+}
+
+int sbd_full_release_assembled(sbd_fham* H) {
+    if (!H) return fail(SBD_ERR_ARG, "null argument");
+    H->v64 = DevBuf();
+    H->v32 = DevBuf();
+    H->asm_prec = 0;
+    return SBD_OK;
+}
+
+int sbd_full_assembled(const sbd_fham* H, int* precisions) {
+    if (!H) return fail(SBD_ERR_ARG, "null argument");
+    if (precisions) *precisions = H->asm_prec;
+    return SBD_OK;
 }
 
 int sbd_full_davidson(const sbd_fbasis* B, const sbd_fham* H, int nroots, const sbd_davidson_opts* opts_in,

@@ -340,10 +340,16 @@ struct FullSigmaArgs {
     const int32_t* J = nullptr;
     const double *h = nullptr, *eri = nullptr, *jt = nullptr, *kt = nullptr, *diag = nullptr;
     double shift = 0.0;
+    const double* v64 = nullptr;  // assembled elements per connection (FP64 / FP32), or null
+    const float* v32 = nullptr;
 };
-// y = (H - shift) x over a determinant list (layout and nvec as sbd_sigma)
+// y = (H - shift) x over a determinant list (layout and nvec as sbd_sigma),
+// from the assembled elements of the vectors' precision where given
 template <class T>
 hipError_t launch_full_sigma(const FullSigmaArgs& S, int nvec, const T* x, T* y, int layout, hipStream_t st);
+// out[e] = the element of connection e (in the connection order), rounded once to T
+template <class T>
+hipError_t launch_full_values(const FullSigmaArgs& S, T* out, hipStream_t st);
 
 // Device-resident state of device-driven Davidson iterations (k_devloop.hip).
 constexpr int kDlMaxSpace = 48;   // subspace rows

@@ -290,6 +290,7 @@ struct FullArgs {
     const double* kt;   // norb^3: (ak|ki)
     const double* diag;
     double shift;
+    const void* vals;   // assembled elements per connection (T), or null
 };
 
 // Phase of a+_a a_i |w> (i in w, a not): the occupied orbitals strictly between.
@@ -338,9 +339,10 @@ __device__ double full_element(const Det& bra, const Det& ket, const FullArgs& A
 
 // y[I] = (H_II - shift) x[I] + sum_J H_IJ x[J]: one wavefront per bra row, its
 // lanes over the row's connections, NV interleaved vectors per determinant.
-// Each element is formed once in FP64 and, for FP32 vectors, rounded once;
+// Each element is formed once in FP64 and, for FP32 vectors, rounded once
+// (ASM: read from the assembled values, which hold exactly those numbers);
 // partial sums are combined by a fixed butterfly.
-template <class T, int NV>
+template <class T, int NV, bool ASM>
 __global__ void __launch_bounds__(256) k_full_sigma(FullArgs A, const T* __restrict__ x, T* __restrict__ y) {
     const int lane = threadIdx.x & 63;
     const int64_t I = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -352,7 +354,7 @@ __global__ void __launch_bounds__(256) k_full_sigma(FullArgs A, const T* __restr
     const int64_t e1 = A.rp[I + 1];
     for (int64_t e = A.rp[I] + lane; e < e1; e += 64) {
         const int64_t J = A.J[e];
-        const T hv = (T)full_element(bra, A.d[J], A);
+        const T hv = ASM ? static_cast<const T*>(A.vals)[e] : (T)full_element(bra, A.d[J], A);
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] += hv * x[J * NV + v];
     }
@@ -364,6 +366,19 @@ __global__ void __launch_bounds__(256) k_full_sigma(FullArgs A, const T* __restr
 #pragma unroll
         for (int v = 0; v < NV; ++v) y[I * NV + v] = dg * x[I * NV + v] + acc[v];
     }
+}
+
+// The element of every stored connection, in the connection order: one
+// wavefront per bra row, its lanes over the row's connections (the matrix-free
+// product's evaluation, kept instead of summed).
+template <class T>
+__global__ void __launch_bounds__(256) k_full_values(FullArgs A, T* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t I = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (I >= A.n) return;  // wave-uniform
+    const Det bra = A.d[I];
+    const int64_t e1 = A.rp[I + 1];
+    for (int64_t e = A.rp[I] + lane; e < e1; e += 64) out[e] = (T)full_element(bra, A.d[A.J[e]], A);
 }
 
 }  // namespace
@@ -442,9 +457,9 @@ hipError_t launch_full_diag(const void* dets, int64_t nd, int n, const double* h
     return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_full_sigma(const FullSigmaArgs& S, int nvec, const T* x, T* y, int layout, hipStream_t st) {
-    if (S.n <= 0) return hipGetLastError();
+namespace {
+
+FullArgs full_args(const FullSigmaArgs& S) {
     FullArgs A{};
     A.n = S.n;
     A.norb = S.norb;
@@ -457,21 +472,51 @@ hipError_t launch_full_sigma(const FullSigmaArgs& S, int nvec, const T* x, T* y,
     A.kt = S.kt;
     A.diag = S.diag;
     A.shift = S.shift;
-    const dim3 grid(blocks_for(S.n, 4)), block(256);
+    return A;
+}
+
+template <class T, bool ASM>
+hipError_t full_sigma_layouts(const FullArgs& A, int nvec, const T* x, T* y, int layout, hipStream_t st) {
+    const dim3 grid(blocks_for(A.n, 4)), block(256);
     if (layout == 0) {
         for (int v = 0; v < nvec; ++v)
-            hipLaunchKernelGGL((k_full_sigma<T, 1>), grid, block, 0, st, A, x + (size_t)v * S.n,
-                               y + (size_t)v * S.n);
+            hipLaunchKernelGGL((k_full_sigma<T, 1, ASM>), grid, block, 0, st, A, x + (size_t)v * A.n,
+                               y + (size_t)v * A.n);
         return hipGetLastError();
     }
     switch (nvec) {
-        case 1: hipLaunchKernelGGL((k_full_sigma<T, 1>), grid, block, 0, st, A, x, y); break;
-        case 2: hipLaunchKernelGGL((k_full_sigma<T, 2>), grid, block, 0, st, A, x, y); break;
-        case 4: hipLaunchKernelGGL((k_full_sigma<T, 4>), grid, block, 0, st, A, x, y); break;
-        case 8: hipLaunchKernelGGL((k_full_sigma<T, 8>), grid, block, 0, st, A, x, y); break;
+        case 1: hipLaunchKernelGGL((k_full_sigma<T, 1, ASM>), grid, block, 0, st, A, x, y); break;
+        case 2: hipLaunchKernelGGL((k_full_sigma<T, 2, ASM>), grid, block, 0, st, A, x, y); break;
+        case 4: hipLaunchKernelGGL((k_full_sigma<T, 4, ASM>), grid, block, 0, st, A, x, y); break;
+        case 8: hipLaunchKernelGGL((k_full_sigma<T, 8, ASM>), grid, block, 0, st, A, x, y); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+template <class T>
+hipError_t launch_full_values(const FullSigmaArgs& S, T* out, hipStream_t st) {
+    if (S.n <= 0) return hipGetLastError();
+    const FullArgs A = full_args(S);
+    hipLaunchKernelGGL((k_full_values<T>), dim3(blocks_for(S.n, 4)), dim3(256), 0, st, A, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_full_values<double>(const FullSigmaArgs&, double*, hipStream_t);
+template hipError_t launch_full_values<float>(const FullSigmaArgs&, float*, hipStream_t);
+
+template <class T>
+hipError_t launch_full_sigma(const FullSigmaArgs& S, int nvec, const T* x, T* y, int layout, hipStream_t st) {
+    if (S.n <= 0) return hipGetLastError();
+    FullArgs A = full_args(S);
+    const void* vals = sizeof(T) == 8 ? (const void*)S.v64 : (const void*)S.v32;
+    if (vals) {
+        A.vals = vals;
+        return full_sigma_layouts<T, true>(A, nvec, x, y, layout, st);
+    }
+    return full_sigma_layouts<T, false>(A, nvec, x, y, layout, st);
 }
 
 template hipError_t launch_full_sigma<double>(const FullSigmaArgs&, int, const double*, double*, int, hipStream_t);

@@ -288,3 +288,62 @@ def test_full_random_shapes(seed):
     e, rep, st = sbd.full_davidson(H, 1, tol_residual=1e-8)
     assert st == 0
     assert abs(e[0] - np.linalg.eigvalsh(Hd)[0]) <= 1e-8
+
+
+@pytest.mark.parametrize("case", [c for c in LISTS if c[4].shape[0] <= 20000], ids=[c[0] for c in LISTS
+                                                                                      if c[4].shape[0] <= 20000])
+def test_full_assembled_bitwise_matrix_free(case):
+    """The explicit realization (every connection's element kept, Sec. II-A)
+    gives bitwise the matrix-free product in both precisions, one vector and
+    2, 4, 8 interleaved vectors, and the same Davidson energies; releasing it
+    returns to the matrix-free product."""
+    name, norb, na, nb, dets, h, eri, ec = case
+    B, H = gpu_full(norb, na, nb, dets, h, eri, ec)
+    N = B.N
+    X = wl.random_vector(N, 31, nvec=8)
+    shift = -151.25
+    free = {}
+    for prec in (0, 1):
+        free[(prec, 1)] = run_sigma(H, X[0], prec=prec, shift=shift)
+        for nv in (2, 4, 8):
+            free[(prec, nv)] = run_sigma(H, X[:nv].T.copy(), prec=prec, shift=shift, nvec=nv, layout=1)
+    e_free, _, _ = sbd.full_davidson(H, 2, tol_residual=1e-8, max_space=16)
+    H.assemble(3)
+    assert H.assembled() == 3
+    for prec in (0, 1):
+        assert np.array_equal(run_sigma(H, X[0], prec=prec, shift=shift), free[(prec, 1)])
+        for nv in (2, 4, 8):
+            y = run_sigma(H, X[:nv].T.copy(), prec=prec, shift=shift, nvec=nv, layout=1)
+            assert np.array_equal(y, free[(prec, nv)]), (prec, nv)
+    e_asm, _, st = sbd.full_davidson(H, 2, tol_residual=1e-8, max_space=16)
+    assert st == 0 and np.array_equal(e_asm[:2], e_free[:2])
+    H.release_assembled()
+    assert H.assembled() == 0
+    assert np.array_equal(run_sigma(H, X[0], shift=shift), free[(0, 1)])
+
+
+def test_full_assemble_limits_and_errors():
+    """A byte limit below the elements' size fails with SBD_ERR_NOMEM and
+    leaves the Hamiltonian matrix-free; FP32 alone leaves FP64 matrix-free;
+    a Hamiltonian of another list is refused."""
+    W = wl.make_full_config("full16", ndet=3000, nstr=100)
+    B, H = gpu_full(W.norb, W.n_alpha, W.n_beta, W.dets, W.h, W.eri, W.e_core)
+    nconn = B.export()[1][-1]
+    with pytest.raises(sbd.SBDError) as ei:
+        H.assemble(1, max_bytes=8 * nconn - 1)
+    assert ei.value.status == -5 and H.assembled() == 0
+    H.assemble(1, max_bytes=8 * nconn)
+    assert H.assembled() == 1
+    H.assemble(2)
+    assert H.assembled() == 2
+    x = wl.random_vector(B.N, 3)[0]
+    S = oracle.FullOracleSystem(W.norb, W.dets, W.h, W.eri, W.e_core)
+    assert np.linalg.norm(run_sigma(H, x) - S.sigma(x)) <= 1e-12 * np.linalg.norm(S.sigma(x))
+    with pytest.raises(sbd.SBDError):
+        H.assemble(4)
+    W2 = wl.make_full_config("full16", ndet=500, nstr=100)
+    B2, _ = gpu_full(W2.norb, W2.n_alpha, W2.n_beta, W2.dets, W2.h, W2.eri, W2.e_core)
+    with pytest.raises(sbd.SBDError) as ei:
+        check_other = sbd.load().sbd_full_assemble(H._h, B2._h, 1, 0, None)
+        sbd._native.check(check_other)
+    assert ei.value.status == -8
