@@ -415,6 +415,25 @@ def sqd_leg(sbd, wl, stream, steps=(2500, 5000, 7500, 10000)):
                                      setup_ms=r["setup_ms"], solve_ms=r["solve_ms"], status=r["status"])
                                 for r in rep])
     out["energy_max_diff"] = float(max(abs(a - b) for a, b in zip(out["cold"]["energies"], out["warm"]["energies"])))
+    # full-bitstring steps: the basis of a step is the set of sampled determinants.  The record
+    # is the full16 determinant list (drawn from the sel16 string product with level weights,
+    # connected like a selected basis) in a random drawing order, taken in growing prefixes.
+    F = wl.make_full_config("full16")
+    fsmp = F.dets[np.random.default_rng(3102).permutation(F.dets.shape[0])]
+    fsteps = (25000, 50000, 100000, 200000)
+    sbd.sqd_run(F.norb, F.n_alpha, F.n_beta, F.h, F.eri, F.e_core, fsmp, fsteps, full_bitstring=True,
+                stream=stream, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e, rep = sbd.sqd_run(F.norb, F.n_alpha, F.n_beta, F.h, F.eri, F.e_core, fsmp, fsteps, full_bitstring=True,
+                         stream=stream, **kw)
+    torch.cuda.synchronize()
+    out["full_bitstring_warm"] = dict(workload="full16 list, random drawing order",
+                                      ms=1e3 * (time.perf_counter() - t0), energies=[float(x) for x in e[:, 0]],
+                                      steps=[dict(samples=r["samples"], determinants=r["ndet"],
+                                                  alpha_strings=r["n_alpha_str"], iterations=r["iterations"],
+                                                  setup_ms=r["setup_ms"], solve_ms=r["solve_ms"],
+                                                  status=r["status"]) for r in rep])
     return out
 
 
@@ -902,6 +921,10 @@ def main():
             log(f"[bench] sqd loop {name}: {q[name]['ms']:.0f} ms, steps "
                 f"{[(x['determinants'], x['iterations'], round(x['solve_ms'], 1)) for x in q[name]['steps']]}, "
                 f"energies {[round(x, 6) for x in q[name]['energies']]}")
+        fq = q["full_bitstring_warm"]
+        log(f"[bench] sqd loop full bitstring: {fq['ms']:.0f} ms, steps "
+            f"{[(x['determinants'], x['iterations'], round(x['solve_ms'], 1)) for x in fq['steps']]}, "
+            f"energies {[round(x, 6) for x in fq['energies']]}")
         sbd.release_cached_memory()
     if not args.no_full:
         extra["full_bitstring"] = full_leg(sbd, wl, stream)

@@ -349,8 +349,11 @@ void sbd_davidson_default_opts(sbd_davidson_opts* o);
  * classical Gram-Schmidt against the subspace with a second pass when the
  * first removes more than 1 - 1/sqrt(2) of the norm, restart onto
  * the lowest Ritz vectors at max_space, block variant for several roots.
- * Initial vectors: opts->guess, else unit vectors on the nroots lowest
- * diagonal elements (lowest index on ties).
+ * Initial vectors: opts->guess (if any), then unit vectors on the nroots
+ * lowest diagonal elements (lowest index on ties), orthonormalised; vectors
+ * that depend on earlier ones are dropped.  The unit vectors are added after a
+ * guess too, so that a guess lying in a block of H that does not couple to
+ * the lowest state (sparse determinant lists) cannot hide it.
  *   energies: host array of nroots (including e_core), ascending.
  *   vectors : optional caller-owned device array nroots x N (FP64, unit norm).
  *   report  : optional host struct.
@@ -386,6 +389,12 @@ typedef struct {
     sbd_davidson_opts davidson;  /* per-step solve options (guess must be unset) */
     int warm_start;              /* default 1 */
     int spin_union;              /* default 0 */
+    int full_bitstring;          /* default 0.  1: the basis of a step is the set of distinct
+                                    sampled determinants (full-bitstring path, Sec. II-F:
+                                    sbd_full_build_basis, sbd_full_davidson, transfer by
+                                    sbd_full_map_vectors); the step report's n_alpha_str is
+                                    then the number of distinct alpha strings and
+                                    n_beta_str 0.  Not with spin_union. */
 } sbd_sqd_opts;
 typedef struct {
     int status;                  /* sbd_davidson status of the step (0 or SBD_NOT_CONVERGED) */
@@ -471,6 +480,17 @@ int sbd_full_sigma(const sbd_fbasis* b, const sbd_fham* h, int nvec, int prec, d
  */
 int sbd_full_davidson(const sbd_fbasis* b, const sbd_fham* h, int nroots, const sbd_davidson_opts* opts,
                       double* energies, double* vectors, sbd_davidson_report* report, void* stream);
+
+/*
+ * Carry nvec FP64 vectors from one determinant list to another (the
+ * full-bitstring counterpart of sbd_map_vectors, for successive solves of an
+ * SQD run, Sec. I): x_to[v][i] = x_from[v][j] where determinant j of `from`
+ * equals determinant i of `to`, else 0.  Vectors row-major, nvec x ndet of
+ * each list, device pointers; the lists must have the same orbital and
+ * electron counts.  Asynchronous on stream.  Errors: SBD_ERR_ARG, SBD_ERR_HIP.
+ */
+int sbd_full_map_vectors(const sbd_fbasis* from, const sbd_fbasis* to, int nvec, const double* x_from,
+                         double* x_to, void* stream);
 
 /*
  * Explicit realization over a determinant list (Sec. II-A for the list of

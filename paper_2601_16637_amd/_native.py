@@ -35,7 +35,8 @@ EXPORTED = ["sbd_last_error", "sbd_version", "sbd_source_hash", "sbd_release_cac
             "sbd_serve_submit", "sbd_serve_wait", "sbd_serve_destroy",
             "sbd_full_build_basis", "sbd_full_basis_sizes", "sbd_full_basis_export", "sbd_free_full_basis",
             "sbd_full_set_hamiltonian", "sbd_full_ham_diag", "sbd_free_full_ham", "sbd_full_sigma",
-            "sbd_full_davidson", "sbd_full_assemble", "sbd_full_release_assembled", "sbd_full_assembled",
+            "sbd_full_davidson", "sbd_full_map_vectors", "sbd_full_assemble", "sbd_full_release_assembled",
+            "sbd_full_assembled",
             "sbd_sqd_default_opts", "sbd_sqd_run"]
 
 
@@ -84,7 +85,8 @@ class DavidsonReport(ctypes.Structure):
 
 
 class SqdOpts(ctypes.Structure):
-    _fields_ = [("davidson", DavidsonOpts), ("warm_start", ctypes.c_int), ("spin_union", ctypes.c_int)]
+    _fields_ = [("davidson", DavidsonOpts), ("warm_start", ctypes.c_int), ("spin_union", ctypes.c_int),
+                ("full_bitstring", ctypes.c_int)]
 
 
 class SqdStep(ctypes.Structure):
@@ -180,6 +182,7 @@ def load():
     L.sbd_full_sigma.argtypes = [P, P, i32, i32, d, P, P, i32, P]
     L.sbd_full_davidson.argtypes = [P, P, i32, ctypes.POINTER(DavidsonOpts), P, P,
                                     ctypes.POINTER(DavidsonReport), P]
+    L.sbd_full_map_vectors.argtypes = [P, P, i32, P, P, P]
     L.sbd_full_assemble.argtypes = [P, P, i32, ctypes.c_size_t, P]
     L.sbd_full_release_assembled.argtypes = [P]
     L.sbd_full_assembled.argtypes = [P, ctypes.POINTER(i32)]
@@ -536,8 +539,16 @@ def full_davidson(ham: FullHamiltonian, nroots: int = 1, vectors=None, stream=No
     return e, rep.as_dict(nroots), st
 
 
+def full_map_vectors(basis_from: "FullBasis", basis_to: "FullBasis", x_from, x_to, nvec: int = 1, stream=None):
+    """Carry nvec FP64 device vectors from one determinant list to another
+    (sbd_full_map_vectors): determinants absent from basis_from get 0."""
+    check(load().sbd_full_map_vectors(basis_from._h, basis_to._h, int(nvec), _dptr(x_from), _dptr(x_to),
+                                      _stream(stream)))
+    return x_to
+
+
 def sqd_run(norb, n_alpha, n_beta, h1, eri, e_core, samples, step_samples, nroots: int = 1,
-            warm_start: bool = True, spin_union: bool = False, stream=None, **kw):
+            warm_start: bool = True, spin_union: bool = False, full_bitstring: bool = False, stream=None, **kw):
     """Successive solves on a growing set of sampled configurations
     (sbd_sqd_run): step s uses the first step_samples[s] rows of ``samples``
     (alpha string, beta string).  Keyword options are DavidsonOpts fields.
@@ -551,6 +562,7 @@ def sqd_run(norb, n_alpha, n_beta, h1, eri, e_core, samples, step_samples, nroot
     o = SqdOpts()
     load().sbd_sqd_default_opts(ctypes.byref(o))
     o.warm_start, o.spin_union = int(bool(warm_start)), int(bool(spin_union))
+    o.full_bitstring = int(bool(full_bitstring))
     for k, v in kw.items():
         if not hasattr(o.davidson, k) or k == "guess":
             raise TypeError(f"unknown or unsupported option {k}")

@@ -666,8 +666,7 @@ int davidson_run(const SigmaOp& op, int k, const sbd_davidson_opts& o, double* e
     {
         double vprev = -INFINITY;
         int64_t iprev = -1;
-        const int need = (o.n_guess >= k) ? 1 : k;
-        for (int r = 0; r < need; ++r) {
+        for (int r = 0; r < k; ++r) {
             hipError_t e = launch_argmin_after(diag, N, vprev, iprev, sm + kMisc, S.idx.as<int64_t>(),
                                                part, S.idx.as<int64_t>() + 1, st);
             if (e != hipSuccess) return hip_fail(e, "argmin");
@@ -698,7 +697,12 @@ int davidson_run(const SigmaOp& op, int k, const sbd_davidson_opts& o, double* e
     std::vector<double> ebound(ms + 8, 0.0);  // error bound of each basis vector's sigma
     int refinements = 0;
 
-    // ---- initial subspace: guesses, then unit vectors, orthonormalised
+    // ---- initial subspace: guesses, then the unit vectors of the k lowest
+    // diagonal entries, orthonormalised.  The unit vectors are added after a
+    // guess too: where H falls apart into blocks that do not couple (sparse
+    // determinant lists), an iteration started in one block never leaves it,
+    // and a carried guess can sit in a block that no longer holds the lowest
+    // state.
     int m = 0;
     auto add_start = [&](const double* src, int64_t unit) -> int {
         double* t = tmp;
@@ -723,7 +727,7 @@ int davidson_run(const SigmaOp& op, int k, const sbd_davidson_opts& o, double* e
         rc = add_start(o.guess + (size_t)g * N, 0);
         if (rc) return rc;
     }
-    for (size_t r = 0; m < k && r < low_idx.size(); ++r) {
+    for (size_t r = 0; r < low_idx.size() && (m < k || m < ms - k); ++r) {
         rc = add_start(nullptr, low_idx[r]);
         if (rc) return rc;
     }

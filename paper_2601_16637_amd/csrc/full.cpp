@@ -247,6 +247,18 @@ int sbd_full_sigma(const sbd_fbasis* B, const sbd_fham* H, int nvec, int prec, d
     return full_sigma_launch(B, H, nvec, prec, shift, c, sigma, layout, (hipStream_t)stream);
 }
 
+int sbd_full_map_vectors(const sbd_fbasis* from, const sbd_fbasis* to, int nvec, const double* x_from,
+                         double* x_to, void* stream) {
+    if (!from || !to || !x_from || !x_to) return fail(SBD_ERR_ARG, "null argument");
+    if (nvec < 1) return fail(SBD_ERR_ARG, "nvec must be >= 1");
+    if (from->norb != to->norb || from->n_el[0] != to->n_el[0] || from->n_el[1] != to->n_el[1])
+        return fail(SBD_ERR_ARG, "the lists have different orbital or electron counts");
+    const hipError_t e = launch_full_map(from->dets.p, from->n, to->dets.p, to->n, nvec, x_from, x_to,
+                                         (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sbd_full_map_vectors launch");
+    return SBD_OK;
+}
+
 int sbd_full_assemble(sbd_fham* H, const sbd_fbasis* B, int precisions, size_t max_bytes, void* stream) {
     if (!B || !H) return fail(SBD_ERR_ARG, "null argument");
     if (H->basis_id != B->id) return fail(SBD_ERR_STATE, "Hamiltonian belongs to another basis");

@@ -350,6 +350,10 @@ hipError_t launch_full_sigma(const FullSigmaArgs& S, int nvec, const T* x, T* y,
 // out[e] = the element of connection e (in the connection order), rounded once to T
 template <class T>
 hipError_t launch_full_values(const FullSigmaArgs& S, T* out, hipStream_t st);
+// xt[v][i] = xf[v][j] for the determinant j of the sorted list `from` equal to
+// determinant i of `to`, else 0 (nvec vectors of nf and nt doubles)
+hipError_t launch_full_map(const void* from, int64_t nf, const void* to, int64_t nt, int nvec, const double* xf,
+                           double* xt, hipStream_t st);
 
 // Device-resident state of device-driven Davidson iterations (k_devloop.hip).
 constexpr int kDlMaxSpace = 48;   // subspace rows

@@ -381,9 +381,33 @@ __global__ void __launch_bounds__(256) k_full_values(FullArgs A, T* __restrict__
     for (int64_t e = A.rp[I] + lane; e < e1; e += 64) out[e] = (T)full_element(bra, A.d[A.J[e]], A);
 }
 
+// x_to[v][i] = x_from[v][j] where from[j] == to[i] (binary search in the sorted
+// from-list), else 0: one thread per determinant of the new list.
+__global__ void k_full_map(const Det* __restrict__ from, int64_t nf, const Det* __restrict__ to, int64_t nt,
+                           int nvec, const double* __restrict__ xf, double* __restrict__ xt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    const Det d = to[i];
+    int64_t lo = 0, hi = nf;  // first index with from[j] >= d
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (det_gt(d, from[mid])) lo = mid + 1;
+        else hi = mid;
+    }
+    const bool hit = lo < nf && !det_ne(from[lo], d);
+    for (int v = 0; v < nvec; ++v) xt[(size_t)v * nt + i] = hit ? xf[(size_t)v * nf + lo] : 0.0;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+hipError_t launch_full_map(const void* from, int64_t nf, const void* to, int64_t nt, int nvec, const double* xf,
+                           double* xt, hipStream_t st) {
+    if (nt > 0)
+        hipLaunchKernelGGL(k_full_map, dim3(blocks_for(nt, 256)), dim3(256), 0, st, static_cast<const Det*>(from),
+                           nf, static_cast<const Det*>(to), nt, nvec, xf, xt);
+    return hipGetLastError();
+}
 hipError_t launch_full_sort_unique(void* work, int64_t n, void* out, int64_t* d_count, hipStream_t st) {
     Det* a = static_cast<Det*>(work);
     int64_t P = 1;

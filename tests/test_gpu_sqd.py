@@ -68,3 +68,57 @@ def test_sqd_rejects_bad_steps():
         assert ei.value.status == -1
     with pytest.raises(sbd.SBDError):
         sbd.sqd_run(norb, n, n + 1, h, eri, ec, smp, [10], spin_union=True)
+
+
+# ------------------------------------------------------------------ full-bitstring steps
+def test_full_map_vectors_bitexact():
+    """sbd_full_map_vectors: each determinant of the new list takes the
+    coefficient of the same determinant in the old list, or 0 (checked by a
+    dictionary lookup over the exported lists)."""
+    norb, n = 10, 4
+    smp = wl.sample_configurations(norb, n, n, 900, 640)
+    B1 = sbd.FullBasis(norb, n, n, smp[:300])
+    B2 = sbd.FullBasis(norb, n, n, smp[150:900])  # overlaps the first list only in part
+    d1, d2 = B1.export()[0], B2.export()[0]
+    X = wl.random_vector(B1.N, 641, nvec=3)
+    xf = torch.tensor(X.reshape(-1), device="cuda", dtype=torch.float64)
+    xt = torch.full((3 * B2.N,), float("nan"), device="cuda", dtype=torch.float64)
+    sbd.full_map_vectors(B1, B2, xf, xt, nvec=3)
+    torch.cuda.synchronize()
+    got = xt.cpu().numpy().reshape(3, B2.N)
+    pos = {(int(a), int(b)): j for j, (a, b) in enumerate(d1)}
+    want = np.zeros((3, B2.N))
+    for i, (a, b) in enumerate(d2):
+        j = pos.get((int(a), int(b)))
+        if j is not None:
+            want[:, i] = X[:, j]
+    assert np.array_equal(got, want)
+    assert 0 < sum(1 for a, b in d2 if (int(a), int(b)) in pos) < B2.N
+
+
+@pytest.mark.parametrize("nroots", [1, 2])
+def test_sqd_full_bitstring_steps_match_dense(nroots):
+    """With full_bitstring each step's basis is the set of distinct sampled
+    determinants (no Cartesian product): every step's energies equal the
+    dense eigenvalues of the oracle's H over that list within 1e-8 Ha, warm and
+    cold runs agree, and the lowest energy does not rise."""
+    norb, n = 10, 4
+    h, eri, ec = wl.make_integrals(norb, 650)
+    smp = wl.sample_configurations(norb, n, n, 1200, 651)
+    steps = [40, 200, 600, 1200]
+    e, rep = sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps, nroots=nroots, full_bitstring=True,
+                         tol_residual=1e-8)
+    ec_, _ = sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps, nroots=nroots, full_bitstring=True,
+                         warm_start=False, tol_residual=1e-8)
+    for s, m in enumerate(steps):
+        dets = np.unique(smp[:m], axis=0)
+        S = oracle.FullOracleSystem(norb, dets, h, eri, ec)
+        eo = np.linalg.eigvalsh(S.dense_h())[:nroots]
+        assert rep[s]["ndet"] == S.N and rep[s]["status"] == 0 and rep[s]["n_beta_str"] == 0
+        assert rep[s]["n_alpha_str"] == np.unique(dets[:, 0]).size
+        assert np.abs(e[s, :eo.size] - eo).max() <= 1e-8, (s, e[s], eo)
+        assert rep[s]["warm"] == (1 if s > 0 else 0)
+    assert np.abs(e - ec_).max() <= 1e-8
+    assert np.all(np.diff(e[:, 0]) <= 1e-10)
+    with pytest.raises(sbd.SBDError):
+        sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps, full_bitstring=True, spin_union=True)
