@@ -32,7 +32,7 @@ struct sbd_fham {
     int norb = 0;
     int64_t n = 0;
     double e_core = 0.0;
-    DevBuf h64, eri64, jt, kt, jd, kd, diag;
+    DevBuf h64, eri64, jt, kt, jd, kd, dd, diag;
     DevBuf v64, v32;   // assembled elements per connection (explicit realization)
     int asm_prec = 0;  // bit 0: FP64 assembled, bit 1: FP32
 };
@@ -54,10 +54,10 @@ int validate_dets(int norb, int na, int nb, const uint64_t* d, int64_t n) {
     return SBD_OK;
 }
 
-int full_sigma_launch(const sbd_fbasis* B, const sbd_fham* H, int nvec, int prec, double shift, const void* c,
-                      void* y, int layout, hipStream_t st) {
+FullSigmaArgs sigma_args(const sbd_fbasis* B, const sbd_fham* H) {
     FullSigmaArgs A;
     A.n = B->n;
+    A.nconn = B->nconn;
     A.norb = B->norb;
     A.dets = B->dets.p;
     A.rp = B->rp.as<int64_t>();
@@ -66,7 +66,14 @@ int full_sigma_launch(const sbd_fbasis* B, const sbd_fham* H, int nvec, int prec
     A.eri = H->eri64.as<double>();
     A.jt = H->jt.as<double>();
     A.kt = H->kt.as<double>();
+    A.dd = H->dd.as<double>();
     A.diag = H->diag.as<double>();
+    return A;
+}
+
+int full_sigma_launch(const sbd_fbasis* B, const sbd_fham* H, int nvec, int prec, double shift, const void* c,
+                      void* y, int layout, hipStream_t st) {
+    FullSigmaArgs A = sigma_args(B, H);
     A.shift = shift;
     if (H->asm_prec & 1) A.v64 = H->v64.as<double>();
     if (H->asm_prec & 2) A.v32 = H->v32.as<float>();
@@ -202,19 +209,20 @@ int sbd_full_set_hamiltonian(const sbd_fbasis* B, const double* h1, const double
     H->norb = n;
     H->n = B->n;
     H->e_core = e_core;
-    const size_t n2 = (size_t)n * n, n3 = n2 * n, n4 = n3 * n;
+    const size_t n2 = (size_t)n * n, n3 = n2 * n, n4 = n3 * n, npair = (size_t)n * (n - 1) / 2;
     hipError_t e = H->h64.alloc(sizeof(double) * n2);
     if (e == hipSuccess) e = H->eri64.alloc(sizeof(double) * n4);
     if (e == hipSuccess) e = H->jt.alloc(sizeof(double) * n3);
     if (e == hipSuccess) e = H->kt.alloc(sizeof(double) * n3);
     if (e == hipSuccess) e = H->jd.alloc(sizeof(double) * n2);
     if (e == hipSuccess) e = H->kd.alloc(sizeof(double) * n2);
+    if (e == hipSuccess) e = H->dd.alloc(sizeof(double) * npair * npair);
     if (e == hipSuccess) e = H->diag.alloc(sizeof(double) * B->n);
     if (e == hipSuccess) e = hipMemcpyAsync(H->h64.p, h1, sizeof(double) * n2, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(H->eri64.p, eri, sizeof(double) * n4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = launch_full_tables(H->eri64.as<double>(), n, H->jt.as<double>(), H->kt.as<double>(), H->jd.as<double>(),
-                               H->kd.as<double>(), st);
+                               H->kd.as<double>(), H->dd.as<double>(), st);
     if (e == hipSuccess)
         e = launch_full_diag(B->dets.p, B->n, n, H->h64.as<double>(), H->jd.as<double>(), H->kd.as<double>(),
                              e_core, H->diag.as<double>(), st);
@@ -269,17 +277,7 @@ int sbd_full_assemble(sbd_fham* H, const sbd_fbasis* B, int precisions, size_t m
         return fail(SBD_ERR_NOMEM, "sbd_full_assemble: the elements need " + std::to_string(bytes) +
                                        " bytes, more than max_bytes = " + std::to_string(max_bytes));
     hipStream_t st = (hipStream_t)stream;
-    FullSigmaArgs A;
-    A.n = B->n;
-    A.norb = B->norb;
-    A.dets = B->dets.p;
-    A.rp = B->rp.as<int64_t>();
-    A.J = B->J.as<int32_t>();
-    A.h = H->h64.as<double>();
-    A.eri = H->eri64.as<double>();
-    A.jt = H->jt.as<double>();
-    A.kt = H->kt.as<double>();
-    A.diag = H->diag.as<double>();
+    const FullSigmaArgs A = sigma_args(B, H);
     // built aside, so that a failure leaves the handle as it was
     DevBuf v64, v32;
     hipError_t e = hipSuccess;

@@ -327,9 +327,11 @@ hipError_t launch_full_group_nbr(const uint64_t* ua, int64_t ng, int64_t* cnt, c
 hipError_t launch_full_conn(const void* dets, int64_t n, const int32_t* grp, const int64_t* goff,
                             const int64_t* gn_rp, const int32_t* gn_j, const int8_t* gn_d, int64_t* cnt,
                             const int64_t* rp, int32_t* J, int8_t* deg, hipStream_t st);
-// integral tables: jt/kt norb^3 ((ai|kk), (ak|ki)), jd/kd norb^2 ((pp|qq), (pq|qp))
+// integral tables: jt/kt norb^3 ((ai|kk), (ak|ki)), jd/kd norb^2 ((pp|qq), (pq|qp)),
+// and dd npair^2 (npair = norb(norb-1)/2): dd[P(a,b) npair + P(i,j)] = (ai|bj) - (aj|bi)
+// for a < b, i < j, P(p,q) = q(q-1)/2 + p
 hipError_t launch_full_tables(const double* eri, int n, double* jt, double* kt, double* jd, double* kd,
-                              hipStream_t st);
+                              double* dd, hipStream_t st);
 hipError_t launch_full_diag(const void* dets, int64_t nd, int n, const double* h, const double* jd,
                             const double* kd, double e_core, double* out, hipStream_t st);
 struct FullSigmaArgs {
@@ -338,7 +340,8 @@ struct FullSigmaArgs {
     const void* dets = nullptr;
     const int64_t* rp = nullptr;
     const int32_t* J = nullptr;
-    const double *h = nullptr, *eri = nullptr, *jt = nullptr, *kt = nullptr, *diag = nullptr;
+    int64_t nconn = 0;
+    const double *h = nullptr, *eri = nullptr, *jt = nullptr, *kt = nullptr, *dd = nullptr, *diag = nullptr;
     double shift = 0.0;
     const double* v64 = nullptr;  // assembled elements per connection (FP64 / FP32), or null
     const float* v32 = nullptr;

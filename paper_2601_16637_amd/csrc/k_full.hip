@@ -19,8 +19,9 @@
 // sigma is matrix-free: each connection's matrix element is formed from the two
 // bitstrings alone (bit scans for the moved orbitals, popcounts of masked words
 // for the phase, integrals by index), as the excitation generator of the
-// full-bitstring representation prescribes, and accumulated per bra row by one
-// wavefront in a fixed order (bitwise reproducible, no atomics).
+// full-bitstring representation prescribes, and accumulated per bra row by a
+// fixed group of lanes in a fixed order (bitwise reproducible, no atomics).
+// Same-spin doubles read one antisymmetrised integral from a pair table.
 #include "internal.h"
 
 namespace sbd {
@@ -233,12 +234,28 @@ __global__ void __launch_bounds__(kWaves * 64) k_conn(const Det* __restrict__ d,
 }
 
 // ------------------------------------------------------------------ Hamiltonian
+// Index of the orbital pair p < q among the n(n-1)/2 pairs.
+__device__ __forceinline__ int pair_index(int p, int q) { return q * (q - 1) / 2 + p; }
+
 // Tables of the single-excitation spectator terms: jt[(a n + i) n + k] = (ai|kk),
-// kt[(a n + i) n + k] = (ak|ki); and jd[p n + q] = (pp|qq), kd[p n + q] = (pq|qp).
+// kt[(a n + i) n + k] = (ak|ki); jd[p n + q] = (pp|qq), kd[p n + q] = (pq|qp);
+// and the antisymmetrised same-spin double elements
+// dd[P(a,b) npair + P(i,j)] = (ai|bj) - (aj|bi) for a < b, i < j.
 __global__ void k_full_tables(const double* __restrict__ eri, int n, double* jt, double* kt, double* jd,
-                              double* kd) {
+                              double* kd, double* dd) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n3 = (int64_t)n * n * n;
+    const int64_t np = (int64_t)n * (n - 1) / 2;
+    if (t < np * np) {
+        // invert the pair index: q is the largest with q(q-1)/2 <= P
+        const int P = (int)(t / np), Q = (int)(t % np);
+        int b = 1, j = 1;
+        while ((b + 1) * b / 2 <= P) ++b;
+        while ((j + 1) * j / 2 <= Q) ++j;
+        const int a = P - b * (b - 1) / 2, i = Q - j * (j - 1) / 2;
+        const int64_t nn = n;
+        dd[t] = eri[((a * nn + i) * nn + b) * nn + j] - eri[((a * nn + j) * nn + b) * nn + i];
+    }
     if (t < n3) {
         const int k = (int)(t % n), i = (int)((t / n) % n), a = (int)(t / ((int64_t)n * n));
         const int64_t nn = n;
@@ -288,6 +305,8 @@ struct FullArgs {
     const double* eri;  // norb^4
     const double* jt;   // norb^3: (ai|kk)
     const double* kt;   // norb^3: (ak|ki)
+    const double* dd;   // npair^2: (ai|bj) - (aj|bi), a < b, i < j
+    int npair;          // norb (norb - 1) / 2
     const double* diag;
     double shift;
     const void* vals;   // assembled elements per connection (T), or null
@@ -326,7 +345,7 @@ __device__ double full_element(const Det& bra, const Det& ket, const FullArgs& A
         const uint64_t k1 = wk ^ (1ull << i), k2 = k1 ^ (1ull << j), k3 = k2 | (1ull << b);
         const int par = __popcll(wk & below(i)) + __popcll(k1 & below(j)) + __popcll(k2 & below(b)) +
                         __popcll(k3 & below(a));
-        const double v = A.eri[((a * nn + i) * nn + b) * nn + j] - A.eri[((a * nn + j) * nn + b) * nn + i];
+        const double v = A.dd[(int64_t)pair_index(a, b) * A.npair + pair_index(i, j)];
         return (par & 1) ? -v : v;
     }
     // one alpha and one beta electron: alpha i -> a, beta j -> b, element (ai|bj)
@@ -337,22 +356,25 @@ __device__ double full_element(const Det& bra, const Det& ket, const FullArgs& A
     return (par & 1) ? -v : v;
 }
 
-// y[I] = (H_II - shift) x[I] + sum_J H_IJ x[J]: one wavefront per bra row, its
-// lanes over the row's connections, NV interleaved vectors per determinant.
-// Each element is formed once in FP64 and, for FP32 vectors, rounded once
-// (ASM: read from the assembled values, which hold exactly those numbers);
-// partial sums are combined by a fixed butterfly.
-template <class T, int NV, bool ASM>
+// y[I] = (H_II - shift) x[I] + sum_J H_IJ x[J]: G lanes per bra row (64 / G
+// rows per wavefront), the lanes over the row's connections, NV interleaved
+// vectors per determinant.  Each element is formed once in FP64 and, for FP32
+// vectors, rounded once (ASM: read from the assembled values, which hold
+// exactly those numbers); partial sums are combined by a fixed butterfly
+// within the row's lanes.
+template <class T, int NV, bool ASM, int G>
 __global__ void __launch_bounds__(256) k_full_sigma(FullArgs A, const T* __restrict__ x, T* __restrict__ y) {
-    const int lane = threadIdx.x & 63;
-    const int64_t I = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (I >= A.n) return;  // wave-uniform
+    const int lane = threadIdx.x & 63, sub = lane & (G - 1);
+    const int64_t I = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / G) + lane / G;
+    // a whole row group leaves together, so the butterfly below (lane offsets
+    // below G) only reads lanes of the same row
+    if (I >= A.n) return;
     const Det bra = A.d[I];
     T acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = T(0);
     const int64_t e1 = A.rp[I + 1];
-    for (int64_t e = A.rp[I] + lane; e < e1; e += 64) {
+    for (int64_t e = A.rp[I] + sub; e < e1; e += G) {
         const int64_t J = A.J[e];
         const T hv = ASM ? static_cast<const T*>(A.vals)[e] : (T)full_element(bra, A.d[J], A);
 #pragma unroll
@@ -360,8 +382,8 @@ __global__ void __launch_bounds__(256) k_full_sigma(FullArgs A, const T* __restr
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v)
-        for (int off = 32; off > 0; off >>= 1) acc[v] += __shfl_xor(acc[v], off, 64);
-    if (lane == 0) {
+        for (int off = G / 2; off > 0; off >>= 1) acc[v] += __shfl_xor(acc[v], off, 64);
+    if (sub == 0) {
         const T dg = (T)(A.diag[I] - A.shift);
 #pragma unroll
         for (int v = 0; v < NV; ++v) y[I * NV + v] = dg * x[I * NV + v] + acc[v];
@@ -467,9 +489,10 @@ hipError_t launch_full_conn(const void* dets, int64_t n, const int32_t* grp, con
 }
 
 hipError_t launch_full_tables(const double* eri, int n, double* jt, double* kt, double* jd, double* kd,
-                              hipStream_t st) {
-    const int64_t n3 = (int64_t)n * n * n;
-    hipLaunchKernelGGL(k_full_tables, dim3(blocks_for(n3, 256)), dim3(256), 0, st, eri, n, jt, kt, jd, kd);
+                              double* dd, hipStream_t st) {
+    const int64_t n3 = (int64_t)n * n * n, np = (int64_t)n * (n - 1) / 2;
+    const int64_t m = n3 > np * np ? n3 : np * np;
+    hipLaunchKernelGGL(k_full_tables, dim3(blocks_for(m, 256)), dim3(256), 0, st, eri, n, jt, kt, jd, kd, dd);
     return hipGetLastError();
 }
 
@@ -494,28 +517,50 @@ FullArgs full_args(const FullSigmaArgs& S) {
     A.eri = S.eri;
     A.jt = S.jt;
     A.kt = S.kt;
+    A.dd = S.dd;
+    A.npair = S.norb * (S.norb - 1) / 2;
     A.diag = S.diag;
     A.shift = S.shift;
     return A;
 }
 
-template <class T, bool ASM>
+template <class T, bool ASM, int G>
 hipError_t full_sigma_layouts(const FullArgs& A, int nvec, const T* x, T* y, int layout, hipStream_t st) {
-    const dim3 grid(blocks_for(A.n, 4)), block(256);
+    const dim3 grid(blocks_for(A.n, 4 * (64 / G))), block(256);
     if (layout == 0) {
         for (int v = 0; v < nvec; ++v)
-            hipLaunchKernelGGL((k_full_sigma<T, 1, ASM>), grid, block, 0, st, A, x + (size_t)v * A.n,
+            hipLaunchKernelGGL((k_full_sigma<T, 1, ASM, G>), grid, block, 0, st, A, x + (size_t)v * A.n,
                                y + (size_t)v * A.n);
         return hipGetLastError();
     }
     switch (nvec) {
-        case 1: hipLaunchKernelGGL((k_full_sigma<T, 1, ASM>), grid, block, 0, st, A, x, y); break;
-        case 2: hipLaunchKernelGGL((k_full_sigma<T, 2, ASM>), grid, block, 0, st, A, x, y); break;
-        case 4: hipLaunchKernelGGL((k_full_sigma<T, 4, ASM>), grid, block, 0, st, A, x, y); break;
-        case 8: hipLaunchKernelGGL((k_full_sigma<T, 8, ASM>), grid, block, 0, st, A, x, y); break;
+        case 1: hipLaunchKernelGGL((k_full_sigma<T, 1, ASM, G>), grid, block, 0, st, A, x, y); break;
+        case 2: hipLaunchKernelGGL((k_full_sigma<T, 2, ASM, G>), grid, block, 0, st, A, x, y); break;
+        case 4: hipLaunchKernelGGL((k_full_sigma<T, 4, ASM, G>), grid, block, 0, st, A, x, y); break;
+        case 8: hipLaunchKernelGGL((k_full_sigma<T, 8, ASM, G>), grid, block, 0, st, A, x, y); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Lanes per bra row, from the list's mean row length m: about m / 2, a power of
+// two from 8 to 64.  Fewer lanes per row put several short rows in one
+// wavefront (more connections in flight per wave); at m = 28 sixteen lanes
+// beat 64 by a quarter, at m = 275 64 lanes are best.
+int full_lanes(int64_t n, int64_t nconn) {
+    const double m = n > 0 ? (double)nconn / (double)n : 0.0;
+    return m >= 96 ? 64 : m >= 48 ? 32 : m >= 12 ? 16 : 8;
+}
+
+template <class T, bool ASM>
+hipError_t full_sigma_lanes(const FullArgs& A, int64_t nconn, int nvec, const T* x, T* y, int layout,
+                            hipStream_t st) {
+    switch (full_lanes(A.n, nconn)) {
+        case 64: return full_sigma_layouts<T, ASM, 64>(A, nvec, x, y, layout, st);
+        case 32: return full_sigma_layouts<T, ASM, 32>(A, nvec, x, y, layout, st);
+        case 16: return full_sigma_layouts<T, ASM, 16>(A, nvec, x, y, layout, st);
+        default: return full_sigma_layouts<T, ASM, 8>(A, nvec, x, y, layout, st);
+    }
 }
 
 }  // namespace
@@ -538,9 +583,9 @@ hipError_t launch_full_sigma(const FullSigmaArgs& S, int nvec, const T* x, T* y,
     const void* vals = sizeof(T) == 8 ? (const void*)S.v64 : (const void*)S.v32;
     if (vals) {
         A.vals = vals;
-        return full_sigma_layouts<T, true>(A, nvec, x, y, layout, st);
+        return full_sigma_lanes<T, true>(A, S.nconn, nvec, x, y, layout, st);
     }
-    return full_sigma_layouts<T, false>(A, nvec, x, y, layout, st);
+    return full_sigma_lanes<T, false>(A, S.nconn, nvec, x, y, layout, st);
 }
 
 template hipError_t launch_full_sigma<double>(const FullSigmaArgs&, int, const double*, double*, int, hipStream_t);
