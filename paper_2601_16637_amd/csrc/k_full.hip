@@ -11,10 +11,11 @@
 // Connections (the Slater-Condon neighbourhood of Eq. 4: the determinants that
 // differ by one or two electrons) are found group-wise: the alpha strings of
 // the groups are compared all-pairs (popcount of the XOR <= 4, itself
-// included), and a determinant then scans only the groups whose alpha string is
-// that close, testing popcount(alpha XOR) + popcount(beta XOR) in {2, 4}.  Rows
-// come out sorted by ket index because groups and their members are visited in
-// ascending order and hits are placed by a wave ballot.
+// included), and a determinant then visits only the groups whose alpha string is
+// that close, testing popcount(alpha XOR) + popcount(beta XOR) in {2, 4}: a
+// group two alpha electrons away by a binary search for the same beta string,
+// the others by a scan.  Rows come out sorted by ket index because groups and
+// their members are visited in ascending order and hits are placed in order.
 //
 // sigma is matrix-free: each connection's matrix element is formed from the two
 // bitstrings alone (bit scans for the moved orbitals, popcounts of masked words
@@ -188,7 +189,13 @@ __global__ void __launch_bounds__(kWaves * 64) k_group_nbr(const uint64_t* __res
 }
 
 // Connections of each determinant: count pass and fill pass (ket index and
-// electrons moved, 1 or 2), rows sorted by ket.
+// electrons moved, 1 or 2), rows sorted by ket.  The neighbour groups are taken
+// 64 at a time, in ascending order.  A group whose alpha string is two electrons
+// away can hold only one connection, the determinant with the same beta string:
+// each lane finds it for one such group by binary search (the group is sorted
+// by beta string).  The other groups (alpha string equal or one electron away)
+// are scanned by the whole wavefront, one group after another, so hits are
+// placed in ascending ket order by a wave ballot.
 template <bool FILL>
 __global__ void __launch_bounds__(kWaves * 64) k_conn(const Det* __restrict__ d, int64_t n,
                                                       const int32_t* __restrict__ grp,
@@ -205,25 +212,56 @@ __global__ void __launch_bounds__(kWaves * 64) k_conn(const Det* __restrict__ d,
     const int g = grp[I];
     int64_t o = FILL ? rp[I] : 0;
     int c = 0;
-    for (int64_t e = gn_rp[g]; e < gn_rp[g + 1]; ++e) {
-        const int h = gn_j[e];
-        const int pa = 2 * (int)gn_d[e];
-        const int64_t k0 = goff[h], k1 = goff[h + 1];
-        for (int64_t t0 = k0; t0 < k1; t0 += 64) {
-            const int64_t K = t0 + lane;
-            const bool ok = K < k1;
-            const int tot = pa + (ok ? __popcll(ib ^ d[K].b) : 0);
-            const bool hit = ok && (tot == 2 || tot == 4);
-            if (FILL) {
-                const uint64_t m = __ballot(hit);
-                if (hit) {
-                    const int64_t q = o + __popcll(m & lt);
-                    J[q] = (int32_t)K;
-                    deg[q] = (int8_t)(tot >> 1);
+    const int64_t e0 = gn_rp[g], e1 = gn_rp[g + 1];
+    for (int64_t eb = e0; eb < e1; eb += 64) {
+        const int64_t e = eb + lane;
+        const bool dbl = e < e1 && gn_d[e] == 2;
+        int hitK = -1;
+        if (dbl) {
+            const int h = gn_j[e];
+            const int64_t end = goff[h + 1];
+            int64_t lo = goff[h], hi = end;  // first member with beta string >= ib
+            while (lo < hi) {
+                const int64_t mid = lo + ((hi - lo) >> 1);
+                if (d[mid].b < ib) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < end && d[lo].b == ib) hitK = (int)lo;
+        }
+        if (!FILL) c += hitK >= 0;
+        const uint64_t dmask = __ballot(dbl), hmask = __ballot(hitK >= 0);
+        const int m = (int)((e1 - eb) < 64 ? (e1 - eb) : 64);
+        for (int t = 0; t < m; ++t) {  // wave-uniform
+            if ((dmask >> t) & 1) {
+                if (FILL && ((hmask >> t) & 1)) {
+                    const int K = __shfl(hitK, t, 64);
+                    if (lane == 0) {
+                        J[o] = (int32_t)K;
+                        deg[o] = 2;
+                    }
+                    ++o;
                 }
-                o += __popcll(m);
-            } else {
-                c += hit;
+                continue;
+            }
+            const int h = gn_j[eb + t];
+            const int pa = 2 * (int)gn_d[eb + t];
+            const int64_t k0 = goff[h], k1 = goff[h + 1];
+            for (int64_t t0 = k0; t0 < k1; t0 += 64) {
+                const int64_t K = t0 + lane;
+                const bool ok = K < k1;
+                const int tot = pa + (ok ? __popcll(ib ^ d[K].b) : 0);
+                const bool hit = ok && (tot == 2 || tot == 4);
+                if (FILL) {
+                    const uint64_t hm = __ballot(hit);
+                    if (hit) {
+                        const int64_t q = o + __popcll(hm & lt);
+                        J[q] = (int32_t)K;
+                        deg[q] = (int8_t)(tot >> 1);
+                    }
+                    o += __popcll(hm);
+                } else {
+                    c += hit;
+                }
             }
         }
     }
