@@ -452,7 +452,9 @@ void sbd_free_full_basis(sbd_fbasis* b);
  * Hamiltonian over a determinant list (Eq. 3): h1 norb*norb and eri norb^4
  * host arrays as in sbd_set_hamiltonian, e_core added to every diagonal
  * element.  Uploads the integrals, derives the single-excitation spectator
- * tables (ai|kk), (ak|ki) and caches the FP64 diagonal H_II (Sec. II-E).
+ * tables (ai|kk), (ak|ki), the antisymmetrised same-spin double elements
+ * (ai|bj) - (aj|bi) over orbital pairs a < b, i < j (8 (norb(norb-1)/2)^2
+ * bytes), and caches the FP64 diagonal H_II (Sec. II-E).
  * Errors: SBD_ERR_INTEGRALS, SBD_ERR_ARG, SBD_ERR_NOMEM, SBD_ERR_HIP.
  */
 int sbd_full_set_hamiltonian(const sbd_fbasis* b, const double* h1, const double* eri, double e_core,
@@ -466,8 +468,9 @@ void sbd_free_full_ham(sbd_fham* h);
  * the full-bitstring path).  nvec, prec, layout and ownership as in
  * sbd_sigma, N = ndet.  Every connection's element is formed in FP64 from the
  * two bitstrings; in SBD_FP32 it is rounded once to FP32 and the gathers and
- * accumulation are FP32.  One wavefront per row sums in a fixed order: results
- * are bitwise reproducible.  No workspace.
+ * accumulation are FP32.  A fixed group of lanes per row (8 to 64, from the
+ * list's mean row length) sums in a fixed order: results are bitwise
+ * reproducible.  No workspace.
  * Errors: SBD_ERR_ARG, SBD_ERR_STATE (h built on another list), SBD_ERR_HIP.
  */
 int sbd_full_sigma(const sbd_fbasis* b, const sbd_fham* h, int nvec, int prec, double shift,
