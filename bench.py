@@ -218,10 +218,12 @@ def _short(name):
 
 def stats_summary(csv_path, top=25, prefix=None):
     """Markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv),
-    optionally only of the kernels whose short name starts with `prefix`."""
+    optionally only of the kernels whose short name starts with `prefix` (or
+    with one of several comma-separated prefixes)."""
     rows = _csv_rows(csv_path)
     if prefix:
-        rows = [r for r in rows if _short(_col(r, "Name")).startswith(prefix)]
+        keep = tuple(p for p in prefix.split(",") if p)
+        rows = [r for r in rows if _short(_col(r, "Name")).startswith(keep)]
     rows.sort(key=lambda r: -float(_col(r, "TotalDurationNs")))
     out = ["| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
     for r in rows[:top]:
@@ -748,7 +750,8 @@ def main():
     ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
                     help="print a markdown summary of a rocprofv3 --stats run and exit")
     ap.add_argument("--stats-prefix", metavar="PREFIX",
-                    help="with --stats-summary: only kernels whose name starts with PREFIX")
+                    help="with --stats-summary: only kernels whose name starts with PREFIX "
+                         "(several prefixes separated by commas)")
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_ONLY_LOG"),
                     help="print calibrated HBM bytes per launch of the dominant kernel and exit")
     ap.add_argument("--launch-gaps", metavar="KERNEL_TRACE_CSV",

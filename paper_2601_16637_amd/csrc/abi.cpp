@@ -211,8 +211,8 @@ int sbd_build_excitations(const sbd_basis* b, void* stream, sbd_exc** out) {
         if (e == hipSuccess) e = t2.row_ptr.alloc(sizeof(int64_t) * (n + 1));
         if (e == hipSuccess)
             e = launch_exc_count(b->s[s].d.as<uint64_t>(), n, c1.as<int64_t>(), c2.as<int64_t>(), st);
-        if (e == hipSuccess) e = launch_exclusive_scan(c1.as<int64_t>(), n, t1.row_ptr.as<int64_t>(), st);
-        if (e == hipSuccess) e = launch_exclusive_scan(c2.as<int64_t>(), n, t2.row_ptr.as<int64_t>(), st);
+        if (e == hipSuccess) e = launch_exclusive_scan(c1.as<int64_t>(), n, t1.row_ptr.as<int64_t>(), nullptr, st);
+        if (e == hipSuccess) e = launch_exclusive_scan(c2.as<int64_t>(), n, t2.row_ptr.as<int64_t>(), nullptr, st);
         int64_t tot[2] = {0, 0};
         if (e == hipSuccess)
             e = hipMemcpyAsync(&tot[0], t1.row_ptr.as<int64_t>() + n, sizeof(int64_t),
@@ -263,7 +263,7 @@ int sbd_build_excitations(const sbd_basis* b, void* stream, sbd_exc** out) {
             e = launch_sell_len(t1.row_ptr.as<int64_t>(), t1.sell_pos.as<int32_t>(), n,
                                 slots.as<int64_t>(), st);
         if (e == hipSuccess)
-            e = launch_exclusive_scan(slots.as<int64_t>(), nslice, t1.sell_off.as<int64_t>(), st);
+            e = launch_exclusive_scan(slots.as<int64_t>(), nslice, t1.sell_off.as<int64_t>(), nullptr, st);
         int64_t sell_total = 0;
         if (e == hipSuccess)
             e = hipMemcpyAsync(&sell_total, t1.sell_off.as<int64_t>() + nslice, sizeof(int64_t),
@@ -574,11 +574,12 @@ extern "C" int sbd_ham_assemble(sbd_ham* H, const sbd_exc* x, int precisions, si
     t.Ga = H->sc[0].G64.as<double>(); t.Gb = H->sc[1].G64.as<double>();
     t.eri = H->eri64.as<double>(); t.diag = H->diag.as<double>();
     // row lengths, their scan, then the size check before the large allocations
-    DevBuf cnt, rp;
+    DevBuf cnt, rp, tmp;
     SBD_HIP(cnt.alloc(sizeof(int64_t) * (size_t)std::max<int64_t>(N, 1)));
     SBD_HIP(rp.alloc(sizeof(int64_t) * (size_t)(N + 1)));
+    SBD_HIP(tmp.alloc(sizeof(int64_t) * (size_t)scan_tmp_words(N)));
     SBD_HIP(launch_csr_count(t, cnt.as<int64_t>(), st));
-    SBD_HIP(launch_exclusive_scan(cnt.as<int64_t>(), N, rp.as<int64_t>(), st));
+    SBD_HIP(launch_exclusive_scan(cnt.as<int64_t>(), N, rp.as<int64_t>(), tmp.as<int64_t>(), st));
     int64_t nnz = 0;
     SBD_HIP(hipMemcpyAsync(&nnz, rp.as<int64_t>() + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     SBD_HIP(hipStreamSynchronize(st));

@@ -105,24 +105,29 @@ int sbd_full_build_basis(int norb, int n_alpha, int n_beta, const uint64_t* dets
     B->n_el[1] = n_beta;
     int64_t P = 1;
     while (P < ndet) P <<= 1;
-    DevBuf work, cnt, scan;
+    DevBuf work, cnt, scan, tmp, uniq;
     hipError_t e = work.alloc(16 * (size_t)P);
     if (e == hipSuccess) e = cnt.alloc(sizeof(int64_t));
     if (e == hipSuccess) e = B->dets.alloc(16 * (size_t)ndet);
+    // scan scratch, sized for the longest scan below (the determinants given)
+    if (e == hipSuccess) e = tmp.alloc(sizeof(int64_t) * (size_t)scan_tmp_words(ndet));
+    if (e == hipSuccess) e = uniq.alloc(sizeof(int64_t) * (size_t)(2 * ndet + 1 + scan_tmp_words(ndet)));
     if (e == hipSuccess) e = hipMemcpyAsync(work.p, dets, 16 * (size_t)ndet, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_full_sort_unique(work.p, ndet, B->dets.p, cnt.as<int64_t>(), st);
+    if (e == hipSuccess)
+        e = launch_full_sort_unique(work.p, ndet, B->dets.p, cnt.as<int64_t>(), uniq.as<int64_t>(), st);
     int64_t n = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&n, cnt.p, sizeof(int64_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "sbd_full_build_basis (sort)");
     B->n = n;
     work.release();
+    uniq.release();
     // groups of equal alpha strings
     DevBuf flag;
     e = flag.alloc(sizeof(int64_t) * n);
     if (e == hipSuccess) e = scan.alloc(sizeof(int64_t) * (n + 1));
     if (e == hipSuccess) e = launch_full_group_flags(B->dets.p, n, flag.as<int64_t>(), st);
-    if (e == hipSuccess) e = launch_exclusive_scan(flag.as<int64_t>(), n, scan.as<int64_t>(), st);
+    if (e == hipSuccess) e = launch_exclusive_scan(flag.as<int64_t>(), n, scan.as<int64_t>(), tmp.as<int64_t>(), st);
     int64_t ng = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&ng, scan.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -140,7 +145,7 @@ int sbd_full_build_basis(int norb, int n_alpha, int n_beta, const uint64_t* dets
     if (e == hipSuccess) e = B->gn_rp.alloc(sizeof(int64_t) * (ng + 1));
     if (e == hipSuccess)
         e = launch_full_group_nbr(B->ua.as<uint64_t>(), ng, gcnt.as<int64_t>(), nullptr, nullptr, nullptr, st);
-    if (e == hipSuccess) e = launch_exclusive_scan(gcnt.as<int64_t>(), ng, B->gn_rp.as<int64_t>(), st);
+    if (e == hipSuccess) e = launch_exclusive_scan(gcnt.as<int64_t>(), ng, B->gn_rp.as<int64_t>(), tmp.as<int64_t>(), st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&B->gnnz, B->gn_rp.as<int64_t>() + ng, sizeof(int64_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -156,7 +161,7 @@ int sbd_full_build_basis(int norb, int n_alpha, int n_beta, const uint64_t* dets
         e = launch_full_conn(B->dets.p, n, B->grp.as<int32_t>(), B->goff.as<int64_t>(), B->gn_rp.as<int64_t>(),
                              B->gn_j.as<int32_t>(), B->gn_d.as<int8_t>(), flag.as<int64_t>(), nullptr, nullptr,
                              nullptr, st);
-    if (e == hipSuccess) e = launch_exclusive_scan(flag.as<int64_t>(), n, B->rp.as<int64_t>(), st);
+    if (e == hipSuccess) e = launch_exclusive_scan(flag.as<int64_t>(), n, B->rp.as<int64_t>(), tmp.as<int64_t>(), st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&B->nconn, B->rp.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -209,7 +209,11 @@ hipError_t launch_sort_unique(uint64_t* d_work, int64_t n, uint64_t* d_out, int6
 // Excitation tables.
 hipError_t launch_exc_count(const uint64_t* d_s, int64_t n, int64_t* d_cnt1, int64_t* d_cnt2,
                             hipStream_t st);
-hipError_t launch_exclusive_scan(const int64_t* d_in, int64_t n, int64_t* d_out /*n+1*/,
+// d_out[0] = 0, d_out[i + 1] = d_in[0] + ... + d_in[i] (n + 1 words, not in place).
+// d_tmp: scan_tmp_words(n) words of device scratch for the multi-workgroup
+// form, or null (one workgroup; slow for long inputs).
+int64_t scan_tmp_words(int64_t n);
+hipError_t launch_exclusive_scan(const int64_t* d_in, int64_t n, int64_t* d_out /*n+1*/, int64_t* d_tmp,
                                  hipStream_t st);
 hipError_t launch_exc_fill(const uint64_t* d_s, int64_t n, const int64_t* rp1, const int64_t* rp2,
                            int32_t* J1, uint32_t* orb1, int8_t* sg1, int32_t* J2, uint32_t* orb2,
@@ -310,8 +314,10 @@ hipError_t launch_sigma(const SigmaArgs<T>& A, int nvec, const T* c, T* y, int l
 // Full-bitstring determinant lists (k_full.hip).  A determinant is two words
 // {alpha string, beta string}; lists are sorted by (alpha, beta) ascending.
 // Sort and dedupe n determinants in `work` (device, capacity pow2(n)); unique
-// ones to `out`, their count to d_count (device int64).
-hipError_t launch_full_sort_unique(void* work, int64_t n, void* out, int64_t* d_count, hipStream_t st);
+// ones to `out`, their count to d_count (device int64); scratch: 2 n + 1 +
+// scan_tmp_words(n) device words.
+hipError_t launch_full_sort_unique(void* work, int64_t n, void* out, int64_t* d_count, int64_t* scratch,
+                                   hipStream_t st);
 // flag[i] = 1 where determinant i starts a group of equal alpha strings
 hipError_t launch_full_group_flags(const void* dets, int64_t n, int64_t* flag, hipStream_t st);
 // from gpos (gpos[i+1] = group starts in [0, i]): group alpha strings ua, group

@@ -84,36 +84,18 @@ __global__ void __launch_bounds__(kTile) k_det_bitonic_local(Det* a, int64_t k, 
     a[base + t] = s[t];
 }
 
-// exclusive scan of one int64 per thread over the block (blockDim == 1024)
-__device__ int64_t block_scan(int64_t v, int64_t* sh, int64_t* total) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-        const int64_t add = (t >= off) ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += add;
-        __syncthreads();
-    }
-    const int64_t incl = sh[t];
-    *total = sh[blockDim.x - 1];
-    __syncthreads();
-    return incl - v;
+// unique compaction of the sorted list (first n entries real): flags of the
+// first entry of each run of equal determinants, then a scatter to the scanned
+// positions; the count is pos[n]
+__global__ void k_det_flags(const Det* a, int64_t n, int64_t* flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = (i == 0 || det_ne(a[i], a[i - 1])) ? 1 : 0;
 }
 
-// unique compaction of the sorted list (first n entries real), one workgroup
-__global__ void __launch_bounds__(1024) k_det_unique(const Det* a, int64_t n, Det* out, int64_t* count) {
-    __shared__ int64_t sh[1024];
-    int64_t carry = 0;
-    for (int64_t base = 0; base < n; base += blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        const int64_t f = (i < n && (i == 0 || det_ne(a[i], a[i - 1]))) ? 1 : 0;
-        int64_t tot;
-        const int64_t pos = block_scan(f, sh, &tot);
-        if (f) out[carry + pos] = a[i];
-        carry += tot;
-    }
-    if (threadIdx.x == 0) *count = carry;
+__global__ void k_det_scatter(const Det* a, int64_t n, const int64_t* pos, Det* out, int64_t* count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && pos[i + 1] != pos[i]) out[pos[i]] = a[i];
+    if (i == 0) *count = pos[n];
 }
 
 // ------------------------------------------------------------------ alpha groups
@@ -468,7 +450,8 @@ hipError_t launch_full_map(const void* from, int64_t nf, const void* to, int64_t
                            nf, static_cast<const Det*>(to), nt, nvec, xf, xt);
     return hipGetLastError();
 }
-hipError_t launch_full_sort_unique(void* work, int64_t n, void* out, int64_t* d_count, hipStream_t st) {
+hipError_t launch_full_sort_unique(void* work, int64_t n, void* out, int64_t* d_count, int64_t* scratch,
+                                   hipStream_t st) {
     Det* a = static_cast<Det*>(work);
     int64_t P = 1;
     while (P < n) P <<= 1;
@@ -481,7 +464,12 @@ hipError_t launch_full_sort_unique(void* work, int64_t n, void* out, int64_t* d_
             hipLaunchKernelGGL(k_det_bitonic_global, dim3(blocks_for(P, 256)), dim3(256), 0, st, a, P, k, j);
         hipLaunchKernelGGL(k_det_bitonic_local, dim3(tiles), dim3(T), 0, st, a, k, j, T);
     }
-    hipLaunchKernelGGL(k_det_unique, dim3(1), dim3(1024), 0, st, a, n, static_cast<Det*>(out), d_count);
+    int64_t *flag = scratch, *pos = scratch + n, *tmp = scratch + 2 * n + 1;
+    hipLaunchKernelGGL(k_det_flags, dim3(blocks_for(n, 256)), dim3(256), 0, st, a, n, flag);
+    hipError_t e = launch_exclusive_scan(flag, n, pos, tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_det_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, a, n, pos,
+                       static_cast<Det*>(out), d_count);
     return hipGetLastError();
 }
 

@@ -118,6 +118,41 @@ __global__ void __launch_bounds__(1024) k_scan_single(const int64_t* in, int64_t
     }
 }
 
+// Multi-workgroup form of the same scan for long inputs: chunk sums, a scan of
+// the chunk sums, then each chunk scanned again from its offset.
+constexpr int kScanPer = 4;
+constexpr int64_t kScanChunk = 1024 * kScanPer;  // elements per workgroup
+
+__global__ void __launch_bounds__(1024) k_scan_part(const int64_t* in, int64_t n, int64_t* part) {
+    __shared__ int64_t sh[1024];
+    const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+    int64_t s = 0;
+    for (int q = 0; q < kScanPer; ++q) s += (i0 + q < n) ? in[i0 + q] : 0;
+    int64_t tot;
+    block_exclusive_scan(s, sh, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// out[i + 1] = off[chunk] + inclusive sum of in over the chunk up to i
+__global__ void __launch_bounds__(1024) k_scan_apply(const int64_t* in, int64_t n, const int64_t* off,
+                                                     int64_t* out) {
+    __shared__ int64_t sh[1024];
+    const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+    int64_t v[kScanPer];
+    int64_t s = 0;
+    for (int q = 0; q < kScanPer; ++q) {
+        v[q] = (i0 + q < n) ? in[i0 + q] : 0;
+        s += v[q];
+    }
+    int64_t tot;
+    int64_t run = off[blockIdx.x] + block_exclusive_scan(s, sh, &tot);
+    for (int q = 0; q < kScanPer; ++q) {
+        run += v[q];
+        if (i0 + q < n) out[i0 + q + 1] = run;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
+}
+
 constexpr int kExcWaves = 8;        // bra strings per workgroup
 constexpr int kExcChunk = 2048;     // ket strings staged in LDS per pass
 
@@ -308,9 +343,22 @@ hipError_t launch_exc_count(const uint64_t* d_s, int64_t n, int64_t* c1, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_exclusive_scan(const int64_t* d_in, int64_t n, int64_t* d_out,
+int64_t scan_tmp_words(int64_t n) {
+    const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+    return 2 * nb + 1;
+}
+
+hipError_t launch_exclusive_scan(const int64_t* d_in, int64_t n, int64_t* d_out, int64_t* d_tmp,
                                  hipStream_t st) {
-    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, d_in, n, d_out);
+    if (!d_tmp || n <= 4 * kScanChunk) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, d_in, n, d_out);
+        return hipGetLastError();
+    }
+    const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+    int64_t *part = d_tmp, *off = d_tmp + nb;  // nb chunk sums, nb + 1 offsets
+    hipLaunchKernelGGL(k_scan_part, dim3((unsigned)nb), dim3(1024), 0, st, d_in, n, part);
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, part, nb, off);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(1024), 0, st, d_in, n, off, d_out);
     return hipGetLastError();
 }
 

@@ -44,6 +44,8 @@ def test_stats_summary_orders_and_filters(tmp_path):
     assert t[2].startswith("| `k_stream<double,1,2,1>` | 2 | 1.00 | 500.0 | 50.0 |")
     t = bench.stats_summary(str(p), prefix="k_dl").splitlines()
     assert len(t) == 4 and "k_dl_ritz" in t[2] and "k_dl_sub<3>" in t[3]
+    t = bench.stats_summary(str(p), prefix="k_stream,k_dl_sub").splitlines()
+    assert len(t) == 4 and "k_stream" in t[2] and "k_dl_sub<3>" in t[3]
 
 
 def test_counters_summary_rates(tmp_path):

@@ -76,6 +76,24 @@ def test_full_basis_and_connections_bitexact(case):
     assert B.nalpha == np.unique(S.dets[:, 0]).size
 
 
+@pytest.mark.parametrize("ndet", [16384, 16385, 20480, 24577])
+def test_full_scan_chunk_boundaries(ndet):
+    """Lists whose lengths sit at the chunk boundaries of the multi-workgroup
+    scan (4096 entries per workgroup, one workgroup up to 16384): the unique
+    compaction (with duplicates given), the alpha groups and the connection
+    row pointers stay bit-exact against the oracle."""
+    W = wl.make_full_config("full16", ndet=ndet, nstr=400)
+    rng = np.random.default_rng(ndet)
+    given = np.concatenate([W.dets, W.dets[rng.integers(0, ndet, 4099)]])[rng.permutation(ndet + 4099)]
+    B = sbd.FullBasis(W.norb, W.n_alpha, W.n_beta, given)
+    S = oracle.FullOracleSystem(W.norb, W.dets, W.h, W.eri, W.e_core)
+    d, rp, J, deg = B.export()
+    assert B.N == S.N == ndet
+    assert np.array_equal(d, S.dets) and np.array_equal(rp, S.row_ptr)
+    assert np.array_equal(J, S.J) and np.array_equal(deg, S.deg)
+    assert B.nalpha == np.unique(S.dets[:, 0]).size
+
+
 @pytest.mark.parametrize("case", LISTS, ids=IDS)
 def test_full_diag_and_sigma_fp64(case):
     name, norb, na, nb, dets, h, eri, ec = case
