@@ -156,9 +156,12 @@ int sbd_full_build_basis(int norb, int n_alpha, int n_beta, const uint64_t* dets
         e = launch_full_group_nbr(B->ua.as<uint64_t>(), ng, nullptr, B->gn_rp.as<int64_t>(), B->gn_j.as<int32_t>(),
                                   B->gn_d.as<int8_t>(), st);
     // connections of every determinant
+    DevBuf bw;
+    if (e == hipSuccess) e = bw.alloc(sizeof(uint64_t) * n);
+    if (e == hipSuccess) e = launch_full_beta(B->dets.p, n, bw.as<uint64_t>(), st);
     if (e == hipSuccess) e = B->rp.alloc(sizeof(int64_t) * (n + 1));
     if (e == hipSuccess)
-        e = launch_full_conn(B->dets.p, n, B->grp.as<int32_t>(), B->goff.as<int64_t>(), B->gn_rp.as<int64_t>(),
+        e = launch_full_conn(bw.as<uint64_t>(), n, B->grp.as<int32_t>(), B->goff.as<int64_t>(), B->gn_rp.as<int64_t>(),
                              B->gn_j.as<int32_t>(), B->gn_d.as<int8_t>(), flag.as<int64_t>(), nullptr, nullptr,
                              nullptr, st);
     if (e == hipSuccess) e = launch_exclusive_scan(flag.as<int64_t>(), n, B->rp.as<int64_t>(), tmp.as<int64_t>(), st);
@@ -169,7 +172,7 @@ int sbd_full_build_basis(int norb, int n_alpha, int n_beta, const uint64_t* dets
     e = B->J.alloc(sizeof(int32_t) * std::max<int64_t>(B->nconn, 1));
     if (e == hipSuccess) e = B->deg.alloc(std::max<int64_t>(B->nconn, 1));
     if (e == hipSuccess)
-        e = launch_full_conn(B->dets.p, n, B->grp.as<int32_t>(), B->goff.as<int64_t>(), B->gn_rp.as<int64_t>(),
+        e = launch_full_conn(bw.as<uint64_t>(), n, B->grp.as<int32_t>(), B->goff.as<int64_t>(), B->gn_rp.as<int64_t>(),
                              B->gn_j.as<int32_t>(), B->gn_d.as<int8_t>(), nullptr, B->rp.as<int64_t>(),
                              B->J.as<int32_t>(), B->deg.as<int8_t>(), st);
     B->host.resize(2 * (size_t)n);

@@ -328,9 +328,12 @@ hipError_t launch_full_group_fill(const void* dets, int64_t n, const int64_t* gp
 // counts when rp is null, else neighbour group gj and alpha degree gd per row
 hipError_t launch_full_group_nbr(const uint64_t* ua, int64_t ng, int64_t* cnt, const int64_t* rp, int32_t* gj,
                                  int8_t* gd, hipStream_t st);
-// connections (one or two electrons moved) of every determinant: counts when
-// rp is null, else ket J and electrons moved deg, rows sorted by J
-hipError_t launch_full_conn(const void* dets, int64_t n, const int32_t* grp, const int64_t* goff,
+// bw[i] = beta word of determinant i (n words)
+hipError_t launch_full_beta(const void* dets, int64_t n, uint64_t* bw, hipStream_t st);
+// connections (one or two electrons moved) of every determinant, from the beta
+// words bw and the alpha groups: counts when rp is null, else ket J and
+// electrons moved deg, rows sorted by J
+hipError_t launch_full_conn(const uint64_t* bw, int64_t n, const int32_t* grp, const int64_t* goff,
                             const int64_t* gn_rp, const int32_t* gn_j, const int8_t* gn_d, int64_t* cnt,
                             const int64_t* rp, int32_t* J, int8_t* deg, hipStream_t st);
 // integral tables: jt/kt norb^3 ((ai|kk), (ak|ki)), jd/kd norb^2 ((pp|qq), (pq|qp)),

@@ -170,6 +170,12 @@ __global__ void __launch_bounds__(kWaves * 64) k_group_nbr(const uint64_t* __res
     }
 }
 
+// beta words of the sorted list, contiguous (the connection passes read only these)
+__global__ void k_det_beta(const Det* __restrict__ d, int64_t n, uint64_t* __restrict__ bw) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) bw[i] = d[i].b;
+}
+
 // Connections of each determinant: count pass and fill pass (ket index and
 // electrons moved, 1 or 2), rows sorted by ket.  The neighbour groups are taken
 // 64 at a time, in ascending order.  A group whose alpha string is two electrons
@@ -179,7 +185,7 @@ __global__ void __launch_bounds__(kWaves * 64) k_group_nbr(const uint64_t* __res
 // are scanned by the whole wavefront, one group after another, so hits are
 // placed in ascending ket order by a wave ballot.
 template <bool FILL>
-__global__ void __launch_bounds__(kWaves * 64) k_conn(const Det* __restrict__ d, int64_t n,
+__global__ void __launch_bounds__(kWaves * 64) k_conn(const uint64_t* __restrict__ bw, int64_t n,
                                                       const int32_t* __restrict__ grp,
                                                       const int64_t* __restrict__ goff,
                                                       const int64_t* __restrict__ gn_rp,
@@ -190,7 +196,7 @@ __global__ void __launch_bounds__(kWaves * 64) k_conn(const Det* __restrict__ d,
     const int64_t I = (int64_t)blockIdx.x * kWaves + w;
     if (I >= n) return;  // wave-uniform
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t ib = d[I].b;
+    const uint64_t ib = bw[I];
     const int g = grp[I];
     int64_t o = FILL ? rp[I] : 0;
     int c = 0;
@@ -205,10 +211,10 @@ __global__ void __launch_bounds__(kWaves * 64) k_conn(const Det* __restrict__ d,
             int64_t lo = goff[h], hi = end;  // first member with beta string >= ib
             while (lo < hi) {
                 const int64_t mid = lo + ((hi - lo) >> 1);
-                if (d[mid].b < ib) lo = mid + 1;
+                if (bw[mid] < ib) lo = mid + 1;
                 else hi = mid;
             }
-            if (lo < end && d[lo].b == ib) hitK = (int)lo;
+            if (lo < end && bw[lo] == ib) hitK = (int)lo;
         }
         if (!FILL) c += hitK >= 0;
         const uint64_t dmask = __ballot(dbl), hmask = __ballot(hitK >= 0);
@@ -231,7 +237,7 @@ __global__ void __launch_bounds__(kWaves * 64) k_conn(const Det* __restrict__ d,
             for (int64_t t0 = k0; t0 < k1; t0 += 64) {
                 const int64_t K = t0 + lane;
                 const bool ok = K < k1;
-                const int tot = pa + (ok ? __popcll(ib ^ d[K].b) : 0);
+                const int tot = pa + (ok ? __popcll(ib ^ bw[K]) : 0);
                 const bool hit = ok && (tot == 2 || tot == 4);
                 if (FILL) {
                     const uint64_t hm = __ballot(hit);
@@ -500,16 +506,22 @@ hipError_t launch_full_group_nbr(const uint64_t* ua, int64_t ng, int64_t* cnt, c
     return hipGetLastError();
 }
 
-hipError_t launch_full_conn(const void* dets, int64_t n, const int32_t* grp, const int64_t* goff,
+hipError_t launch_full_beta(const void* dets, int64_t n, uint64_t* bw, hipStream_t st) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_det_beta, dim3(blocks_for(n, 256)), dim3(256), 0, st, static_cast<const Det*>(dets), n,
+                           bw);
+    return hipGetLastError();
+}
+
+hipError_t launch_full_conn(const uint64_t* bw, int64_t n, const int32_t* grp, const int64_t* goff,
                             const int64_t* gn_rp, const int32_t* gn_j, const int8_t* gn_d, int64_t* cnt,
                             const int64_t* rp, int32_t* J, int8_t* deg, hipStream_t st) {
     if (n <= 0) return hipGetLastError();
-    const Det* d = static_cast<const Det*>(dets);
     if (rp)
-        hipLaunchKernelGGL(k_conn<true>, dim3(blocks_for(n, kWaves)), dim3(kWaves * 64), 0, st, d, n, grp, goff,
+        hipLaunchKernelGGL(k_conn<true>, dim3(blocks_for(n, kWaves)), dim3(kWaves * 64), 0, st, bw, n, grp, goff,
                            gn_rp, gn_j, gn_d, cnt, rp, J, deg);
     else
-        hipLaunchKernelGGL(k_conn<false>, dim3(blocks_for(n, kWaves)), dim3(kWaves * 64), 0, st, d, n, grp, goff,
+        hipLaunchKernelGGL(k_conn<false>, dim3(blocks_for(n, kWaves)), dim3(kWaves * 64), 0, st, bw, n, grp, goff,
                            gn_rp, gn_j, gn_d, cnt, rp, J, deg);
     return hipGetLastError();
 }
