@@ -275,6 +275,18 @@ def sample_configurations(norb: int, n_alpha: int, n_beta: int, count: int, seed
     return out
 
 
+def add_readout_noise(samples: np.ndarray, norb: int, p_flip: float, seed: int) -> np.ndarray:
+    """Sampled configurations with every bit below norb of both words flipped
+    independently with probability p_flip: a stand-in for a noisy device's
+    records, whose strings can carry the wrong number of electrons."""
+    rng = np.random.default_rng(seed)
+    out = np.array(samples, dtype=np.uint64, copy=True).reshape(-1, 2)
+    flips = rng.random((out.shape[0], 2, norb)) < p_flip
+    weights = (np.uint64(1) << np.arange(norb, dtype=np.uint64))
+    mask = (flips * weights).sum(axis=2, dtype=np.uint64)
+    return out ^ mask
+
+
 @dataclass
 class FullWorkload:
     """A full-bitstring workload: an explicit determinant list."""
