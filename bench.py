@@ -397,7 +397,9 @@ def sqd_leg(sbd, wl, stream, steps=(2500, 5000, 7500, 10000)):
     norb 26 with 7 + 7 electrons (the sel26 integrals), configurations drawn
     with level weights, taken in growing prefixes; each step diagonalises over
     the product of the distinct sampled strings (up to 1e8 determinants) in
-    the chosen form, cold and warm (previous eigenvector carried over)."""
+    the chosen form, cold and warm (previous eigenvector carried over); the
+    same record with bit-flip noise and sample recovery; and full-bitstring
+    steps over the full16 list."""
     import torch
     W = wl.make_config("sel26", nstr=10)
     smp = wl.sample_configurations(W.norb, W.n_alpha, W.n_beta, max(steps), 3101)
@@ -417,6 +419,22 @@ def sqd_leg(sbd, wl, stream, steps=(2500, 5000, 7500, 10000)):
                                      setup_ms=r["setup_ms"], solve_ms=r["solve_ms"], status=r["status"])
                                 for r in rep])
     out["energy_max_diff"] = float(max(abs(a - b) for a, b in zip(out["cold"]["energies"], out["warm"]["energies"])))
+    # the same record read out with bit-flip noise (each bit flipped with probability 0.003, so
+    # about 7 % of the strings of each spin carry a wrong electron count), with recovery: wrong
+    # samples dropped at the first step and corrected from the previous ground state after it
+    noisy = wl.add_readout_noise(smp, W.norb, 0.003, 3103)
+    rkw = dict(kw, recovery=True, recovery_seed=3104)
+    sbd.sqd_run(W.norb, W.n_alpha, W.n_beta, W.h, W.eri, W.e_core, noisy, steps, stream=stream, **rkw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e, rep = sbd.sqd_run(W.norb, W.n_alpha, W.n_beta, W.h, W.eri, W.e_core, noisy, steps, stream=stream, **rkw)
+    torch.cuda.synchronize()
+    out["recovery_warm"] = dict(workload="sel26 record with bit-flip noise 0.003, recovery",
+                                ms=1e3 * (time.perf_counter() - t0), energies=[float(x) for x in e[:, 0]],
+                                steps=[dict(samples=r["samples"], corrected=r["corrected"], dropped=r["dropped"],
+                                            strings=[r["n_alpha_str"], r["n_beta_str"]], determinants=r["ndet"],
+                                            iterations=r["iterations"], setup_ms=r["setup_ms"],
+                                            solve_ms=r["solve_ms"], status=r["status"]) for r in rep])
     # full-bitstring steps: the basis of a step is the set of sampled determinants.  The record
     # is the full16 determinant list (drawn from the sel16 string product with level weights,
     # connected like a selected basis) in a random drawing order, taken in growing prefixes.
@@ -924,6 +942,10 @@ def main():
             log(f"[bench] sqd loop {name}: {q[name]['ms']:.0f} ms, steps "
                 f"{[(x['determinants'], x['iterations'], round(x['solve_ms'], 1)) for x in q[name]['steps']]}, "
                 f"energies {[round(x, 6) for x in q[name]['energies']]}")
+        rq = q["recovery_warm"]
+        log(f"[bench] sqd loop with recovery: {rq['ms']:.0f} ms, steps "
+            f"{[(x['corrected'], x['dropped'], x['determinants'], x['iterations'], round(x['solve_ms'], 1)) for x in rq['steps']]}, "
+            f"energies {[round(x, 6) for x in rq['energies']]}")
         fq = q["full_bitstring_warm"]
         log(f"[bench] sqd loop full bitstring: {fq['ms']:.0f} ms, steps "
             f"{[(x['determinants'], x['iterations'], round(x['solve_ms'], 1)) for x in fq['steps']]}, "

@@ -382,7 +382,12 @@ int sbd_davidson(const sbd_basis* b, const sbd_exc* e, const sbd_ham* h, int nro
  * energies: host, nsteps x nroots (roots beyond a step's N are 0).  steps
  * (nullable): host array of nsteps reports.  step_samples must be
  * non-decreasing, so the bases are nested and the lowest energy cannot rise
- * from one step to the next (variational principle).
+ * from one step to the next (variational principle).  With recovery, the
+ * samples of a step are first filtered (Sec. I: the sampled configurations are
+ * filtered before the subspace is formed) by sbd_recover_configurations: at
+ * the first step samples with a wrong electron count are dropped, at later
+ * steps they are corrected from the occupations (sbd_occupations) of the
+ * previous step's lowest root; the bases are then no longer nested.
  * Errors: SBD_ERR_ARG, SBD_ERR_INTEGRALS, those of the calls it makes.
  */
 typedef struct {
@@ -395,6 +400,9 @@ typedef struct {
                                     sbd_full_map_vectors); the step report's n_alpha_str is
                                     then the number of distinct alpha strings and
                                     n_beta_str 0.  Not with spin_union. */
+    int recovery;                /* default 0.  1: filter and correct the samples of every
+                                    step (see above); product bases only */
+    uint64_t recovery_seed;      /* default 0: seed of the recovery's uniforms */
 } sbd_sqd_opts;
 typedef struct {
     int status;                  /* sbd_davidson status of the step (0 or SBD_NOT_CONVERGED) */
@@ -404,8 +412,41 @@ typedef struct {
     int iterations, sigma_calls;
     double residual;             /* largest final residual norm */
     double setup_ms, solve_ms;   /* basis, tables, Hamiltonian (+ transfer); Davidson */
+    int64_t corrected, dropped;  /* with recovery: samples corrected, samples dropped */
 } sbd_sqd_step;
 void sbd_sqd_default_opts(sbd_sqd_opts* o);
+
+/*
+ * Average occupation of every spin-orbital in a vector over a product basis
+ * (the input of the sample recovery below): occ[p] = sum_I |c_I|^2 [alpha
+ * orbital p occupied in I] / sum_I |c_I|^2, occ[norb + p] the same for beta.
+ * vec: device, N = n_alpha_str * n_beta_str doubles (index ia * nb + ib);
+ * occ: host, 2 * norb doubles.  Fixed reduction order (reproducible).
+ * Synchronises the stream.  Errors: SBD_ERR_ARG, SBD_ERR_NOMEM, SBD_ERR_HIP.
+ */
+int sbd_occupations(const sbd_basis* b, const double* vec, double* occ, void* stream);
+
+/*
+ * Filtering of sampled configurations before an SQD solve (Sec. I).  samples:
+ * host, 2 * nsamples words (alpha string, beta string).  Samples with the
+ * right electron counts are copied to out unchanged.  Without occupations
+ * (occ null) the others are dropped; with occ (2 * norb values, as
+ * sbd_occupations writes them) each wrong spin string is corrected: with w
+ * electrons instead of n, |w - n| orbitals are drawn one after another
+ * without replacement among the occupied (w > n) or empty (w < n) ones, with
+ * probability proportional to the weight of y = |x_p - occ_p| (x_p the
+ * sampled bit): delta * y / h for y <= h, delta + (1 - delta)(y - h) / (1 - h)
+ * above, h = n / norb, delta = 0.01; and flipped.  Uniform j of sample i, spin
+ * s (0 alpha, 1 beta) is the top 53 bits of SplitMix64(seed + (2 i + s) 64 +
+ * j) times 2^-53; the orbital is the first, in increasing order, whose
+ * cumulative weight exceeds u times the total.  out: host, room for 2 *
+ * nsamples words, filled in sample order; *n_out samples written,
+ * *n_corrected (nullable) of them corrected.  Host only, no device work.
+ * Errors: SBD_ERR_ARG, SBD_ERR_NORB, SBD_ERR_STRING (a bit at or above norb).
+ */
+int sbd_recover_configurations(int norb, int n_alpha, int n_beta, const uint64_t* samples, int64_t nsamples,
+                               const double* occ, uint64_t seed, uint64_t* out, int64_t* n_out,
+                               int64_t* n_corrected);
 int sbd_sqd_run(int norb, int n_alpha, int n_beta, const double* h1, const double* eri, double e_core,
                 const uint64_t* samples, int64_t nsamples, const int64_t* step_samples, int nsteps,
                 int nroots, const sbd_sqd_opts* opts, double* energies, sbd_sqd_step* steps, void* stream);

@@ -37,7 +37,7 @@ EXPORTED = ["sbd_last_error", "sbd_version", "sbd_source_hash", "sbd_release_cac
             "sbd_full_set_hamiltonian", "sbd_full_ham_diag", "sbd_free_full_ham", "sbd_full_sigma",
             "sbd_full_davidson", "sbd_full_map_vectors", "sbd_full_assemble", "sbd_full_release_assembled",
             "sbd_full_assembled",
-            "sbd_sqd_default_opts", "sbd_sqd_run"]
+            "sbd_sqd_default_opts", "sbd_sqd_run", "sbd_occupations", "sbd_recover_configurations"]
 
 
 class SBDError(RuntimeError):
@@ -86,14 +86,15 @@ class DavidsonReport(ctypes.Structure):
 
 class SqdOpts(ctypes.Structure):
     _fields_ = [("davidson", DavidsonOpts), ("warm_start", ctypes.c_int), ("spin_union", ctypes.c_int),
-                ("full_bitstring", ctypes.c_int)]
+                ("full_bitstring", ctypes.c_int), ("recovery", ctypes.c_int), ("recovery_seed", ctypes.c_uint64)]
 
 
 class SqdStep(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("warm", ctypes.c_int), ("samples", ctypes.c_int64),
                 ("n_alpha_str", ctypes.c_int64), ("n_beta_str", ctypes.c_int64), ("ndet", ctypes.c_int64),
                 ("iterations", ctypes.c_int), ("sigma_calls", ctypes.c_int), ("residual", ctypes.c_double),
-                ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+                ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("corrected", ctypes.c_int64), ("dropped", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -410,6 +411,30 @@ def map_vectors(basis_from: "Basis", basis_to: "Basis", x_from, x_to, nvec: int 
                                  _stream(stream)))
 
 
+def occupations(basis: "Basis", vec, stream=None) -> tuple:
+    """Spin-orbital occupations of an FP64 device vector over a product basis
+    (sbd_occupations): (alpha occupations, beta occupations), norb each."""
+    occ = np.zeros(2 * basis.norb, dtype=np.float64)
+    check(load().sbd_occupations(basis._h, _dptr(vec), _host(occ), _stream(stream)))
+    return occ[:basis.norb].copy(), occ[basis.norb:].copy()
+
+
+def recover_configurations(norb, n_alpha, n_beta, samples, occ_alpha=None, occ_beta=None, seed: int = 0):
+    """Samples (rows: alpha string, beta string) filtered and corrected
+    (sbd_recover_configurations); returns (samples out, number corrected)."""
+    smp = np.ascontiguousarray(np.asarray(samples, dtype=np.uint64).reshape(-1, 2))
+    out = np.zeros_like(smp)
+    occ = None
+    if occ_alpha is not None:
+        occ = np.ascontiguousarray(np.concatenate([np.asarray(occ_alpha, dtype=np.float64),
+                                                   np.asarray(occ_beta, dtype=np.float64)]))
+    n_out, n_corr = ctypes.c_int64(), ctypes.c_int64()
+    check(load().sbd_recover_configurations(int(norb), int(n_alpha), int(n_beta), _host(smp), smp.shape[0],
+                                            _host(occ) if occ is not None else None, ctypes.c_uint64(int(seed)),
+                                            _host(out), ctypes.byref(n_out), ctypes.byref(n_corr)))
+    return out[:n_out.value].copy(), n_corr.value
+
+
 def gram(A, ma: int, X, k: int, N: int, stream=None) -> np.ndarray:
     """A^T X for device row blocks (sbd_gram): returns an (ma, k) host array."""
     out = np.zeros((ma, k), dtype=np.float64)
@@ -548,10 +573,12 @@ def full_map_vectors(basis_from: "FullBasis", basis_to: "FullBasis", x_from, x_t
 
 
 def sqd_run(norb, n_alpha, n_beta, h1, eri, e_core, samples, step_samples, nroots: int = 1,
-            warm_start: bool = True, spin_union: bool = False, full_bitstring: bool = False, stream=None, **kw):
+            warm_start: bool = True, spin_union: bool = False, full_bitstring: bool = False,
+            recovery: bool = False, recovery_seed: int = 0, stream=None, **kw):
     """Successive solves on a growing set of sampled configurations
     (sbd_sqd_run): step s uses the first step_samples[s] rows of ``samples``
-    (alpha string, beta string).  Keyword options are DavidsonOpts fields.
+    (alpha string, beta string), filtered and corrected first with
+    ``recovery``.  Keyword options are DavidsonOpts fields.
     Returns (energies (nsteps, nroots), list of step reports)."""
     smp = np.ascontiguousarray(np.asarray(samples, dtype=np.uint64).reshape(-1, 2))
     steps_in = np.ascontiguousarray(step_samples, dtype=np.int64)
@@ -563,6 +590,7 @@ def sqd_run(norb, n_alpha, n_beta, h1, eri, e_core, samples, step_samples, nroot
     load().sbd_sqd_default_opts(ctypes.byref(o))
     o.warm_start, o.spin_union = int(bool(warm_start)), int(bool(spin_union))
     o.full_bitstring = int(bool(full_bitstring))
+    o.recovery, o.recovery_seed = int(bool(recovery)), int(recovery_seed)
     for k, v in kw.items():
         if not hasattr(o.davidson, k) or k == "guess":
             raise TypeError(f"unknown or unsupported option {k}")

@@ -469,6 +469,12 @@ hipError_t launch_string_map(const uint64_t* to, int64_t nto, const uint64_t* fr
 hipError_t launch_map_vectors(const int64_t* amap, const int64_t* bmap, int64_t na, int64_t nb, int64_t nb_from,
                               int64_t n_from, int nvec, const double* x, double* y, hipStream_t st);
 hipError_t launch_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
+// occ[spin * norb + p]: occupation of spin-orbital p in the vector c over the
+// product of the sorted strings sa (na) and sb (nb), c[ia * nb + ib];
+// scratch: occupation_scratch_words(na, nb) doubles
+int64_t occupation_scratch_words(int64_t na, int64_t nb);
+hipError_t launch_occupations(const double* c, const uint64_t* sa, int64_t na, const uint64_t* sb, int64_t nb,
+                              int norb, double* scratch, double* occ, hipStream_t st);
 hipError_t launch_f32_to_f64_axpy(const float* y32, const double* x, double shift, double* y,
                                   int64_t n, hipStream_t st);
 

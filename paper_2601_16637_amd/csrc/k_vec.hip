@@ -314,4 +314,103 @@ hipError_t launch_f32_to_f64_axpy(const float* y32, const double* x, double shif
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ occupations
+// Spin-orbital occupations of a vector over the alpha x beta product basis
+// (the input of the sample recovery of an SQD iteration): the squared entries
+// summed per row (alpha string) and per column (beta string), then for every
+// orbital the share of that weight on the strings that hold it.  Fixed
+// reduction orders, so the result does not depend on scheduling.
+namespace {
+
+constexpr int kOccRows = 128;  // rows per partial column sum (at least)
+
+__device__ double block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = kVB / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// wa[ia] = sum_ib c[ia, ib]^2: one workgroup per row
+__global__ void __launch_bounds__(kVB) k_row_sq(const double* __restrict__ c, int64_t nb, double* __restrict__ wa) {
+    __shared__ double sh[kVB];
+    const double* r = c + (int64_t)blockIdx.x * nb;
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < nb; j += kVB) s += r[j] * r[j];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) wa[blockIdx.x] = s;
+}
+
+// part[q * nb + ib] = sum of c[ia, ib]^2 over the rows of chunk q
+__global__ void __launch_bounds__(kVB) k_col_sq_part(const double* __restrict__ c, int64_t na, int64_t nb,
+                                                     int64_t rows, double* __restrict__ part) {
+    const int64_t ib = (int64_t)blockIdx.x * kVB + threadIdx.x;
+    if (ib >= nb) return;
+    const int64_t r0 = (int64_t)blockIdx.y * rows, r1 = r0 + rows < na ? r0 + rows : na;
+    double s = 0.0;
+    for (int64_t ia = r0; ia < r1; ++ia) {
+        const double v = c[ia * nb + ib];
+        s += v * v;
+    }
+    part[(int64_t)blockIdx.y * nb + ib] = s;
+}
+
+__global__ void __launch_bounds__(kVB) k_col_sq_sum(const double* __restrict__ part, int64_t nq, int64_t nb,
+                                                    double* __restrict__ wb) {
+    const int64_t ib = (int64_t)blockIdx.x * kVB + threadIdx.x;
+    if (ib >= nb) return;
+    double s = 0.0;
+    for (int64_t q = 0; q < nq; ++q) s += part[q * nb + ib];
+    wb[ib] = s;
+}
+
+// occ[spin * norb + p] = (sum of w over the strings holding p) / (sum of w):
+// one workgroup per (orbital, spin)
+__global__ void __launch_bounds__(kVB) k_orb_occ(const uint64_t* __restrict__ sa, const double* __restrict__ wa,
+                                                 int64_t na, const uint64_t* __restrict__ sb,
+                                                 const double* __restrict__ wb, int64_t nb, int norb,
+                                                 double* __restrict__ occ) {
+    __shared__ double sh[kVB];
+    const int p = blockIdx.x, spin = blockIdx.y;
+    const uint64_t* s = spin ? sb : sa;
+    const double* w = spin ? wb : wa;
+    const int64_t n = spin ? nb : na;
+    double tot = 0.0, hold = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kVB) {
+        tot += w[i];
+        if ((s[i] >> p) & 1ull) hold += w[i];
+    }
+    tot = block_sum(tot, sh);
+    hold = block_sum(hold, sh);
+    if (threadIdx.x == 0) occ[spin * norb + p] = tot > 0.0 ? hold / tot : 0.0;
+}
+
+}  // namespace
+
+int64_t occupation_scratch_words(int64_t na, int64_t nb) {
+    int64_t rows = kOccRows;
+    if ((na + rows - 1) / rows > 65535) rows = (na + 65534) / 65535;
+    const int64_t nq = (na + rows - 1) / rows;
+    return na + nb + nq * nb;
+}
+
+hipError_t launch_occupations(const double* c, const uint64_t* sa, int64_t na, const uint64_t* sb, int64_t nb,
+                              int norb, double* scratch, double* occ, hipStream_t st) {
+    int64_t rows = kOccRows;
+    if ((na + rows - 1) / rows > 65535) rows = (na + 65534) / 65535;
+    const int64_t nq = (na + rows - 1) / rows;
+    double *wa = scratch, *wb = scratch + na, *part = scratch + na + nb;
+    const unsigned cb = (unsigned)((nb + kVB - 1) / kVB);
+    hipLaunchKernelGGL(k_row_sq, dim3((unsigned)na), dim3(kVB), 0, st, c, nb, wa);
+    hipLaunchKernelGGL(k_col_sq_part, dim3(cb, (unsigned)nq), dim3(kVB), 0, st, c, na, nb, rows, part);
+    hipLaunchKernelGGL(k_col_sq_sum, dim3(cb), dim3(kVB), 0, st, part, nq, nb, wb);
+    hipLaunchKernelGGL(k_orb_occ, dim3((unsigned)norb, 2), dim3(kVB), 0, st, sa, wa, na, sb, wb, nb, norb, occ);
+    return hipGetLastError();
+}
+
 }  // namespace sbd

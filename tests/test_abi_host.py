@@ -92,7 +92,8 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("gcc not available")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     structs = {"sbd_davidson_opts": nat.DavidsonOpts, "sbd_davidson_report": nat.DavidsonReport,
-               "sbd_request": nat.Request, "sbd_result": nat.Result}
+               "sbd_request": nat.Request, "sbd_result": nat.Result, "sbd_sqd_opts": nat.SqdOpts,
+               "sbd_sqd_step": nat.SqdStep}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sbd.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -122,3 +122,91 @@ def test_sqd_full_bitstring_steps_match_dense(nroots):
     assert np.all(np.diff(e[:, 0]) <= 1e-10)
     with pytest.raises(sbd.SBDError):
         sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps, full_bitstring=True, spin_union=True)
+
+
+# ------------------------------------------------------------------ sample recovery
+from oracle import recovery as orec  # noqa: E402
+
+
+@pytest.mark.parametrize("norb,na,nb,p,seed", [(12, 5, 4, 0.03, 1), (10, 4, 4, 0.1, 2), (6, 0, 6, 0.2, 3),
+                                               (64, 9, 7, 0.01, 4), (16, 1, 15, 0.05, 5)])
+def test_recover_configurations_bitexact_vs_oracle(norb, na, nb, p, seed):
+    """sbd_recover_configurations against the oracle's recovery on the same
+    noisy samples, occupations and seed: identical samples, in order, and the
+    same count of corrected samples; without occupations the same samples
+    are dropped.  Includes empty and full spins (filling 0 and 1) and norb 64."""
+    smp = wl.sample_configurations(norb, na, nb, 2000, 700 + seed)
+    noisy = wl.add_readout_noise(smp, norb, p, 710 + seed)
+    rng = np.random.default_rng(720 + seed)
+    oa, ob = rng.random(norb), rng.random(norb)
+    oa[rng.random(norb) < 0.2] = 0.0
+    ob[rng.random(norb) < 0.2] = 1.0
+    for s in (0, 0xFFFFFFFFFFFFFFF0, 12345):
+        got, nc = sbd.recover_configurations(norb, na, nb, noisy, oa, ob, seed=s)
+        ref, nr = orec.recover(noisy, norb, na, nb, oa, ob, seed=s)
+        assert nc == nr and np.array_equal(got, ref)
+    got, nc = sbd.recover_configurations(norb, na, nb, noisy)
+    ref, nr = orec.recover(noisy, norb, na, nb)
+    assert nc == nr == 0 and np.array_equal(got, ref)
+
+
+def test_recover_configurations_rejects_bad_input():
+    ok = np.array([[0b0111, 0b0011]], dtype=np.uint64)
+    with pytest.raises(sbd.SBDError) as ei:
+        sbd.recover_configurations(4, 3, 2, np.array([[0b10111, 0b0011]], dtype=np.uint64))
+    assert ei.value.status == -3
+    with pytest.raises(sbd.SBDError) as ei:
+        sbd.recover_configurations(4, 3, 2, ok, np.full(4, np.nan), np.zeros(4))
+    assert ei.value.status == -1
+    with pytest.raises(sbd.SBDError):
+        sbd.recover_configurations(65, 3, 2, ok)
+    out, nc = sbd.recover_configurations(4, 3, 2, np.zeros((0, 2), dtype=np.uint64))
+    assert out.shape == (0, 2) and nc == 0
+
+
+@pytest.mark.parametrize("name,nstr", [("sel16", 120), ("fci8", None), ("block20", 90)])
+def test_occupations_vs_oracle(name, nstr):
+    """sbd_occupations against the oracle's occupations of the same vector
+    (1e-13), and exactly the bits of a determinant for a unit vector."""
+    W = wl.make_config(name, nstr=nstr)
+    B = sbd.Basis(W.norb, W.n_alpha, W.n_beta, W.alpha, W.beta)
+    A, Bs = np.sort(np.unique(W.alpha)), np.sort(np.unique(W.beta))
+    x = wl.random_vector(A.size * Bs.size, 33)[0]
+    ga, gb = sbd.occupations(B, torch.tensor(x, device="cuda"))
+    ra, rb = orec.occupations(W.norb, A, Bs, x)
+    assert np.abs(ga - ra).max() <= 1e-13 and np.abs(gb - rb).max() <= 1e-13
+    assert abs(ga.sum() - W.n_alpha) <= 1e-12 and abs(gb.sum() - W.n_beta) <= 1e-12
+    u = np.zeros_like(x)
+    i = x.size // 3
+    u[i] = 1.0
+    ga, gb = sbd.occupations(B, torch.tensor(u, device="cuda"))
+    ia, ib = divmod(i, Bs.size)
+    assert np.array_equal(ga, [(int(A[ia]) >> p) & 1 for p in range(W.norb)])
+    assert np.array_equal(gb, [(int(Bs[ib]) >> p) & 1 for p in range(W.norb)])
+
+
+def test_sqd_recovery_steps_match_oracle():
+    """SQD loop on noisy samples with recovery: at the first step the samples
+    with wrong electron counts are dropped, later they are corrected from the
+    occupations of the previous step's ground state.  The oracle replays the
+    same loop (its own Davidson vectors, its own occupations and recovery) and
+    reaches the same bases and energies within 1e-8 Ha."""
+    norb, n = 10, 4
+    h, eri, ec = wl.make_integrals(norb, 730)
+    smp = wl.add_readout_noise(wl.sample_configurations(norb, n, n, 600, 731), norb, 0.04, 732)
+    steps, seed = [150, 300, 600], 77
+    e, rep = sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps, recovery=True, recovery_seed=seed,
+                         tol_residual=1e-9)
+    occ = None
+    for s, m in enumerate(steps):
+        kept, nc = orec.recover(smp[:m], norb, n, n, *(occ if occ else (None, None)), seed=seed)
+        S = oracle.OracleSystem(norb, kept[:, 0], kept[:, 1], h, eri, ec)
+        r = oracle.davidson(S.sigma, S.diag(), 1, tol=1e-10, max_space=30)
+        assert rep[s]["ndet"] == S.N and rep[s]["status"] == 0 and rep[s]["samples"] == m
+        assert rep[s]["corrected"] == nc and rep[s]["dropped"] == m - kept.shape[0]
+        assert abs(e[s, 0] - r.energies[0]) <= 1e-8, (s, e[s, 0], r.energies[0])
+        A, Bs = np.unique(kept[:, 0]), np.unique(kept[:, 1])
+        occ = orec.occupations(norb, A, Bs, r.vectors[0])
+    assert rep[0]["dropped"] > 0 and rep[0]["corrected"] == 0 and rep[1]["corrected"] > 0
+    with pytest.raises(sbd.SBDError):
+        sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps, recovery=True, full_bitstring=True)
