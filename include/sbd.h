@@ -401,7 +401,7 @@ typedef struct {
                                     then the number of distinct alpha strings and
                                     n_beta_str 0.  Not with spin_union. */
     int recovery;                /* default 0.  1: filter and correct the samples of every
-                                    step (see above); product bases only */
+                                    step (see above); product or full-bitstring bases */
     uint64_t recovery_seed;      /* default 0: seed of the recovery's uniforms */
 } sbd_sqd_opts;
 typedef struct {
@@ -535,6 +535,11 @@ int sbd_full_davidson(const sbd_fbasis* b, const sbd_fham* h, int nroots, const 
  */
 int sbd_full_map_vectors(const sbd_fbasis* from, const sbd_fbasis* to, int nvec, const double* x_from,
                          double* x_to, void* stream);
+/* Spin-orbital occupations of a vector over a determinant list, as
+ * sbd_occupations (vec: device, ndet doubles in the list's order; occ: host,
+ * 2 * norb).  Synchronises the stream.  Errors: SBD_ERR_ARG, SBD_ERR_NOMEM,
+ * SBD_ERR_HIP. */
+int sbd_full_occupations(const sbd_fbasis* b, const double* vec, double* occ, void* stream);
 
 /*
  * Explicit realization over a determinant list (Sec. II-A for the list of

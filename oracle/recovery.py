@@ -71,6 +71,22 @@ def occupations(norb: int, alpha, beta, vec) -> tuple[np.ndarray, np.ndarray]:
     return out[0], out[1]
 
 
+def occupations_dets(norb: int, dets, vec) -> tuple[np.ndarray, np.ndarray]:
+    """The same over a determinant list (rows: alpha word, beta word), one
+    vector entry per determinant."""
+    dets = np.asarray(dets, dtype=np.uint64).reshape(-1, 2)
+    w = np.asarray(vec, dtype=np.float64) ** 2
+    total = w.sum()
+    out = []
+    for col in (0, 1):
+        occ = np.zeros(norb)
+        for p in range(norb):
+            bit = ((dets[:, col] >> np.uint64(p)) & np.uint64(1)).astype(bool)
+            occ[p] = w[bit].sum() / total
+        out.append(occ)
+    return out[0], out[1]
+
+
 def flip_weight(y: float, h: float, delta: float = DELTA) -> float:
     """Weight of a bit at distance y from its average occupation, filling h."""
     if y <= h:

@@ -37,7 +37,8 @@ EXPORTED = ["sbd_last_error", "sbd_version", "sbd_source_hash", "sbd_release_cac
             "sbd_full_set_hamiltonian", "sbd_full_ham_diag", "sbd_free_full_ham", "sbd_full_sigma",
             "sbd_full_davidson", "sbd_full_map_vectors", "sbd_full_assemble", "sbd_full_release_assembled",
             "sbd_full_assembled",
-            "sbd_sqd_default_opts", "sbd_sqd_run", "sbd_occupations", "sbd_recover_configurations"]
+            "sbd_sqd_default_opts", "sbd_sqd_run", "sbd_occupations", "sbd_full_occupations",
+            "sbd_recover_configurations"]
 
 
 class SBDError(RuntimeError):
@@ -416,6 +417,14 @@ def occupations(basis: "Basis", vec, stream=None) -> tuple:
     (sbd_occupations): (alpha occupations, beta occupations), norb each."""
     occ = np.zeros(2 * basis.norb, dtype=np.float64)
     check(load().sbd_occupations(basis._h, _dptr(vec), _host(occ), _stream(stream)))
+    return occ[:basis.norb].copy(), occ[basis.norb:].copy()
+
+
+def full_occupations(basis: "FullBasis", vec, stream=None) -> tuple:
+    """Spin-orbital occupations of an FP64 device vector over a determinant
+    list (sbd_full_occupations): (alpha occupations, beta occupations)."""
+    occ = np.zeros(2 * basis.norb, dtype=np.float64)
+    check(load().sbd_full_occupations(basis._h, _dptr(vec), _host(occ), _stream(stream)))
     return occ[:basis.norb].copy(), occ[basis.norb:].copy()
 
 

@@ -275,6 +275,18 @@ int sbd_full_map_vectors(const sbd_fbasis* from, const sbd_fbasis* to, int nvec,
     return SBD_OK;
 }
 
+int sbd_full_occupations(const sbd_fbasis* B, const double* vec, double* occ, void* stream) {
+    if (!B || !vec || !occ) return fail(SBD_ERR_ARG, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf scratch, od;
+    SBD_HIP(scratch.alloc(sizeof(double) * (size_t)full_occupation_scratch_words(B->n, B->norb)));
+    SBD_HIP(od.alloc(sizeof(double) * 2 * (size_t)B->norb));
+    SBD_HIP(launch_full_occupations(B->dets.p, vec, B->n, B->norb, scratch.as<double>(), od.as<double>(), st));
+    SBD_HIP(hipMemcpyAsync(occ, od.p, sizeof(double) * 2 * (size_t)B->norb, hipMemcpyDeviceToHost, st));
+    SBD_HIP(hipStreamSynchronize(st));
+    return SBD_OK;
+}
+
 int sbd_full_assemble(sbd_fham* H, const sbd_fbasis* B, int precisions, size_t max_bytes, void* stream) {
     if (!B || !H) return fail(SBD_ERR_ARG, "null argument");
     if (H->basis_id != B->id) return fail(SBD_ERR_STATE, "Hamiltonian belongs to another basis");

@@ -362,6 +362,11 @@ hipError_t launch_full_sigma(const FullSigmaArgs& S, int nvec, const T* x, T* y,
 // out[e] = the element of connection e (in the connection order), rounded once to T
 template <class T>
 hipError_t launch_full_values(const FullSigmaArgs& S, T* out, hipStream_t st);
+// occ[spin * norb + p]: occupation of spin-orbital p in the vector c over the
+// list; scratch: full_occupation_scratch_words(n, norb) doubles
+int64_t full_occupation_scratch_words(int64_t n, int norb);
+hipError_t launch_full_occupations(const void* dets, const double* c, int64_t n, int norb, double* scratch,
+                                   double* occ, hipStream_t st);
 // xt[v][i] = xf[v][j] for the determinant j of the sorted list `from` equal to
 // determinant i of `to`, else 0 (nvec vectors of nf and nt doubles)
 hipError_t launch_full_map(const void* from, int64_t nf, const void* to, int64_t nt, int nvec, const double* xf,

@@ -446,9 +446,73 @@ __global__ void k_full_map(const Det* __restrict__ from, int64_t nf, const Det* 
     for (int v = 0; v < nvec; ++v) xt[(size_t)v * nt + i] = hit ? xf[(size_t)v * nf + lo] : 0.0;
 }
 
+// Spin-orbital occupations of a vector over the list (input of the sample
+// recovery of an SQD iteration): part[j * nq + q] = sum over the determinants
+// of chunk q of c_I^2 [orbital j of spin j / norb occupied] (j < 2 norb), or
+// of c_I^2 (j = 2 norb); then per j the chunk sums in order.
+constexpr int kOccChunk = 8192;
+
+__device__ double occ_block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_full_occ_part(const Det* __restrict__ d, const double* __restrict__ c,
+                                                       int64_t n, int norb, int64_t nq, double* __restrict__ part) {
+    __shared__ double sh[256];
+    const int64_t q = blockIdx.x;
+    const int j = blockIdx.y;
+    const int64_t i0 = q * kOccChunk, i1 = i0 + kOccChunk < n ? i0 + kOccChunk : n;
+    double s = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        const double w = c[i] * c[i];
+        if (j == 2 * norb) {
+            s += w;
+        } else {
+            const uint64_t word = j < norb ? d[i].a : d[i].b;
+            if ((word >> (j % norb)) & 1ull) s += w;
+        }
+    }
+    s = occ_block_sum(s, sh);
+    if (threadIdx.x == 0) part[(int64_t)j * nq + q] = s;
+}
+
+__global__ void __launch_bounds__(256) k_full_occ_sum(const double* __restrict__ part, int64_t nq, int norb,
+                                                      double* __restrict__ occ) {
+    __shared__ double sh[256];
+    const int j = blockIdx.x;
+    double s = 0.0, t = 0.0;
+    for (int64_t q = threadIdx.x; q < nq; q += 256) {
+        s += part[(int64_t)j * nq + q];
+        t += part[(int64_t)2 * norb * nq + q];
+    }
+    s = occ_block_sum(s, sh);
+    __syncthreads();
+    t = occ_block_sum(t, sh);
+    if (threadIdx.x == 0) occ[j] = t > 0.0 ? s / t : 0.0;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+int64_t full_occupation_scratch_words(int64_t n, int norb) {
+    const int64_t nq = (n + kOccChunk - 1) / kOccChunk;
+    return (2 * (int64_t)norb + 1) * nq;
+}
+
+hipError_t launch_full_occupations(const void* dets, const double* c, int64_t n, int norb, double* scratch,
+                                   double* occ, hipStream_t st) {
+    const int64_t nq = (n + kOccChunk - 1) / kOccChunk;
+    hipLaunchKernelGGL(k_full_occ_part, dim3((unsigned)nq, (unsigned)(2 * norb + 1)), dim3(256), 0, st,
+                       static_cast<const Det*>(dets), c, n, norb, nq, scratch);
+    hipLaunchKernelGGL(k_full_occ_sum, dim3((unsigned)(2 * norb)), dim3(256), 0, st, scratch, nq, norb, occ);
+    return hipGetLastError();
+}
 hipError_t launch_full_map(const void* from, int64_t nf, const void* to, int64_t nt, int nvec, const double* xf,
                            double* xt, hipStream_t st) {
     if (nt > 0)

@@ -183,7 +183,6 @@ extern "C" int sbd_sqd_run(int norb, int n_alpha, int n_beta, const double* h1, 
     if (o.spin_union && n_alpha != n_beta) return fail(SBD_ERR_ARG, "spin_union needs n_alpha == n_beta");
     if (o.spin_union && o.full_bitstring) return fail(SBD_ERR_ARG, "spin_union applies to product bases only");
     if (o.davidson.n_guess != 0 || o.davidson.guess) return fail(SBD_ERR_ARG, "guess is set by the SQD loop");
-    if (o.recovery && o.full_bitstring) return fail(SBD_ERR_ARG, "recovery applies to product bases only");
     int rc = validate_integrals(norb, h1, eri);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -202,7 +201,8 @@ extern "C" int sbd_sqd_run(int norb, int n_alpha, int n_beta, const double* h1, 
         if (o.recovery) {  // wrong electron counts: dropped at the first step, corrected after it
             if (prev) {
                 occ.assign(2 * (size_t)norb, 0.0);
-                rc = sbd_occupations(prev->b, prev_vec.as<double>(), occ.data(), stream);
+                rc = o.full_bitstring ? sbd_full_occupations(prev->fb, prev_vec.as<double>(), occ.data(), stream)
+                                      : sbd_occupations(prev->b, prev_vec.as<double>(), occ.data(), stream);
                 if (rc) return rc;
             }
             rec.resize(2 * (size_t)m);

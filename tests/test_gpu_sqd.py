@@ -208,5 +208,42 @@ def test_sqd_recovery_steps_match_oracle():
         A, Bs = np.unique(kept[:, 0]), np.unique(kept[:, 1])
         occ = orec.occupations(norb, A, Bs, r.vectors[0])
     assert rep[0]["dropped"] > 0 and rep[0]["corrected"] == 0 and rep[1]["corrected"] > 0
-    with pytest.raises(sbd.SBDError):
-        sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps, recovery=True, full_bitstring=True)
+
+
+def test_full_occupations_vs_oracle():
+    """sbd_full_occupations against the oracle over a determinant list
+    (1e-13), across several reduction chunks, and a unit vector's bits."""
+    W = wl.make_full_config("full16", ndet=20000, nstr=400)
+    B = sbd.FullBasis(W.norb, W.n_alpha, W.n_beta, W.dets)
+    d = B.export()[0]
+    x = wl.random_vector(B.N, 35)[0]
+    ga, gb = sbd.full_occupations(B, torch.tensor(x, device="cuda"))
+    ra, rb = orec.occupations_dets(W.norb, d, x)
+    assert np.abs(ga - ra).max() <= 1e-13 and np.abs(gb - rb).max() <= 1e-13
+    u = np.zeros(B.N)
+    u[B.N - 1] = 1.0
+    ga, gb = sbd.full_occupations(B, torch.tensor(u, device="cuda"))
+    assert np.array_equal(ga, [(int(d[-1, 0]) >> p) & 1 for p in range(W.norb)])
+    assert np.array_equal(gb, [(int(d[-1, 1]) >> p) & 1 for p in range(W.norb)])
+
+
+def test_sqd_full_bitstring_recovery_steps_match_oracle():
+    """Full-bitstring SQD steps on noisy samples with recovery, replayed by the
+    oracle (recovery, determinant list, dense lowest eigenpair, occupations
+    over the list)."""
+    norb, n = 10, 4
+    h, eri, ec = wl.make_integrals(norb, 740)
+    smp = wl.add_readout_noise(wl.sample_configurations(norb, n, n, 900, 741), norb, 0.04, 742)
+    steps, seed = [300, 600, 900], 78
+    e, rep = sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps, full_bitstring=True, recovery=True,
+                         recovery_seed=seed, tol_residual=1e-9)
+    occ = None
+    for s, m in enumerate(steps):
+        kept, nc = orec.recover(smp[:m], norb, n, n, *(occ if occ else (None, None)), seed=seed)
+        S = oracle.FullOracleSystem(norb, kept, h, eri, ec)
+        w, v = oracle.dense_lowest(S.dense_h(), 1)  # sparse lists: H may fall apart into blocks
+        assert rep[s]["ndet"] == S.N and rep[s]["status"] == 0
+        assert rep[s]["corrected"] == nc and rep[s]["dropped"] == m - kept.shape[0]
+        assert abs(e[s, 0] - w[0]) <= 1e-8, (s, e[s, 0], w[0])
+        occ = orec.occupations_dets(norb, S.dets, v[0])
+    assert rep[1]["corrected"] > 0

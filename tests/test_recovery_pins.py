@@ -54,6 +54,23 @@ def test_occupations_single_determinant_and_brute_force():
     assert math.isclose(oa.sum(), na, rel_tol=1e-13) and math.isclose(ob.sum(), nb, rel_tol=1e-13)
 
 
+def test_occupations_of_a_list_equal_product_occupations():
+    """Over a complete product listed determinant by determinant (in the
+    product's order) the list form gives the product form's occupations."""
+    norb, na, nb = 6, 2, 3
+    A, B = wl.all_strings(norb, na), wl.all_strings(norb, nb)
+    dets = np.array([(a, b) for a in A for b in B], dtype=np.uint64)
+    x = wl.random_vector(dets.shape[0], 4)[0]
+    pa, pb = rec.occupations(norb, A, B, x)
+    la, lb = rec.occupations_dets(norb, dets, x)
+    assert np.allclose(pa, la, rtol=1e-14, atol=1e-15) and np.allclose(pb, lb, rtol=1e-14, atol=1e-15)
+    u = np.zeros(dets.shape[0])
+    u[5] = 3.0
+    la, lb = rec.occupations_dets(norb, dets, u)
+    assert np.array_equal(la, [(int(dets[5, 0]) >> p) & 1 for p in range(norb)])
+    assert np.array_equal(lb, [(int(dets[5, 1]) >> p) & 1 for p in range(norb)])
+
+
 @pytest.mark.parametrize("extra_a,extra_b", [(1, 0), (-1, 0), (2, -1), (0, 2), (-2, 1)])
 def test_recovery_forced_by_exact_occupations(extra_a, extra_b):
     """Occupations exactly 0/1 on a determinant D: a sample that differs from D
