@@ -117,6 +117,16 @@ def test_struct_layouts_match_header(tmp_path):
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
+def test_recover_configurations_validation_on_host():
+    ok = np.array([[0b0111, 0b0011]], dtype=np.uint64)
+    assert _status(lambda: sbd.recover_configurations(0, 3, 2, ok)) == -2
+    assert _status(lambda: sbd.recover_configurations(65, 3, 2, ok)) == -2
+    assert _status(lambda: sbd.recover_configurations(4, 5, 2, ok)) == -1
+    assert _status(lambda: sbd.recover_configurations(4, 3, 2, np.array([[0b10111, 0b0011]], dtype=np.uint64))) == -3
+    assert "at or above norb" in sbd.last_error()
+    assert _status(lambda: sbd.recover_configurations(4, 3, 2, ok, np.full(4, np.inf), np.zeros(4))) == -1
+
+
 def test_full_basis_validation_on_host():
     ok = np.array([[0b1111, 0b1111]], dtype=np.uint64)
     assert _status(lambda: sbd.FullBasis(0, 4, 4, ok)) == -2
