@@ -3,7 +3,10 @@ sampled configurations, through the C ABI.  Each step's energies are checked
 against the oracle's Davidson on the oracle's sigma over the same basis (the
 Cartesian product of the distinct sampled alpha and beta strings), within
 1e-8 Ha; warm and cold runs reach the same energies; the nested bases make the
-lowest energy non-increasing."""
+lowest energy non-increasing.  Full-bitstring steps, the transfer between
+determinant lists, and the filtering of noisy samples (occupations and
+recovered samples bit-exact against the oracle; whole recovery loops replayed
+by the oracle) are covered as well."""
 import numpy as np
 import pytest
 
