@@ -188,7 +188,8 @@ def test_occupations_vs_oracle(name, nstr):
     assert np.array_equal(gb, [(int(Bs[ib]) >> p) & 1 for p in range(W.norb)])
 
 
-def test_sqd_recovery_steps_match_oracle():
+@pytest.mark.parametrize("union", [False, True])
+def test_sqd_recovery_steps_match_oracle(union):
     """SQD loop on noisy samples with recovery: at the first step the samples
     with wrong electron counts are dropped, later they are corrected from the
     occupations of the previous step's ground state.  The oracle replays the
@@ -199,16 +200,19 @@ def test_sqd_recovery_steps_match_oracle():
     smp = wl.add_readout_noise(wl.sample_configurations(norb, n, n, 600, 731), norb, 0.04, 732)
     steps, seed = [150, 300, 600], 77
     e, rep = sbd.sqd_run(norb, n, n, h, eri, ec, smp, steps, recovery=True, recovery_seed=seed,
-                         tol_residual=1e-9)
+                         spin_union=union, tol_residual=1e-9)
     occ = None
     for s, m in enumerate(steps):
         kept, nc = orec.recover(smp[:m], norb, n, n, *(occ if occ else (None, None)), seed=seed)
-        S = oracle.OracleSystem(norb, kept[:, 0], kept[:, 1], h, eri, ec)
+        ka, kb = kept[:, 0], kept[:, 1]
+        if union:
+            ka = kb = np.concatenate([ka, kb])
+        S = oracle.OracleSystem(norb, ka, kb, h, eri, ec)
         r = oracle.davidson(S.sigma, S.diag(), 1, tol=1e-10, max_space=30)
         assert rep[s]["ndet"] == S.N and rep[s]["status"] == 0 and rep[s]["samples"] == m
         assert rep[s]["corrected"] == nc and rep[s]["dropped"] == m - kept.shape[0]
         assert abs(e[s, 0] - r.energies[0]) <= 1e-8, (s, e[s, 0], r.energies[0])
-        A, Bs = np.unique(kept[:, 0]), np.unique(kept[:, 1])
+        A, Bs = np.unique(ka), np.unique(kb)
         occ = orec.occupations(norb, A, Bs, r.vectors[0])
     assert rep[0]["dropped"] > 0 and rep[0]["corrected"] == 0 and rep[1]["corrected"] > 0
 
